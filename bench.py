@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of polynomial preconditioned Arnoldi on one MI355X.
+
+One step = one whole solve on the device: GMRES polynomial construction
+(degree d, or d1 x d2 for the double polynomial), then thick-restarted
+Arnoldi(m, k) on pi(A) until the nev wanted pairs meet rtol * ||A||_inf (or
+the cycle cap).  Inputs are seeded synthetic matrices already resident in HBM.
+
+Prints one JSON line: `value` is the whole-job pi(A)v throughput (algorithmic
+bytes of every fused SpMV pass of the operator applications in the timed
+steps, divided by the timed wall clock); `roofline` gives the fused SpMV
+kernel's own bandwidth from HIP events recorded on the launch stream during
+the timed steps; `cpu_baseline` times the FP64 oracle's pi(A)v on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
+
+CONFIGS = {
+    # name: (builder, seed, d or (d1, d2), m, k, nev, precision, description)
+    "c1": dict(mat=("laplacian_2d", (50,)), seed=1, d=10, m=30, k=15, nev=10, precision="f64",
+               desc="2-D Laplacian 50x50 (n=2500), d=10, Arnoldi(30,15), nev=10, FP64"),
+    "c2": dict(mat=("convdiff_2d", (1000, 0.5)), seed=2, d=50, m=50, k=25, nev=20, precision="f64",
+               desc="2-D convection-diffusion 1000x1000 (n=1e6), beta*h=0.5, d=50, Arnoldi(50,25), nev=20, FP64"),
+    "c3": dict(mat=("convdiff_3d", (160, 0.3)), seed=3, d=(10, 20), m=40, k=20, nev=15, precision="mixed",
+               desc="3-D convection-diffusion 160^3 (n=4.1e6), beta*h=0.3, double poly 10x20, Arnoldi(40,20), nev=15, mixed"),
+    "c4": dict(mat=("random_banded", (2_000_000, 27, 5000)), seed=4, d=100, m=60, k=15, nev=10,
+               precision="mixed",
+               desc="random banded n=2e6, 27 nnz/row, band 5000, d=100, Arnoldi(60,15), nev=10, mixed"),
+}
+
+
+def make_matrix(cfg):
+    from paper_1806_08020_amd import workloads as W
+    name, args = cfg["mat"]
+    if name == "random_banded":
+        return W.random_banded(*args, seed=cfg["seed"])
+    return getattr(W, name)(*args)
+
+
+def pass_bytes(n, nnz, val_bytes, vec_bytes):
+    """Algorithmic bytes of one fused SpMV + axpy pass: CSR arrays once
+    (values, int32 column indices, int32 row pointers), the gathered vector
+    once, the streamed vector once, the output once."""
+    return nnz * (val_bytes + 4) + 4 * (n + 1) + 3 * n * vec_bytes
+
+
+def cpu_baseline(csr, roots, bytes_per_apply, budget_s):
+    import oracle as O
+    mv = O.csr_matvec(csr)
+    v = np.random.default_rng(0).standard_normal(csr.n)
+    t0 = time.perf_counter()
+    reps = 0
+    if isinstance(roots, tuple):
+        r1, r2 = roots
+        while True:
+            O.apply_double(mv, r1, r2, v)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+    else:
+        while True:
+            O.apply_poly(mv, roots, v)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+    dt = time.perf_counter() - t0
+    return reps, dt, bytes_per_apply * reps / dt / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--max-cycles", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1806_08020_amd import ppa
+    from paper_1806_08020_amd import workloads as W
+
+    cfg = CONFIGS[args.config]
+    csr = make_matrix(cfg)
+    b, v0 = W.start_vectors(csr.n, cfg["seed"])
+    prec = cfg["precision"]
+    A = ppa.Matrix(csr, want_f32=(prec != "f64"))
+    bt = torch.as_tensor(b, device="cuda")
+    vt = torch.as_tensor(v0, device="cuda")
+    dbl = isinstance(cfg["d"], tuple)
+    vbytes = 8 if prec == "f64" else 4
+    pb = pass_bytes(csr.n, csr.nnz, vbytes, vbytes)
+
+    def one_step():
+        if dbl:
+            P = ppa.Poly.build_double(A, cfg["d"][0], cfg["d"][1], bt)
+        else:
+            P = ppa.Poly.build(A, cfg["d"], bt)
+        r = ppa.eigs(A, P, vt, cfg["m"], cfg["k"], cfg["nev"], rtol=1e-8, max_cycles=args.max_cycles,
+                     precision=prec, timing=True)
+        return P, r
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    lat = []
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        P, r = one_step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        results.append(r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    passes = sum(r.spmv_passes for r in results)
+    t_apply = sum(r.t_apply_ms for r in results) / 1e3
+    pi_bytes = passes * pb
+    value = pi_bytes / wall / 1e9
+    kern_gbs = (pb * passes / t_apply / 1e9) if t_apply > 0 else None
+    avg_pass_us = t_apply / passes * 1e6 if passes else None
+    nconv = sum(r.nconv for r in results)
+    line = {
+        "metric": "pi(A)v HBM GB/s; eigenpairs/s at rtol 1e-8 (mixed vs FP64); p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "f64" else "f32 pi(A)v + f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "n": csr.n, "nnz": csr.nnz, "max_cycles": args.max_cycles},
+        "eigenpairs_per_s": round(nconv / wall, 4),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+        "solve": {"converged": [bool(r.converged) for r in results], "nconv": [r.nconv for r in results],
+                  "cycles": [r.cycles for r in results],
+                  "max_resid_rel": [r.max_resid / A.norm_inf for r in results],
+                  "mvps": results[-1].mvps, "dots": results[-1].dots,
+                  "fp32_cycles": results[-1].fp32_cycles},
+        "roofline": {"kernel": "k_fused_spmv", "bound": "hbm",
+                     "achieved": round(kern_gbs, 1) if kern_gbs else None, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4) if kern_gbs else None,
+                     "traffic": None, "bytes_per_launch": pb,
+                     "avg_launch_us": round(avg_pass_us, 3) if avg_pass_us else None,
+                     "launches": passes},
+    }
+    if not args.no_cpu_baseline:
+        roots = (P.roots(1), P.roots(2)) if dbl else P.roots()
+        bpa = pb * (cfg["d"][0] * cfg["d"][1] if dbl else cfg["d"])
+        reps, dt, gbs = cpu_baseline(csr, roots, bpa, args.cpu_seconds)
+        line["cpu_baseline"] = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{reps} FP64 pi(A)v applications of the same polynomial on "
+                                          f"the same matrix ({dt:.1f} s, SciPy CSR mat-vec, one thread)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * ppa.h -- C ABI of libppa.so, polynomial preconditioned Arnoldi on one
+ * MI355X (gfx950).  Method: Embree, Loe & Morgan, "Polynomial Preconditioned
+ * Arnoldi" (arXiv:1806.08020).
+ *
+ * Conventions
+ *  - Pointers named *_d are device pointers (HIP global memory on the current
+ *    device); all other pointers are host pointers.
+ *  - The library never takes ownership of caller memory.  Device arrays passed
+ *    to ppa_matrix_create are borrowed for the lifetime of the handle.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; calls documented as synchronising wait for it.
+ *  - Scratch device memory on the solve paths comes from a caller-provided
+ *    workspace (`ws_d`, `ws_bytes`), sized by the *_workspace_bytes queries;
+ *    those paths never call hipMalloc.  Handle creation may allocate.
+ *  - Vectors are contiguous; a block of vectors is column-major with leading
+ *    dimension n unless stated otherwise.
+ *  - Every entry point returns a ppa_status.  On a negative status nothing was
+ *    written to the outputs and ppa_last_error() (thread-local) describes the
+ *    failure; positive statuses are warnings and the outputs are filled.
+ *  - A handle is used by one host thread at a time; distinct handles may be
+ *    used concurrently from different threads.
+ */
+#ifndef PPA_H
+#define PPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PPA_ABI_VERSION 1
+
+typedef enum ppa_status {
+    PPA_OK = 0,
+    PPA_WARN_DEGREE_REDUCED = 1,  /* GMRES broke down early: lower-degree polynomial */
+    PPA_WARN_NOT_CONVERGED = 2,   /* max_cycles reached; best estimates returned   */
+    PPA_WARN_BREAKDOWN = 3,       /* Arnoldi basis became invariant; see result     */
+    PPA_ERR_INVALID = -1,         /* bad argument or malformed matrix               */
+    PPA_ERR_HIP = -2,             /* a HIP runtime call failed                      */
+    PPA_ERR_WORKSPACE = -3,       /* workspace missing or too small                 */
+    PPA_ERR_NONFINITE = -4,       /* NaN/Inf met in the input or during the solve   */
+    PPA_ERR_SINGULAR = -5,        /* H_d singular in the harmonic Ritz solve        */
+    PPA_ERR_NUMERIC = -6          /* small dense eigensolver did not converge       */
+} ppa_status;
+
+typedef enum ppa_precision {
+    PPA_F64 = 0,    /* everything in FP64                                           */
+    PPA_F32 = 1,    /* pi(A)v with FP32 matrix values and FP32 vectors              */
+    PPA_MIXED = 2   /* eigs: pi(A)v in FP32, orthogonalisation / Ritz / residual in
+                       FP64, closing FP64 cycles to reach rtol                        */
+} ppa_precision;
+
+typedef struct ppa_matrix ppa_matrix;
+typedef struct ppa_poly ppa_poly;
+
+/* ABI version (PPA_ABI_VERSION) and the last error message of this thread. */
+int ppa_abi_version(void);
+const char* ppa_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Sparse matrix A (section 4: A is large, sparse, possibly nonsymmetric; the
+ * paper's cost model counts nnzr nonzeros per row).
+ *
+ * n           number of rows = columns (1 <= n < 2^31)
+ * rowptr_d    int32[n+1], rowptr_d[0] = 0, nondecreasing
+ * colind_d    int32[nnz], column indices in [0, n), strictly increasing in a row
+ * val64_d     double[nnz] values (required)
+ * val32_d     float[nnz] values for the FP32 / mixed paths, or NULL.  When NULL
+ *             and `want_f32` is nonzero, the library converts val64_d into an
+ *             internal FP32 copy it owns.
+ * stream      stream used for validation; the call synchronises it.
+ * out         receives the handle.
+ *
+ * Validates the CSR structure on the device (PPA_ERR_INVALID if malformed),
+ * computes ||A||_inf, and builds the row-block partition used by the SpMV
+ * kernels (allocated by the library, freed by ppa_matrix_destroy).
+ * ------------------------------------------------------------------------ */
+int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
+                      const double* val64_d, const float* val32_d, int want_f32,
+                      void* stream, ppa_matrix** out);
+int ppa_matrix_destroy(ppa_matrix* A);
+/* n, nnz, ||A||_inf (largest absolute row sum) and the number of row blocks. */
+int ppa_matrix_info(const ppa_matrix* A, int64_t* n, int64_t* nnz, double* norm_inf,
+                    int64_t* nblocks);
+
+/* ------------------------------------------------------------------------
+ * Polynomial pi in factored form, eq. (2.1): pi(z) = prod_i (1 - z/theta_i),
+ * roots in modified Leja order with each complex root followed at once by its
+ * conjugate (section 2, step 1(c); section 7: keep complex roots together).
+ * A double polynomial (section 8) is pi_2(tau(z)), tau = 1 - pi_1.
+ * ------------------------------------------------------------------------ */
+
+/* Polynomial from given roots (host arrays re[deg], im[deg]), used in the
+ * given order.  A root with im != 0 must be followed by its exact conjugate.
+ * d1 = 0: single polynomial with roots (re, im).  d1 > 0: double polynomial,
+ * (re1, im1)[d1] are the roots of pi_1 and (re, im)[deg] those of pi_2. */
+int ppa_poly_from_roots(int deg, const double* re, const double* im,
+                        int d1, const double* re1, const double* im1, ppa_poly** out);
+int ppa_poly_destroy(ppa_poly* p);
+/* Degrees: *deg = degree of pi (or pi_2), *d1 = degree of pi_1 (0 if single). */
+int ppa_poly_degree(const ppa_poly* p, int* deg, int* d1);
+/* Copy roots of level 2 (pi, or pi_2 of a double polynomial) or level 1 (pi_1)
+ * into host arrays of capacity `cap`; returns the count in *count. */
+int ppa_poly_roots(const ppa_poly* p, int level, double* re, double* im, int cap, int* count);
+
+/* Workspace bytes for ppa_poly_build / ppa_poly_build_double with degree d
+ * (for a double polynomial pass d = max(d1, d2) and double_poly = 1). */
+int ppa_poly_build_workspace_bytes(const ppa_matrix* A, int d, int double_poly, size_t* bytes);
+
+/* GMRES polynomial (section 2, step 1): one cycle of GMRES(d) on A from b_d
+ * (double[n], device; need not be normalised) with classical Gram-Schmidt and
+ * one reorthogonalisation pass on the device; harmonic Ritz values
+ * theta = eig(H_d + h_{d+1,d}^2 f e_d^T), f = H_d^{-T} e_d (step 1(b)) and
+ * modified Leja ordering (step 1(c)) on the host in FP64.  Synchronises
+ * `stream`.  If the Krylov space becomes invariant at step j < d the degree is
+ * reduced to j and PPA_WARN_DEGREE_REDUCED is returned. */
+int ppa_poly_build(const ppa_matrix* A, int d, const double* b_d,
+                   void* ws_d, size_t ws_bytes, void* stream, ppa_poly** out);
+
+/* Double polynomial (section 8): pi_1 of degree d1 from GMRES on A, then pi_2 of
+ * degree d2 from GMRES on tau(A) = I - pi_1(A), both started from b_d. */
+int ppa_poly_build_double(const ppa_matrix* A, int d1, int d2, const double* b_d,
+                          void* ws_d, size_t ws_bytes, void* stream, ppa_poly** out);
+
+/* Workspace bytes for ppa_poly_apply. */
+int ppa_poly_apply_workspace_bytes(const ppa_matrix* A, const ppa_poly* p, int precision,
+                                   size_t* bytes);
+
+/* y = pi(A) v (eq. (2.1); section 8 for a double polynomial).
+ * precision PPA_F64: v_d, y_d are double[n]; PPA_F32: float[n] and the FP32
+ * matrix values are used (the handle must hold them).  v_d and y_d must not
+ * alias.  Each real root costs one fused pass y = w - (1/theta) A w over the
+ * CSR arrays; a conjugate pair a +/- ib costs two: s = 2a w - A w and
+ * y = w - A s / (a^2 + b^2).  Asynchronous on `stream`. */
+int ppa_poly_apply(const ppa_matrix* A, const ppa_poly* p, int precision,
+                   const void* v_d, void* y_d, void* ws_d, size_t ws_bytes, void* stream);
+
+/* One fused pass, the building block of ppa_poly_apply:
+ *   out = alpha x + beta (A u) + gamma z + delta z2
+ * (x, z, z2 may be NULL, dropping their term).  Types: in_f32 selects
+ * float for x, u, z, z2 (else double); out_f32 float for out (else double);
+ * FP32 matrix values are used iff in_f32 || out_f32.  out must not alias u. */
+int ppa_fused_spmv(const ppa_matrix* A, int in_f32, int out_f32, double alpha,
+                   const void* x_d, double beta, const void* u_d, double gamma,
+                   const void* z_d, double delta, const void* z2_d, void* out_d,
+                   void* stream);
+
+/* ------------------------------------------------------------------------
+ * Classical Gram-Schmidt with one reorthogonalisation pass (section 4: each
+ * orthogonalisation step is followed by a pass of reorthogonalisation).
+ *   V_d  double, n x (j) column-major, leading dimension ldv >= n, orthonormal
+ *   w_d  double[n] (overwritten with the orthogonalised, unnormalised vector)
+ *   h    host double[j+1]: h[0..j-1] = V^T w over both passes, h[j] = ||w_out||
+ *   w0norm host double: ||w_in||.
+ * Synchronises `stream`.
+ * ------------------------------------------------------------------------ */
+int ppa_cgs2_workspace_bytes(int64_t n, int j, size_t* bytes);
+int ppa_cgs2(int64_t n, int j, const double* V_d, int64_t ldv, double* w_d,
+             double* h, double* w0norm, void* ws_d, size_t ws_bytes, void* stream);
+
+/* Dense tall-skinny product C = V Q (the thick-restart update V_k = V_m Q of
+ * section 4 and the Ritz vectors Y = V_m G), on MFMA FP64.
+ *   V_d double n x kin (ld ldv), Q host double kin x kout (column-major,
+ *   ld kin), C_d double n x kout (ld ldc), C must not overlap V.
+ * kin <= 128, kout <= 64.  Asynchronous on `stream` (Q is staged through the
+ * workspace, ppa_gemm_workspace_bytes). */
+int ppa_gemm_workspace_bytes(int kin, int kout, size_t* bytes);
+int ppa_gemm_tall(int64_t n, int kin, int kout, const double* V_d, int64_t ldv,
+                  const double* Q, double* C_d, int64_t ldc, void* ws_d, size_t ws_bytes,
+                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Thick-restarted Arnoldi(m, k) on pi(A) (section 2 step 2, section 4).
+ * ------------------------------------------------------------------------ */
+typedef struct ppa_eigs_opts {
+    int m;            /* largest subspace dimension, 2 <= m <= 64            */
+    int k;            /* Ritz vectors kept at a restart, nev <= k < m        */
+    int nev;          /* wanted eigenpairs, 1 <= nev                          */
+    int max_cycles;   /* restart cycles allowed (>= 1)                        */
+    double rtol;      /* converged when ||A y - mu y|| <= rtol * anorm        */
+    double anorm;     /* norm used with rtol; <= 0 selects ||A||_inf          */
+    int precision;    /* PPA_F64 or PPA_MIXED                                 */
+    int flags;        /* PPA_FLAG_* bits                                      */
+} ppa_eigs_opts;
+
+/* opts.flags: time the polynomial applications and the orthogonalisation with
+ * HIP events recorded on `stream` (results in t_apply_ms / t_cgs_ms). */
+#define PPA_FLAG_TIMING 1
+
+typedef struct ppa_eigs_result {
+    /* host arrays of capacity nev, filled with the returned pairs sorted by
+     * |mu| (ties: real part, then imaginary part) */
+    double* lam_re;
+    double* lam_im;
+    double* resid;       /* ||A y - mu y|| with unit y                       */
+    double* ritz_re;     /* Ritz values nu of pi(A) for the same pairs (may be NULL) */
+    double* ritz_im;
+    /* device array (may be NULL): n x nev complex128 (interleaved re, im),
+     * column j the unit eigenvector estimate of lam j */
+    double* X_d;
+    /* outputs */
+    int nconv;           /* returned pairs meeting the tolerance             */
+    int cycles;          /* restart cycles run                               */
+    int64_t mvps;        /* products with A (polynomial build excluded)      */
+    int64_t dots;        /* inner products                                   */
+    int64_t vops;        /* length-n vector operations                       */
+    double max_resid;    /* largest residual among the returned pairs        */
+    int fp32_cycles;     /* cycles run with FP32 pi(A)v (PPA_MIXED)          */
+    int reserved;
+    int64_t spmv_passes; /* fused SpMV passes issued by the operator applications */
+    double t_apply_ms;   /* PPA_FLAG_TIMING: device time of all operator applications */
+    double t_cgs_ms;     /* PPA_FLAG_TIMING: device time of all CGS2 steps   */
+} ppa_eigs_result;
+
+/* Workspace bytes for ppa_eigs. */
+int ppa_eigs_workspace_bytes(const ppa_matrix* A, const ppa_poly* p, const ppa_eigs_opts* o,
+                             size_t* bytes);
+
+/* Polynomial preconditioned Arnoldi: the nev eigenpairs of A whose pi-images
+ * lie nearest 1 (i.e. of smallest magnitude for a GMRES polynomial), tested on
+ * A with Rayleigh quotients mu = y^* A y of unit Ritz vectors at the end of each
+ * cycle (section 4).  A restart keeps k Ritz vectors, k-1 when the k-th and
+ * (k+1)-th form a conjugate pair.  p == NULL runs standard Arnoldi on A and
+ * orders Ritz values by |nu|.  v0_d: start vector double[n] (device).
+ * Synchronises `stream` once per cycle.  Returns PPA_OK when all nev pairs
+ * converged, PPA_WARN_NOT_CONVERGED after max_cycles (outputs hold the last
+ * estimates), PPA_WARN_BREAKDOWN if the basis became invariant. */
+int ppa_eigs(const ppa_matrix* A, const ppa_poly* p, const ppa_eigs_opts* o,
+             const double* v0_d, void* ws_d, size_t ws_bytes, void* stream,
+             ppa_eigs_result* r);
+
+/* ------------------------------------------------------------------------
+ * Host small dense eigensolver used for the projected problems (exported for
+ * testing).  a: n x n column-major real matrix (host, not modified).
+ * wr, wi: eigenvalues (conjugate pairs adjacent, Im > 0 first).
+ * vr, vi: if non-NULL, unit eigenvectors, column j for eigenvalue j.
+ * ------------------------------------------------------------------------ */
+int ppa_dense_eig(int n, const double* a, double* wr, double* wi, double* vr, double* vi);
+
+/* Modified Leja ordering (section 2, step 1(c)) of a conjugate-closed root set
+ * (host arrays, in/out, length n).  Exported for testing. */
+int ppa_leja_order(int n, double* re, double* im);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPA_H */

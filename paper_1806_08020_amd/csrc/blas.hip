@@ -1,0 +1,449 @@
+// Dense kernels around the polynomial operator: classical Gram-Schmidt with
+// one reorthogonalisation pass against the Krylov basis V (section 4), the
+// tall-skinny product V Q of the thick restart and of the Ritz vectors on
+// FP64 MFMA, and small deterministic reductions for the convergence test.
+//
+// V is column-major (one Krylov vector per column, leading dimension a
+// multiple of 32 doubles).  Tall-skinny V^T w products are two-stage: each
+// block reduces its contiguous row range (wavefront shuffles, then LDS across
+// the 4 waves) into a partial per column, and a second kernel sums the
+// partials of a column in a fixed tree.  No floating-point atomics are used,
+// so every result is bitwise reproducible run to run.
+#include "ppa_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ppa {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int NW = BS / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Reduce `count` per-thread values acc[0..count) across the block and write
+// lane results to dst[c * stride] for c < count (thread c does column c).
+template <int NC>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NC], int count, double* red,
+                                                   double* dst, int64_t stride) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c < count) {
+            const double v = wave_sum(acc[c]);
+            if (lane == 0) red[w * NC + c] = v;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < count; c += BS) {
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += red[q * NC + c];
+        dst[c * stride] = t;
+    }
+}
+
+struct RowRange {
+    int64_t beg, end;
+};
+__device__ __forceinline__ RowRange rows_of_block(int64_t n, int nb) {
+    const int64_t per = (n + nb - 1) / nb;
+    const int64_t beg = (int64_t)blockIdx.x * per;
+    return {beg, min(n, beg + per)};
+}
+
+// partial[(c0 + c) * nb + b] = sum_r V[c0 + c][r] w[r]; optional ||w||^2 at
+// column `normcol`.
+template <int TJ>
+__global__ __launch_bounds__(BS) void k_proj(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                             int j, const double* __restrict__ w,
+                                             double* __restrict__ partial, int nb, int normcol) {
+    __shared__ double red[NW * (TJ + 1)];
+    const int c0 = blockIdx.y * TJ;
+    const int nc = min(TJ, j - c0);
+    const bool wn = normcol >= 0 && blockIdx.y == 0;
+    double acc[TJ + 1];
+#pragma unroll
+    for (int c = 0; c <= TJ; ++c) acc[c] = 0.0;
+    const RowRange rr = rows_of_block(n, nb);
+    for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
+        const double wr = w[r];
+#pragma unroll
+        for (int c = 0; c < TJ; ++c)
+            if (c < nc) acc[c] += V[(int64_t)(c0 + c) * ldv + r] * wr;
+        acc[TJ] += wr * wr;
+    }
+    block_reduce_store<TJ + 1>(acc, nc, red, partial + (int64_t)c0 * nb + blockIdx.x, nb);
+    if (wn) {
+        __syncthreads();
+        double tmp[1] = {acc[TJ]};
+        block_reduce_store<1>(tmp, 1, red, partial + (int64_t)normcol * nb + blockIdx.x, nb);
+    }
+}
+
+// t = w - V h (h of length j, device), then partial = V^T t.  j <= JMAX.
+template <int JMAX>
+__global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V, int64_t ldv,
+                                                    int64_t n, int j, const double* __restrict__ h,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ t,
+                                                    double* __restrict__ partial, int nb) {
+    __shared__ double hs[JMAX];
+    __shared__ double red[NW * JMAX];
+    for (int c = threadIdx.x; c < j; c += BS) hs[c] = h[c];
+    __syncthreads();
+    double acc[JMAX];
+#pragma unroll
+    for (int c = 0; c < JMAX; ++c) acc[c] = 0.0;
+    const RowRange rr = rows_of_block(n, nb);
+    for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
+        double tv = w[r];
+#pragma unroll
+        for (int c = 0; c < JMAX; ++c)
+            if (c < j) tv -= V[(int64_t)c * ldv + r] * hs[c];
+        t[r] = tv;
+#pragma unroll
+        for (int c = 0; c < JMAX; ++c)
+            if (c < j) acc[c] += V[(int64_t)c * ldv + r] * tv;
+    }
+    block_reduce_store<JMAX>(acc, j, red, partial + blockIdx.x, nb);
+}
+
+// out = t - V h (any j); partial[0 * nb + b] = ||out||^2 over the block's rows
+// when partial is non-null.
+__global__ __launch_bounds__(BS) void k_update(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                               int j, const double* __restrict__ h,
+                                               const double* __restrict__ t,
+                                               double* __restrict__ out,
+                                               double* __restrict__ partial, int nb) {
+    __shared__ double hs[CGS_JMAX_ALL];
+    __shared__ double red[NW];
+    for (int c = threadIdx.x; c < j; c += BS) hs[c] = h[c];
+    __syncthreads();
+    double nrm = 0.0;
+    const RowRange rr = rows_of_block(n, nb);
+    for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
+        double tv = t[r];
+        int c = 0;
+        for (; c + 4 <= j; c += 4) {
+            const double a0 = V[(int64_t)c * ldv + r], a1 = V[(int64_t)(c + 1) * ldv + r];
+            const double a2 = V[(int64_t)(c + 2) * ldv + r], a3 = V[(int64_t)(c + 3) * ldv + r];
+            tv -= a0 * hs[c];
+            tv -= a1 * hs[c + 1];
+            tv -= a2 * hs[c + 2];
+            tv -= a3 * hs[c + 3];
+        }
+        for (; c < j; ++c) tv -= V[(int64_t)c * ldv + r] * hs[c];
+        out[r] = tv;
+        nrm += tv * tv;
+    }
+    if (partial) {
+        double acc[1] = {nrm};
+        block_reduce_store<1>(acc, 1, red, partial + blockIdx.x, nb);
+    }
+}
+
+// out[c] = sum_b partial[c * nb + b], one block per column, fixed tree.
+__global__ __launch_bounds__(BS) void k_reduce_cols(const double* __restrict__ partial, int nb,
+                                                    double* __restrict__ out) {
+    __shared__ double red[NW];
+    const double* p = partial + (int64_t)blockIdx.x * nb;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) s += p[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += red[q];
+        out[blockIdx.x] = t;
+    }
+}
+
+// Hessenberg column: H[i] = h1[i] + h2[i] (i < j), H[j] = beta = ||w_out||;
+// h1[j] holds ||w_in||^2 and scal[1] ||w_out||^2.  scal[0] = ||w_in||^2,
+// scal[2] = 1/beta, or 0 when beta <= tol * ||w_in|| (breakdown).
+__global__ void k_cgs_finalize(const double* __restrict__ h1, const double* __restrict__ h2,
+                               int j, double* __restrict__ scal, double* __restrict__ Hcol,
+                               double tol) {
+    for (int i = threadIdx.x; i < j; i += blockDim.x) Hcol[i] = h1[i] + h2[i];
+    if (threadIdx.x == 0) {
+        const double beta = sqrt(scal[1]);
+        scal[0] = h1[j];
+        const double w0 = sqrt(h1[j]);
+        Hcol[j] = beta;
+        scal[2] = (beta > tol * w0 && beta > 0.0) ? 1.0 / beta : 0.0;
+    }
+}
+
+__global__ void k_scale(const double* __restrict__ in, double* __restrict__ out, int64_t n,
+                        const double* __restrict__ sc) {
+    const double s = *sc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] * s;
+}
+
+}  // namespace
+
+int cgs_blocks(int64_t n) {
+    const int64_t nb = (n + BS * 8 - 1) / (BS * 8);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 1024));
+}
+
+void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws) {
+    ws.nb = cgs_blocks(n);
+    ws.partial = c.take<double>((size_t)(CGS_JMAX_ALL + 2) * ws.nb);
+    ws.h1 = c.take<double>(CGS_JMAX_ALL);
+    ws.h2 = c.take<double>(CGS_JMAX_ALL);
+    ws.scal = c.take<double>(4);
+    ws.t = c.take<double>((size_t)n);
+}
+
+static unsigned sgrid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+}
+
+template <int TJ>
+static void proj(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* partial,
+                 int nb, int normcol, hipStream_t s) {
+    const int tiles = std::max(1, (j + TJ - 1) / TJ);
+    hipLaunchKernelGGL((k_proj<TJ>), dim3(nb, tiles), dim3(BS), 0, s, V, ldv, n, j, w, partial, nb,
+                       normcol);
+    PPA_HIP(hipGetLastError());
+}
+
+template <int JMAX>
+static void update_proj(int64_t n, int j, const double* V, int64_t ldv, const double* h,
+                        const double* w, double* t, double* partial, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_update_proj<JMAX>), dim3(nb), dim3(BS), 0, s, V, ldv, n, j, h, w, t,
+                       partial, nb);
+    PPA_HIP(hipGetLastError());
+}
+
+static void reduce_cols(const double* partial, int nb, int ncols, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(BS), 0, s, partial, nb, out);
+    PPA_HIP(hipGetLastError());
+}
+
+void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* w_out,
+                 double* Hcol_d, double* v_next, double breakdown_tol, Cgs2Ws& ws,
+                 hipStream_t s) {
+    PPA_REQUIRE(j >= 1 && j <= CGS_JMAX_ALL - 1, "cgs2: basis size %d out of range", j);
+    const int nb = ws.nb;
+    // pass 1: h1 = V^T w and ||w||^2
+    proj<32>(n, j, V, ldv, w, ws.partial, nb, j, s);
+    reduce_cols(ws.partial, nb, j + 1, ws.h1, s);   // h1[0..j-1], h1[j] = ||w_in||^2
+    // pass 2: t = w - V h1, h2 = V^T t
+    if (j <= 8)
+        update_proj<8>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
+    else if (j <= 16)
+        update_proj<16>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
+    else if (j <= 32)
+        update_proj<32>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
+    else if (j <= 64)
+        update_proj<64>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
+    else {
+        hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, ws.h1, w, ws.t,
+                           (double*)nullptr, nb);
+        PPA_HIP(hipGetLastError());
+        proj<32>(n, j, V, ldv, ws.t, ws.partial, nb, -1, s);
+    }
+    reduce_cols(ws.partial, nb, j, ws.h2, s);
+    // pass 3: w_out = t - V h2 and ||w_out||^2
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, ws.h2, ws.t, w_out,
+                       ws.partial, nb);
+    PPA_HIP(hipGetLastError());
+    reduce_cols(ws.partial, nb, 1, ws.scal + 1, s);
+    hipLaunchKernelGGL(k_cgs_finalize, dim3(1), dim3(256), 0, s, ws.h1, ws.h2, j, ws.scal, Hcol_d,
+                       breakdown_tol);
+    PPA_HIP(hipGetLastError());
+    if (v_next) {
+        hipLaunchKernelGGL(k_scale, dim3(sgrid(n)), dim3(256), 0, s, w_out, v_next, n, ws.scal + 2);
+        PPA_HIP(hipGetLastError());
+    }
+}
+
+// ---------------------------------------------------------------- MFMA GEMM
+// C[:, 0:kout] = V[:, 0:kin] Q, FP64 on v_mfma_f64_16x16x4f64.
+// Block = 4 waves; each wave owns RT tiles of 16 rows and all NT tiles of 16
+// output columns.  Q (zero-padded to KP x 16*NT) is staged in LDS once.
+// Operand layout of the 16x16x4 FP64 MFMA (wave of 64 lanes):
+//   A[i][k] in lane i + 16k;  B[k][j] in lane j + 16k;
+//   D[i][j] in lane j + 16 (i % 4), element i / 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int NT, int RT>
+__global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int kin, int kout,
+                                                   const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ Q,
+                                                   double* __restrict__ C, int64_t ldc) {
+    extern __shared__ double Qs[];
+    constexpr int NP = NT * 16;
+    const int KP = (kin + 3) & ~3;
+    for (int idx = threadIdx.x; idx < KP * NP; idx += 256) {
+        const int kk = idx / NP, cc = idx % NP;
+        Qs[idx] = (kk < kin && cc < kout) ? Q[(int64_t)cc * kin + kk] : 0.0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t rbase = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
+    v4d acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < KP; k0 += 4) {
+        const int kc = k0 + lk;
+        double a[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t row = rbase + rt * 16 + li;
+            a[rt] = (row < n && kc < kin) ? V[(int64_t)kc * ldv + row] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const double bq = Qs[kc * NP + t * 16 + li];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc[rt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], bq, acc[rt][t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int col = t * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = rbase + rt * 16 + lk + 4 * e;
+                if (row < n && col < kout) C[(int64_t)col * ldc + row] = acc[rt][t][e];
+            }
+        }
+}
+
+void launch_gemm_tall(int64_t n, int kin, int kout, const double* V, int64_t ldv, const double* Q_d,
+                      double* C, int64_t ldc, hipStream_t s) {
+    PPA_REQUIRE(kin >= 1 && kin <= 128 && kout >= 1 && kout <= 64, "gemm: kin %d / kout %d out of range",
+                kin, kout);
+    if (n <= 0) return;
+    constexpr int RT = 2;
+    const unsigned grid = (unsigned)((n + 4 * 16 * RT - 1) / (4 * 16 * RT));
+    const int KP = (kin + 3) & ~3;
+    const int NT = (kout + 15) / 16;
+    const size_t lds = (size_t)KP * NT * 16 * sizeof(double);
+    switch (NT) {
+        case 1: hipLaunchKernelGGL((k_gemm_tall<1, RT>), dim3(grid), dim3(256), lds, s, n, kin, kout, V, ldv, Q_d, C, ldc); break;
+        case 2: hipLaunchKernelGGL((k_gemm_tall<2, RT>), dim3(grid), dim3(256), lds, s, n, kin, kout, V, ldv, Q_d, C, ldc); break;
+        case 3: hipLaunchKernelGGL((k_gemm_tall<3, RT>), dim3(grid), dim3(256), lds, s, n, kin, kout, V, ldv, Q_d, C, ldc); break;
+        default: hipLaunchKernelGGL((k_gemm_tall<4, RT>), dim3(grid), dim3(256), lds, s, n, kin, kout, V, ldv, Q_d, C, ldc); break;
+    }
+    PPA_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- dots
+namespace {
+__global__ __launch_bounds__(BS) void k_dots(int64_t n, DotList L, double* __restrict__ partial,
+                                             int nb) {
+    __shared__ double red[NW * 8];
+    const RowRange rr = rows_of_block(n, nb);
+    for (int g = 0; g < L.count; g += 8) {
+        double acc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+        const int cnt = min(8, L.count - g);
+        for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < cnt) acc[c] += L.a[g + c][r] * L.b[g + c][r];
+        }
+        block_reduce_store<8>(acc, cnt, red, partial + (int64_t)g * nb + blockIdx.x, nb);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_combo_norms(int64_t n, ComboList L,
+                                                    double* __restrict__ partial, int nb) {
+    __shared__ double red[NW * 8];
+    const RowRange rr = rows_of_block(n, nb);
+    for (int g = 0; g < L.count; g += 8) {
+        double acc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+        const int cnt = min(8, L.count - g);
+        for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if (c < cnt) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        if (L.v[g + c][t]) v += L.c[g + c][t] * L.v[g + c][t][r];
+                    acc[c] += v * v;
+                }
+            }
+        }
+        block_reduce_store<8>(acc, cnt, red, partial + (int64_t)g * nb + blockIdx.x, nb);
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_complex(int64_t n, const double* __restrict__ Y, int64_t ldy,
+                               const int* __restrict__ cre, const int* __restrict__ cim,
+                               const double* __restrict__ scale, int ncols, double* __restrict__ X) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < ncols; ++c) {
+            const double sr = scale[2 * c], si = scale[2 * c + 1];
+            const double re = cre[c] >= 0 ? Y[(int64_t)cre[c] * ldy + i] : 0.0;
+            const double im = cim[c] >= 0 ? Y[(int64_t)cim[c] * ldy + i] : 0.0;
+            X[2 * ((int64_t)c * n + i)] = sr * re;
+            X[2 * ((int64_t)c * n + i) + 1] = si * im;
+        }
+    }
+}
+
+__global__ void k_zero(double* p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+}  // namespace
+
+void launch_dots(int64_t n, const DotList& L, double* partial, int nb, double* out_d,
+                 hipStream_t s) {
+    PPA_REQUIRE(L.count >= 1 && L.count <= MAX_DOTS, "dots: bad count");
+    hipLaunchKernelGGL(k_dots, dim3(nb), dim3(BS), 0, s, n, L, partial, nb);
+    PPA_HIP(hipGetLastError());
+    reduce_cols(partial, nb, L.count, out_d, s);
+}
+
+void launch_combo_norms(int64_t n, const ComboList& L, double* partial, int nb, double* out_d,
+                        hipStream_t s) {
+    PPA_REQUIRE(L.count >= 1 && L.count <= MAX_COMBOS, "combo norms: bad count");
+    hipLaunchKernelGGL(k_combo_norms, dim3(nb), dim3(BS), 0, s, n, L, partial, nb);
+    PPA_HIP(hipGetLastError());
+    reduce_cols(partial, nb, L.count, out_d, s);
+}
+
+void launch_copy_cols_complex(int64_t n, const double* Y, int64_t ldy, const int* cre,
+                              const int* cim, const double* scale, int ncols, double* X,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_complex, dim3(sgrid(n)), dim3(256), 0, s, n, Y, ldy, cre, cim, scale,
+                       ncols, X);
+    PPA_HIP(hipGetLastError());
+}
+
+void launch_zero(double* p, int64_t count, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_zero, dim3(sgrid(count)), dim3(256), 0, s, p, count);
+    PPA_HIP(hipGetLastError());
+}
+
+}  // namespace ppa

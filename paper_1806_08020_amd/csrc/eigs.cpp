@@ -1,0 +1,663 @@
+// GMRES polynomial construction on the device (section 2, step 1; section 8)
+// and thick-restarted Arnoldi(m,k) on pi(A) (section 2 step 2, section 4).
+//
+// Device work per Krylov step: one application of the polynomial operator
+// (d fused SpMV passes) and one CGS2 orthogonalisation.  The host sees the
+// small projected matrix once per cycle (one stream synchronisation), solves
+// the m x m eigenproblem, and drives the Ritz test and the restart, whose
+// n-sized work (V Q on MFMA, A Y, dots and residual norms) stays on the device.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <numeric>
+
+#include "ppa_internal.hpp"
+
+namespace ppa {
+
+namespace {
+
+constexpr double kBreakdownTol = 1e-14;
+
+__global__ void k_scale_host(double* v, int64_t n, double s) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] *= s;
+}
+__global__ void k_copy(const double* __restrict__ in, double* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+unsigned sgrid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+}
+
+// ||v||^2 of one device vector (deterministic), returned to the host.
+double norm2_host(int64_t n, const double* v, double* partial, int nb, double* out_d,
+                  hipStream_t s) {
+    DotList L{};
+    L.a[0] = v;
+    L.b[0] = v;
+    L.count = 1;
+    launch_dots(n, L, partial, nb, out_d, s);
+    double r = 0.0;
+    PPA_HIP(hipMemcpyAsync(&r, out_d, sizeof(double), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    return r;
+}
+
+// Copy v into dst and normalise it; returns ||v||.
+double set_unit(int64_t n, const double* v, double* dst, double* partial, int nb, double* out_d,
+                hipStream_t s) {
+    const double nn = std::sqrt(norm2_host(n, v, partial, nb, out_d, s));
+    if (!(nn > 0.0) || !std::isfinite(nn)) fail(PPA_ERR_NONFINITE, "start vector has zero or non-finite norm");
+    if (v != dst) {
+        hipLaunchKernelGGL(k_copy, dim3(sgrid(n)), dim3(256), 0, s, v, dst, n);
+        PPA_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_scale_host, dim3(sgrid(n)), dim3(256), 0, s, dst, n, 1.0 / nn);
+    PPA_HIP(hipGetLastError());
+    return nn;
+}
+
+// ---------------------------------------------------------------- GMRES
+struct GmresWs {
+    double* V = nullptr;
+    int64_t ld = 0;
+    double* w = nullptr;
+    double* H = nullptr;
+    Cgs2Ws cw;
+    ApplyWs aw;
+    double* dpart = nullptr;
+    double* dout = nullptr;
+};
+
+void carve_gmres(Carver& c, int64_t n, int d, bool tau, GmresWs& g) {
+    g.ld = col_ld(n);
+    g.V = c.take<double>((size_t)g.ld * (d + 1));
+    g.w = c.take<double>((size_t)n);
+    g.H = c.take<double>((size_t)(d + 1) * d);
+    carve_cgs2(c, n, g.cw);
+    if (tau) {
+        Poly dummy;
+        dummy.roots.assign(1, cplx(1.0, 0.0));
+        carve_apply(c, n, dummy, VecT::F64, g.aw);
+    }
+    g.dpart = c.take<double>((size_t)MAX_DOTS * cgs_blocks(n));
+    g.dout = c.take<double>(MAX_DOTS);
+}
+
+// tau(A) x = x - pi_1(A) x  (F64): the last pass of the pi_1 chain is scaled
+// by -1 and adds x in its epilogue.
+void apply_tau(const Matrix& A, const std::vector<cplx>& roots1, const double* x, double* out,
+               ApplyWs& aw, hipStream_t s) {
+    apply_single_epilogue(A, roots1, x, out, -1.0, 1.0, x, aw, s);
+}
+
+// One cycle of GMRES(d) from b with operator A (roots1 empty) or tau(A).
+// Returns the effective degree; Hbar receives (d_eff+1) x d_eff.
+int gmres_cycle(const Matrix& A, const std::vector<cplx>& roots1, int d, const double* b,
+                GmresWs& g, hipStream_t s, std::vector<double>& Hbar) {
+    const int64_t n = A.n;
+    launch_zero(g.H, (int64_t)(d + 1) * d, s);
+    set_unit(n, b, g.V, g.dpart, g.cw.nb, g.dout, s);
+    for (int j = 0; j < d; ++j) {
+        const double* vj = g.V + (size_t)j * g.ld;
+        if (roots1.empty())
+            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj, 0.0, nullptr, 0.0,
+                              nullptr, g.w, s);
+        else
+            apply_tau(A, roots1, vj, g.w, g.aw, s);
+        double* vn = g.V + (size_t)(j + 1) * g.ld;
+        launch_cgs2(n, j + 1, g.V, g.ld, g.w, vn, g.H + (size_t)j * (d + 1), vn, kBreakdownTol,
+                    g.cw, s);
+    }
+    std::vector<double> H((size_t)(d + 1) * d);
+    PPA_HIP(hipMemcpyAsync(H.data(), g.H, H.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    for (double e : H)
+        if (!std::isfinite(e)) fail(PPA_ERR_NONFINITE, "GMRES: non-finite Hessenberg entry");
+    int deff = d;
+    for (int j = 0; j < d; ++j) {
+        double colsq = 0.0;
+        for (int i = 0; i <= j + 1; ++i) colsq += H[i + (size_t)j * (d + 1)] * H[i + (size_t)j * (d + 1)];
+        if (H[j + 1 + (size_t)j * (d + 1)] <= kBreakdownTol * std::sqrt(colsq)) {
+            deff = j + 1;
+            break;
+        }
+    }
+    Hbar.assign((size_t)(deff + 1) * deff, 0.0);
+    for (int j = 0; j < deff; ++j)
+        for (int i = 0; i <= std::min(j + 1, deff); ++i) {
+            if (i == deff && deff < d) continue;   // breakdown: zero last row
+            Hbar[i + (size_t)j * (deff + 1)] = H[i + (size_t)j * (d + 1)];
+        }
+    return deff;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- build API
+size_t poly_build_ws(int64_t n, int d, bool dbl) {
+    Carver c(nullptr, 0);
+    GmresWs g;
+    carve_gmres(c, n, d, dbl, g);
+    return c.bytes();
+}
+
+int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
+               hipStream_t s, Poly& out) {
+    const bool dbl = d2 > 0;
+    const int dmax = std::max(d1, d2);
+    PPA_REQUIRE(d1 >= 1 && dmax <= CGS_JMAX_ALL - 2, "polynomial degree out of range");
+    Carver c(ws, ws_bytes);
+    GmresWs g;
+    carve_gmres(c, A.n, dmax, dbl, g);
+    c.check();
+    int status = PPA_OK;
+    std::vector<double> Hb;
+    int de = gmres_cycle(A, {}, d1, b, g, s, Hb);
+    if (de < d1) status = PPA_WARN_DEGREE_REDUCED;
+    std::vector<cplx> r1 = leja_order(harmonic_ritz(de, Hb));
+    if (!dbl) {
+        out.roots = r1;
+        out.roots1.clear();
+        return status;
+    }
+    de = gmres_cycle(A, r1, d2, b, g, s, Hb);
+    if (de < d2) status = PPA_WARN_DEGREE_REDUCED;
+    out.roots1 = r1;
+    out.roots = leja_order(harmonic_ritz(de, Hb));
+    return status;
+}
+
+// ---------------------------------------------------------------- Arnoldi
+namespace {
+
+struct EigsWs {
+    double* V = nullptr;
+    double* V2 = nullptr;
+    int64_t ld = 0;
+    double* w = nullptr;
+    ApplyWs aw64, aw32;
+    Cgs2Ws cw;
+    double* Hd = nullptr;
+    double* Qd = nullptr;
+    double* Y = nullptr;
+    double* AY = nullptr;
+    double* dpart = nullptr;
+    double* dout = nullptr;
+    int* cmap = nullptr;
+    double* cscale = nullptr;
+    int ycols = 0;
+};
+
+void carve_eigs(Carver& c, const Matrix& A, const Poly* p, const ppa_eigs_opts& o, EigsWs& e) {
+    const int64_t n = A.n;
+    e.ld = col_ld(n);
+    e.V = c.take<double>((size_t)e.ld * (o.m + 1));
+    e.V2 = c.take<double>((size_t)e.ld * (o.m + 1));
+    e.w = c.take<double>((size_t)n);
+    if (p) {
+        carve_apply(c, n, *p, VecT::F64, e.aw64);
+        if (o.precision == PPA_MIXED) carve_apply(c, n, *p, VecT::F32, e.aw32);
+    }
+    carve_cgs2(c, n, e.cw);
+    e.Hd = c.take<double>((size_t)(o.m + 1) * o.m);
+    // restart Q' ((m+1) x (k+1)) and Ritz coefficients G (m x 2 nev) share it
+    e.Qd = c.take<double>((size_t)(o.m + 1) * std::max(o.m + 1, 2 * o.nev));
+    e.ycols = 2 * o.nev;
+    e.Y = c.take<double>((size_t)e.ld * e.ycols);
+    e.AY = c.take<double>((size_t)e.ld * e.ycols);
+    e.dpart = c.take<double>((size_t)MAX_DOTS * cgs_blocks(n));
+    e.dout = c.take<double>(MAX_DOTS);
+    e.cmap = c.take<int>((size_t)2 * o.nev);
+    e.cscale = c.take<double>((size_t)2 * o.nev);
+}
+
+// Ordering of Ritz values of the operator (section 4): increasing |target - nu|,
+// ties larger Im first, then smaller Re.
+std::vector<int> sort_ritz(const std::vector<cplx>& nu, double target) {
+    std::vector<int> idx(nu.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const double da = std::abs(target - nu[a]), db = std::abs(target - nu[b]);
+        if (da != db) return da < db;
+        if (nu[a].imag() != nu[b].imag()) return nu[a].imag() > nu[b].imag();
+        return nu[a].real() < nu[b].real();
+    });
+    return idx;
+}
+
+struct Wanted {
+    // per wanted Ritz value i: Y columns holding Re / Im of its vector
+    std::vector<int> cre, cim;
+    std::vector<double> imsign;   // +1 or -1 (conjugate member)
+    int ycols = 0;
+};
+
+struct RitzOut {
+    std::vector<cplx> mu;
+    std::vector<double> res;
+    std::vector<double> ynorm;
+};
+
+}  // namespace
+
+size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o) {
+    Carver c(nullptr, 0);
+    EigsWs e;
+    carve_eigs(c, A, p, o, e);
+    return c.bytes();
+}
+
+int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v0, void* ws,
+         size_t ws_bytes, hipStream_t s, ppa_eigs_result& r) {
+    const int m = o.m, k = o.k, nev = o.nev;
+    PPA_REQUIRE(m >= 2 && m <= 64, "eigs: m must be in [2, 64]");
+    PPA_REQUIRE(nev >= 1 && nev <= k && k < m, "eigs: need 1 <= nev <= k < m");
+    PPA_REQUIRE(nev <= 32, "eigs: nev must be <= 32");
+    PPA_REQUIRE(o.max_cycles >= 1, "eigs: max_cycles must be >= 1");
+    PPA_REQUIRE(o.precision == PPA_F64 || o.precision == PPA_MIXED, "eigs: precision must be F64 or MIXED");
+    PPA_REQUIRE(o.precision == PPA_F64 || (p && A.v32), "eigs: MIXED needs a polynomial and FP32 values");
+    PPA_REQUIRE(r.lam_re && r.lam_im && r.resid, "eigs: result arrays are required");
+    const int64_t n = A.n;
+    PPA_REQUIRE(n >= m + 1, "eigs: n must exceed m");
+    Carver c(ws, ws_bytes);
+    EigsWs e;
+    carve_eigs(c, A, p, o, e);
+    c.check();
+    const double anorm = o.anorm > 0.0 ? o.anorm : A.norm_inf;
+    const double rtol_abs = o.rtol * anorm;
+    const double target = p ? 1.0 : 0.0;
+    const int nb = e.cw.nb;
+
+    // operator counts per application (same convention as the oracle)
+    int64_t op_mvps = 1, op_vops = 0;
+    if (p) {
+        if (p->is_double()) {
+            op_mvps = (int64_t)p->roots1.size() * p->roots.size();
+            op_vops = (int64_t)p->roots.size() * ((int64_t)p->roots1.size() + 2);
+        } else {
+            op_mvps = p->roots.size();
+            op_vops = p->roots.size();
+        }
+    }
+    int64_t mvps = 0, dots = 0, vops = 0, passes = 0;
+    bool fp32 = o.precision == PPA_MIXED;
+    const bool timing = (o.flags & PPA_FLAG_TIMING) != 0;
+    struct Events {
+        std::vector<hipEvent_t> ev;
+        ~Events() {
+            for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        }
+    } tev;
+    if (timing) {
+        tev.ev.resize(3 * (size_t)(m + 1));
+        for (auto& x : tev.ev) PPA_HIP(hipEventCreate(&x));
+    }
+    double t_apply = 0.0, t_cgs = 0.0;
+    int fp32_cycles = 0;
+
+    auto apply_op = [&](const double* x, double* y) {
+        if (!p) {
+            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, x, 0.0, nullptr, 0.0,
+                              nullptr, y, s);
+        } else if (fp32) {
+            apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F32, e.aw32, s);
+        } else {
+            apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F64, e.aw64, s);
+        }
+        mvps += op_mvps;
+        vops += op_vops;
+        passes += op_mvps;
+    };
+
+    launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
+    set_unit(n, v0, e.V, e.dpart, nb, e.dout, s);
+    int j0 = 0;
+    std::vector<double> H((size_t)(m + 1) * m);
+    std::vector<double> hist;
+    RitzOut last;
+    Wanted lastw;
+    std::vector<cplx> lastnu;
+    bool converged = false, broke = false;
+    int cycle = 0;
+    for (cycle = 1; cycle <= o.max_cycles; ++cycle) {
+        if (fp32) ++fp32_cycles;
+        for (int j = j0; j < m; ++j) {
+            if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j], s));
+            apply_op(e.V + (size_t)j * e.ld, e.w);
+            if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + 1], s));
+            double* vn = e.V + (size_t)(j + 1) * e.ld;
+            launch_cgs2(n, j + 1, e.V, e.ld, e.w, vn, e.Hd + (size_t)j * (m + 1), vn,
+                        kBreakdownTol, e.cw, s);
+            if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + 2], s));
+            dots += 2 * (j + 1) + 1;
+            vops += 4 * (j + 1) + 2;
+        }
+        PPA_HIP(hipMemcpyAsync(H.data(), e.Hd, H.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        PPA_HIP(hipStreamSynchronize(s));
+        if (timing) {
+            for (int j = j0; j < m; ++j) {
+                float a = 0.f, b = 0.f;
+                PPA_HIP(hipEventElapsedTime(&a, tev.ev[3 * j], tev.ev[3 * j + 1]));
+                PPA_HIP(hipEventElapsedTime(&b, tev.ev[3 * j + 1], tev.ev[3 * j + 2]));
+                t_apply += a;
+                t_cgs += b;
+            }
+        }
+        for (double x : H)
+            if (!std::isfinite(x)) fail(PPA_ERR_NONFINITE, "Arnoldi: non-finite Hessenberg entry");
+        int mc = m;
+        for (int j = j0; j < m; ++j) {
+            double colsq = 0.0;
+            for (int i = 0; i <= j + 1; ++i) colsq += H[i + (size_t)j * (m + 1)] * H[i + (size_t)j * (m + 1)];
+            if (H[j + 1 + (size_t)j * (m + 1)] <= kBreakdownTol * std::sqrt(colsq)) {
+                mc = j + 1;
+                broke = true;
+                break;
+            }
+        }
+        // Ritz pairs of the operator
+        std::vector<double> Hm((size_t)mc * mc);
+        for (int jj = 0; jj < mc; ++jj)
+            for (int i = 0; i < mc; ++i) Hm[i + (size_t)jj * mc] = H[i + (size_t)jj * (m + 1)];
+        std::vector<cplx> nu0, G0;
+        dense_eig(mc, Hm.data(), nu0, &G0);
+        const std::vector<int> ord = sort_ritz(nu0, target);
+        std::vector<cplx> nu(mc);
+        std::vector<cplx> G((size_t)mc * mc);
+        for (int i = 0; i < mc; ++i) {
+            nu[i] = nu0[ord[i]];
+            for (int q = 0; q < mc; ++q) G[q + (size_t)i * mc] = G0[q + (size_t)ord[i] * mc];
+        }
+        // wanted Ritz vectors y = V_m g as real columns of Y
+        const int nw = std::min(nev, mc);
+        Wanted W;
+        std::vector<double> Gw;   // mc x ycols
+        for (int i = 0; i < nw; ++i) {
+            if (nu[i].imag() == 0.0) {
+                W.cre.push_back(W.ycols);
+                W.cim.push_back(-1);
+                W.imsign.push_back(0.0);
+                for (int q = 0; q < mc; ++q) Gw.push_back(G[q + (size_t)i * mc].real());
+                W.ycols += 1;
+            } else if (nu[i].imag() > 0.0 || i == 0 || nu[i - 1] != std::conj(nu[i])) {
+                // y = V g with columns Re g, Im g
+                W.cre.push_back(W.ycols);
+                W.cim.push_back(W.ycols + 1);
+                W.imsign.push_back(1.0);
+                for (int q = 0; q < mc; ++q) Gw.push_back(G[q + (size_t)i * mc].real());
+                for (int q = 0; q < mc; ++q) Gw.push_back(G[q + (size_t)i * mc].imag());
+                W.ycols += 2;
+            } else {
+                // conjugate of the previous wanted value: same columns
+                W.cre.push_back(W.cre.back());
+                W.cim.push_back(W.cim.back());
+                W.imsign.push_back(-1.0);
+            }
+        }
+        PPA_HIP(hipMemcpyAsync(e.Qd, Gw.data(), Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemm_tall(n, mc, W.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);
+        for (int cc = 0; cc < W.ycols; ++cc)
+            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, e.Y + (size_t)cc * e.ld, 0.0,
+                              nullptr, 0.0, nullptr, e.AY + (size_t)cc * e.ld, s);
+        // dots: per column pair (re, im) or single re column; an entry
+        // {a, b} is y_a . (A y)_b, {a, b + 1000} is y_a . y_b
+        std::vector<std::array<int, 2>> dspec;
+        for (int i = 0; i < nw; ++i) {
+            if (i > 0 && W.cre[i] == W.cre[i - 1]) continue;
+            const int a = W.cre[i], b = W.cim[i];
+            dspec.push_back({a, a + 1000});       // y_a . y_a
+            dspec.push_back({a, a});              // y_a . Ay_a
+            if (b >= 0) {
+                dspec.push_back({b, b + 1000});
+                dspec.push_back({b, b});
+                dspec.push_back({a, b});          // y_a . Ay_b
+                dspec.push_back({b, a});          // y_b . Ay_a
+            }
+        }
+        std::vector<double> dv(dspec.size());
+        for (size_t off = 0; off < dspec.size(); off += MAX_DOTS) {
+            DotList L{};
+            L.count = (int)std::min<size_t>(MAX_DOTS, dspec.size() - off);
+            for (int t = 0; t < L.count; ++t) {
+                const auto& q = dspec[off + t];
+                L.a[t] = e.Y + (size_t)q[0] * e.ld;
+                L.b[t] = q[1] >= 1000 ? e.Y + (size_t)(q[1] - 1000) * e.ld : e.AY + (size_t)q[1] * e.ld;
+            }
+            launch_dots(n, L, e.dpart, nb, e.dout, s);
+            PPA_HIP(hipMemcpyAsync(dv.data() + off, e.dout, L.count * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        PPA_HIP(hipStreamSynchronize(s));
+        // Rayleigh quotients mu = y^* A y / y^* y
+        RitzOut R;
+        R.mu.resize(nw);
+        R.res.resize(nw);
+        R.ynorm.resize(nw);
+        {
+            size_t t = 0;
+            std::vector<cplx> mu_col(W.ycols);
+            std::vector<double> yy_col(W.ycols);
+            for (int i = 0; i < nw; ++i) {
+                if (i > 0 && W.cre[i] == W.cre[i - 1]) {
+                    R.mu[i] = std::conj(R.mu[i - 1]);
+                    R.ynorm[i] = R.ynorm[i - 1];
+                    continue;
+                }
+                if (W.cim[i] < 0) {
+                    const double yy = dv[t], yAy = dv[t + 1];
+                    t += 2;
+                    R.mu[i] = cplx(yAy / yy, 0.0);
+                    R.ynorm[i] = std::sqrt(yy);
+                } else {
+                    const double aa = dv[t], aAa = dv[t + 1], bb = dv[t + 2], bAb = dv[t + 3];
+                    const double aAb = dv[t + 4], bAa = dv[t + 5];
+                    t += 6;
+                    const double yy = aa + bb;
+                    R.mu[i] = cplx(aAa + bAb, aAb - bAa) / yy;
+                    R.ynorm[i] = std::sqrt(yy);
+                }
+            }
+        }
+        for (int i = 0; i < nw; ++i) mvps += (nu[i].imag() == 0.0) ? 1 : 2;
+        // residual norms ||A y - mu y|| / ||y||
+        {
+            struct Combo {
+                const double* v[3];
+                double c[3];
+            };
+            std::vector<Combo> L;
+            std::vector<int> owner;
+            for (int i = 0; i < nw; ++i) {
+                if (i > 0 && W.cre[i] == W.cre[i - 1]) continue;
+                const int a = W.cre[i], b = W.cim[i];
+                const double mr = R.mu[i].real(), mi = R.mu[i].imag();
+                const double* Ya = e.Y + (size_t)a * e.ld;
+                const double* AYa = e.AY + (size_t)a * e.ld;
+                if (b < 0) {
+                    L.push_back({{AYa, Ya, nullptr}, {1.0, -mr, 0.0}});
+                    owner.push_back(i);
+                } else {
+                    const double* Yb = e.Y + (size_t)b * e.ld;
+                    const double* AYb = e.AY + (size_t)b * e.ld;
+                    // A y - mu y with y = a + i b, mu = mr + i mi:
+                    // real part A a - mr a + mi b, imaginary part A b - mr b - mi a
+                    L.push_back({{AYa, Ya, Yb}, {1.0, -mr, mi}});
+                    L.push_back({{AYb, Yb, Ya}, {1.0, -mr, -mi}});
+                    owner.push_back(i);
+                    owner.push_back(i);
+                }
+            }
+            const int nl = (int)L.size();
+            std::vector<double> rn(nl);
+            // split into launches of at most MAX_COMBOS
+            int done = 0;
+            while (done < nl) {
+                ComboList P{};
+                P.count = std::min(MAX_COMBOS, nl - done);
+                for (int q = 0; q < P.count; ++q)
+                    for (int t = 0; t < 3; ++t) {
+                        P.v[q][t] = L[done + q].v[t];
+                        P.c[q][t] = L[done + q].c[t];
+                    }
+                launch_combo_norms(n, P, e.dpart, nb, e.dout, s);
+                PPA_HIP(hipMemcpyAsync(rn.data() + done, e.dout, P.count * sizeof(double), hipMemcpyDeviceToHost, s));
+                done += P.count;
+            }
+            PPA_HIP(hipStreamSynchronize(s));
+            std::vector<double> acc(nw, 0.0);
+            for (size_t q = 0; q < owner.size(); ++q) acc[owner[q]] += rn[q];
+            for (int i = 0; i < nw; ++i) {
+                if (i > 0 && W.cre[i] == W.cre[i - 1]) {
+                    R.res[i] = R.res[i - 1];
+                    continue;
+                }
+                R.res[i] = std::sqrt(acc[i]) / R.ynorm[i];
+            }
+        }
+        double mx = 0.0;
+        for (int i = 0; i < nw; ++i) mx = std::max(mx, R.res[i]);
+        hist.push_back(mx);
+        last = R;
+        lastw = W;
+        lastnu.assign(nu.begin(), nu.begin() + nw);
+        converged = (nw == nev) && mx <= rtol_abs;
+        if (converged || broke || cycle == o.max_cycles) break;
+
+        if (fp32) {
+            // leave the FP32 phase when the wanted residuals stop improving
+            // or approach the FP32 floor; restart in FP64 from the sum of the
+            // wanted unit Ritz vectors
+            const size_t hc = hist.size();
+            const bool floor = mx <= 100.0 * 1.1920929e-07 * anorm;
+            const bool stall = hc >= 3 && hist[hc - 1] > 0.5 * hist[hc - 3];
+            if (floor || stall) {
+                fp32 = false;
+                std::vector<double> coef(W.ycols, 0.0);
+                for (int i = 0; i < nw; ++i) {
+                    if (i > 0 && W.cre[i] == W.cre[i - 1]) continue;
+                    coef[W.cre[i]] += 1.0 / R.ynorm[i];
+                    if (W.cim[i] >= 0) coef[W.cim[i]] += 1.0 / R.ynorm[i];
+                }
+                PPA_HIP(hipMemcpyAsync(e.Qd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
+                launch_gemm_tall(n, W.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
+                launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
+                set_unit(n, e.V2, e.V, e.dpart, nb, e.dout, s);
+                j0 = 0;
+                continue;
+            }
+        }
+
+        // thick restart: keep k (k-1 if a conjugate pair would be split)
+        int kk = std::min(k, mc - 1);
+        if (kk < mc && nu[kk - 1].imag() > 0.0) kk -= 1;
+        if (kk == 0) kk = std::min(2, mc - 1);
+        std::vector<double> B;
+        for (int i = 0; i < kk; ++i) {
+            if (nu[i].imag() == 0.0) {
+                for (int q = 0; q < mc; ++q) B.push_back(G[q + (size_t)i * mc].real());
+            } else if (nu[i].imag() > 0.0) {
+                for (int q = 0; q < mc; ++q) B.push_back(G[q + (size_t)i * mc].real());
+                for (int q = 0; q < mc; ++q) B.push_back(G[q + (size_t)i * mc].imag());
+            }
+        }
+        std::vector<double> Q;
+        orthonormal_basis(mc, kk, B, Q);
+        // Q' = [[Q, 0], [0, 1]]  ((m+1) x (kk+1)): V2 = [V_m Q, v_{m+1}]
+        std::vector<double> Qp((size_t)(m + 1) * (kk + 1), 0.0);
+        for (int jj = 0; jj < kk; ++jj)
+            for (int i = 0; i < mc; ++i) Qp[i + (size_t)jj * (m + 1)] = Q[i + (size_t)jj * mc];
+        Qp[m + (size_t)kk * (m + 1)] = 1.0;
+        PPA_HIP(hipMemcpyAsync(e.Qd, Qp.data(), Qp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemm_tall(n, m + 1, kk + 1, e.V, e.ld, e.Qd, e.V2, e.ld, s);
+        std::swap(e.V, e.V2);
+        // H_k = Q^T H_m Q and the spike row h_{m+1,m} e_m^T Q
+        std::vector<double> HQ((size_t)mc * kk, 0.0), Hn((size_t)(m + 1) * m, 0.0);
+        for (int jj = 0; jj < kk; ++jj)
+            for (int i = 0; i < mc; ++i) {
+                double sacc = 0.0;
+                for (int q = 0; q < mc; ++q) sacc += Hm[i + (size_t)q * mc] * Q[q + (size_t)jj * mc];
+                HQ[i + (size_t)jj * mc] = sacc;
+            }
+        for (int jj = 0; jj < kk; ++jj)
+            for (int i = 0; i < kk; ++i) {
+                double sacc = 0.0;
+                for (int q = 0; q < mc; ++q) sacc += Q[q + (size_t)i * mc] * HQ[q + (size_t)jj * mc];
+                Hn[i + (size_t)jj * (m + 1)] = sacc;
+            }
+        const double hm = H[m + (size_t)(m - 1) * (m + 1)];
+        for (int jj = 0; jj < kk; ++jj) Hn[kk + (size_t)jj * (m + 1)] = hm * Q[(m - 1) + (size_t)jj * mc];
+        PPA_HIP(hipMemcpyAsync(e.Hd, Hn.data(), Hn.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        j0 = kk;
+    }
+    if (cycle > o.max_cycles) cycle = o.max_cycles;
+
+    // outputs sorted by |mu| (ties: Re, then Im)
+    const int nw = (int)last.mu.size();
+    std::vector<int> ord(nw);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        const double ma = std::abs(last.mu[a]), mb = std::abs(last.mu[b]);
+        if (ma != mb) return ma < mb;
+        if (last.mu[a].real() != last.mu[b].real()) return last.mu[a].real() < last.mu[b].real();
+        return last.mu[a].imag() < last.mu[b].imag();
+    });
+    int nconv = 0;
+    double maxres = 0.0;
+    for (int t = 0; t < nev; ++t) {
+        if (t < nw) {
+            const int i = ord[t];
+            r.lam_re[t] = last.mu[i].real();
+            r.lam_im[t] = last.mu[i].imag();
+            r.resid[t] = last.res[i];
+            if (r.ritz_re) r.ritz_re[t] = lastnu[i].real();
+            if (r.ritz_im) r.ritz_im[t] = lastnu[i].imag();
+            if (last.res[i] <= rtol_abs) ++nconv;
+            maxres = std::max(maxres, last.res[i]);
+        } else {
+            r.lam_re[t] = r.lam_im[t] = std::nan("");
+            r.resid[t] = std::nan("");
+        }
+    }
+    if (r.X_d && nw > 0) {
+        std::vector<int> cre(nw), cim(nw);
+        std::vector<double> sc(2 * nw);
+        for (int t = 0; t < nw; ++t) {
+            const int i = ord[t];
+            cre[t] = lastw.cre[i];
+            cim[t] = lastw.cim[i];
+            const double inv = 1.0 / last.ynorm[i];
+            sc[2 * t] = inv;
+            sc[2 * t + 1] = (lastw.imsign[i] < 0.0 ? -1.0 : 1.0) * inv;
+        }
+        // Y still holds the wanted columns of the last cycle
+        std::vector<int> maps(2 * nw);
+        for (int t = 0; t < nw; ++t) {
+            maps[t] = cre[t];
+            maps[nw + t] = cim[t];
+        }
+        PPA_HIP(hipMemcpyAsync(e.cmap, maps.data(), maps.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        PPA_HIP(hipMemcpyAsync(e.cscale, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_copy_cols_complex(n, e.Y, e.ld, e.cmap, e.cmap + nw, e.cscale, nw, r.X_d, s);
+        PPA_HIP(hipStreamSynchronize(s));
+    }
+    r.nconv = nconv;
+    r.cycles = cycle;
+    r.mvps = mvps;
+    r.dots = dots;
+    r.vops = vops;
+    r.max_resid = maxres;
+    r.fp32_cycles = fp32_cycles;
+    r.spmv_passes = passes;
+    r.t_apply_ms = t_apply;
+    r.t_cgs_ms = t_cgs;
+    if (converged) return PPA_OK;
+    if (broke) return PPA_WARN_BREAKDOWN;
+    return PPA_WARN_NOT_CONVERGED;
+}
+
+}  // namespace ppa

@@ -1,0 +1,245 @@
+// The GMRES polynomial: construction (section 2, step 1) and application in
+// factored form (eq. (2.1)), single and double (section 8).
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "ppa_internal.hpp"
+
+namespace ppa {
+
+// ---------------------------------------------------------------- roots
+// Step 1(b): harmonic Ritz values = eig(H_d + h_{d+1,d}^2 f e_d^T) with
+// H_d^T f = e_d.  The modified matrix stays upper Hessenberg (only its last
+// column changes), so Francis QR applies directly.
+std::vector<cplx> harmonic_ritz(int d, const std::vector<double>& Hbar) {
+    const int ld = d + 1;
+    std::vector<double> Hd((size_t)d * d), HdT((size_t)d * d);
+    for (int j = 0; j < d; ++j)
+        for (int i = 0; i < d; ++i) {
+            Hd[i + (size_t)j * d] = Hbar[i + (size_t)j * ld];
+            HdT[j + (size_t)i * d] = Hbar[i + (size_t)j * ld];
+        }
+    const double h = Hbar[d + (size_t)(d - 1) * ld];
+    std::vector<double> f(d, 0.0);
+    f[d - 1] = 1.0;
+    if (h != 0.0) {
+        if (!lu_solve(d, HdT, f)) fail(PPA_ERR_SINGULAR, "harmonic Ritz: H_d is singular (d=%d)", d);
+        for (int i = 0; i < d; ++i) Hd[i + (size_t)(d - 1) * d] += h * h * f[i];
+    }
+    std::vector<cplx> w;
+    hessenberg_eigvals(d, Hd, w);
+    return w;
+}
+
+// Step 1(c): modified Leja ordering with sums of logarithms.  Reading of the
+// details: candidates pre-sorted by (Re, Im); a conjugate pair is represented
+// by its Im > 0 member and its conjugate follows it at once; the first root
+// has the largest modulus (ties: real first, then larger real part); each
+// next root maximises sum log|z - c| over the roots already placed (ties: the
+// earliest in pre-sorted order); roots scoring -inf (copies of placed roots)
+// are appended last in pre-sorted order.
+std::vector<cplx> leja_order(const std::vector<cplx>& theta) {
+    std::vector<cplx> pts = theta;
+    std::stable_sort(pts.begin(), pts.end(), [](const cplx& a, const cplx& b) {
+        if (a.real() != b.real()) return a.real() < b.real();
+        return a.imag() < b.imag();
+    });
+    std::vector<cplx> reps;
+    int npos = 0, nneg = 0;
+    for (const cplx& z : pts) {
+        if (z.imag() >= 0.0) reps.push_back(z);
+        if (z.imag() > 0.0) ++npos;
+        if (z.imag() < 0.0) ++nneg;
+    }
+    PPA_REQUIRE(npos == nneg, "root set is not closed under conjugation");
+    std::vector<cplx> out;
+    out.reserve(theta.size());
+    auto take = [&](size_t i) {
+        const cplx z = reps[i];
+        reps.erase(reps.begin() + i);
+        out.push_back(z);
+        if (z.imag() > 0.0) out.push_back(std::conj(z));
+    };
+    if (reps.empty()) return out;
+    {
+        double mx = -1.0;
+        for (const cplx& z : reps) mx = std::max(mx, std::abs(z));
+        size_t best = reps.size();
+        for (size_t i = 0; i < reps.size(); ++i) {
+            if (std::abs(reps[i]) != mx) continue;
+            if (best == reps.size()) { best = i; continue; }
+            const cplx& b = reps[best];
+            const int kb = b.imag() == 0.0 ? 0 : 1, ki = reps[i].imag() == 0.0 ? 0 : 1;
+            if (ki < kb || (ki == kb && reps[i].real() > b.real())) best = i;
+        }
+        take(best);
+    }
+    while (!reps.empty()) {
+        size_t best = 0;
+        double bs = -std::numeric_limits<double>::infinity();
+        bool any = false;
+        for (size_t i = 0; i < reps.size(); ++i) {
+            double sc = 0.0;
+            for (const cplx& c : out) sc += std::log(std::abs(reps[i] - c));
+            if (!any || sc > bs) {
+                bs = sc;
+                best = i;
+                any = true;
+            }
+        }
+        if (bs == -std::numeric_limits<double>::infinity()) {
+            while (!reps.empty()) take(0);
+            break;
+        }
+        take(best);
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------- apply
+int apply_buffers(const Poly& p) { return p.is_double() ? 6 : 4; }
+
+void carve_apply(Carver& c, int64_t n, const Poly& p, VecT t, ApplyWs& ws) {
+    const size_t es = t == VecT::F64 ? sizeof(double) : sizeof(float);
+    for (int i = 0; i < apply_buffers(p); ++i) ws.buf[i] = c.take<char>((size_t)n * es);
+}
+
+namespace {
+
+struct Chain {
+    const Matrix& A;
+    VecT ct;            // chain element type
+    hipStream_t s;
+    std::vector<void*> pool;
+    void pass(double alpha, const void* x, double beta, const void* u, double gamma, const void* z,
+              double delta, const void* z2, void* out, VecT out_t) {
+        launch_fused_spmv(A, ct, out_t, alpha, x, beta, u, gamma, z, delta, z2, out, s);
+    }
+};
+
+// out = c * pi(A) u0 + gamma z + delta z2, factors in order.  `busy` lists
+// buffers the caller still needs.
+void pi_chain(Chain& ch, const std::vector<cplx>& roots, const void* u0, double c, double gamma,
+              const void* z, double delta, const void* z2, void* out, VecT out_t,
+              std::initializer_list<const void*> busy_outer) {
+    const void* cur = u0;
+    const size_t nr = roots.size();
+    std::vector<const void*> busy(busy_outer);
+    auto pick = [&](const void* a, const void* b) {
+        for (void* buf : ch.pool) {
+            bool used = buf == a || buf == b || buf == out;
+            for (const void* q : busy) used |= (q == buf);
+            if (!used) return buf;
+        }
+        fail(PPA_ERR_INVALID, "internal: apply buffer pool exhausted");
+    };
+    size_t i = 0;
+    while (i < nr) {
+        const cplx t = roots[i];
+        const bool pair = t.imag() != 0.0;
+        const bool last = (i + (pair ? 2 : 1)) >= nr;
+        if (!pair) {
+            const double ib = -1.0 / t.real();
+            if (last) {
+                ch.pass(c, cur, c * ib, cur, gamma, z, delta, z2, out, out_t);
+            } else {
+                void* nx = pick(cur, nullptr);
+                ch.pass(1.0, cur, ib, cur, 0.0, nullptr, 0.0, nullptr, nx, ch.ct);
+                cur = nx;
+            }
+            i += 1;
+        } else {
+            const double a = t.real();
+            const double q = t.real() * t.real() + t.imag() * t.imag();
+            void* sb = pick(cur, nullptr);
+            ch.pass(2.0 * a, cur, -1.0, cur, 0.0, nullptr, 0.0, nullptr, sb, ch.ct);
+            if (last) {
+                ch.pass(c, cur, -c / q, sb, gamma, z, delta, z2, out, out_t);
+            } else {
+                void* nx = pick(cur, sb);
+                ch.pass(1.0, cur, -1.0 / q, sb, 0.0, nullptr, 0.0, nullptr, nx, ch.ct);
+                cur = nx;
+            }
+            i += 2;
+        }
+    }
+}
+
+}  // namespace
+
+void apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
+                           double* y, double c, double gamma, const double* z, ApplyWs& ws,
+                           hipStream_t s) {
+    PPA_REQUIRE(!roots.empty(), "apply: empty polynomial");
+    Chain ch{A, VecT::F64, s, {}};
+    for (int i = 0; i < 4; ++i) ch.pool.push_back(ws.buf[i]);
+    pi_chain(ch, roots, v, c, gamma, z, 0.0, nullptr, y, VecT::F64, {v, z});
+}
+
+void apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vout, void* y,
+                VecT chain, ApplyWs& ws, hipStream_t s) {
+    PPA_REQUIRE(p.degree() >= 1, "apply: empty polynomial");
+    Chain ch{A, chain, s, {}};
+    const int nb = apply_buffers(p);
+    for (int i = 0; i < nb; ++i) ch.pool.push_back(ws.buf[i]);
+    const void* v0 = v;
+    if (vin != chain) {
+        // bring the input into the chain precision (one streaming pass)
+        void* cv = ch.pool.back();
+        ch.pool.pop_back();
+        if (chain == VecT::F32)
+            launch_cast_f64_f32((const double*)v, (float*)cv, A.n, s);
+        else
+            launch_cast_f32_f64((const float*)v, (double*)cv, A.n, s);
+        v0 = cv;
+    }
+    if (!p.is_double()) {
+        pi_chain(ch, p.roots, v0, 1.0, 0.0, nullptr, 0.0, nullptr, y, vout, {v0});
+        return;
+    }
+    // pi_2(tau(A)) v with tau = 1 - pi_1 (section 8):
+    //  real eta:  w <- (1 - 1/eta) w + (1/eta) pi_1(A) w
+    //  pair eta:  s = (2a - 1) w + pi_1(A) w,
+    //             w <- w - s/|eta|^2 + (1/|eta|^2) pi_1(A) s
+    const void* w = v0;
+    const size_t nr = p.roots.size();
+    size_t i = 0;
+    auto pick_outer = [&](const void* a, const void* b) -> void* {
+        for (void* buf : ch.pool)
+            if (buf != a && buf != b) return buf;
+        fail(PPA_ERR_INVALID, "internal: apply buffer pool exhausted");
+    };
+    while (i < nr) {
+        const cplx eta = p.roots[i];
+        const bool pair = eta.imag() != 0.0;
+        const bool last = (i + (pair ? 2 : 1)) >= nr;
+        if (!pair) {
+            void* out = last ? y : pick_outer(w, v0);
+            const VecT ot = last ? vout : chain;
+            pi_chain(ch, p.roots1, w, 1.0 / eta.real(), 1.0 - 1.0 / eta.real(), w, 0.0, nullptr, out,
+                     ot, {w, v0});
+            w = out;
+            i += 1;
+        } else {
+            const double a = eta.real();
+            const double q = eta.real() * eta.real() + eta.imag() * eta.imag();
+            void* sb = pick_outer(w, v0);
+            pi_chain(ch, p.roots1, w, 1.0, 2.0 * a - 1.0, w, 0.0, nullptr, sb, chain, {w, v0});
+            void* out = nullptr;
+            if (last) {
+                out = y;
+            } else {
+                for (void* buf : ch.pool)
+                    if (buf != w && buf != v0 && buf != sb) { out = buf; break; }
+                PPA_REQUIRE(out != nullptr, "internal: apply buffer pool exhausted");
+            }
+            pi_chain(ch, p.roots1, sb, 1.0 / q, 1.0, w, -1.0 / q, sb, out, last ? vout : chain,
+                     {w, v0, sb});
+            w = out;
+            i += 2;
+        }
+    }
+}
+
+}  // namespace ppa

@@ -1,0 +1,185 @@
+// Internal declarations of libppa (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ppa.h"
+
+namespace ppa {
+
+using cplx = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define PPA_HIP(x) ::ppa::hip_check((x), #x, __FILE__, __LINE__)
+#define PPA_REQUIRE(cond, ...) \
+    do { if (!(cond)) ::ppa::fail(PPA_ERR_INVALID, __VA_ARGS__); } while (0)
+
+// ---------------------------------------------------------------- handles
+// SpMV row-block partition: each block holds at most SPMV_CHUNK nonzeros and
+// at most SPMV_MAXROWS rows, or exactly one row longer than SPMV_CHUNK.
+constexpr int SPMV_BS = 256;
+constexpr int SPMV_CHUNK = 2048;
+constexpr int SPMV_MAXROWS = 2048;
+// MI355X: 8 accelerator complex dies, workgroups dispatched round-robin.
+constexpr int NUM_XCD = 8;
+
+struct Matrix {
+    int64_t n = 0, nnz = 0;
+    const int32_t* rowptr = nullptr;
+    const int32_t* colind = nullptr;
+    const double* v64 = nullptr;
+    const float* v32 = nullptr;
+    float* v32_owned = nullptr;
+    int32_t* blk = nullptr;          // device, nblocks + 1 row starts
+    int64_t nblocks = 0;
+    double norm_inf = 0.0;
+    int device = 0;
+};
+
+struct Poly {
+    std::vector<cplx> roots;    // pi (single) or pi_2 (double), application order
+    std::vector<cplx> roots1;   // pi_1 (double polynomial), empty otherwise
+    bool is_double() const { return !roots1.empty(); }
+    int degree() const { return (int)roots.size(); }
+    int total_degree() const {
+        return is_double() ? (int)(roots.size() * roots1.size()) : (int)roots.size();
+    }
+};
+
+// ---------------------------------------------------------------- workspace
+// Carves 256-byte aligned sub-buffers out of one caller allocation.  With
+// base == nullptr it only measures (used by the *_workspace_bytes queries).
+struct Carver {
+    char* base;
+    size_t cap;
+    size_t off = 0;
+    Carver(void* b, size_t c) : base((char*)b), cap(c) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    void check() const {
+        if (base && off > cap)
+            fail(PPA_ERR_WORKSPACE, "workspace too small: need %zu bytes, got %zu", off, cap);
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Leading dimension of a block of n-vectors (256-byte aligned columns).
+inline int64_t col_ld(int64_t n) { return round_up(n, 32); }
+
+// ---------------------------------------------------------------- kernels
+enum class VecT { F64, F32 };
+
+// out = alpha x + beta (A u) + gamma z + delta z2   (x, z, z2 may be null)
+void launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
+                       double beta, const void* u, double gamma, const void* z, double delta,
+                       const void* z2, void* o, hipStream_t s);
+void matrix_setup(Matrix& A, hipStream_t s);   // validate, norm, partition
+void launch_cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void launch_cast_f32_f64(const float* in, double* out, int64_t n, hipStream_t s);
+
+// Gram-Schmidt kernels (blas.hip)
+struct Cgs2Ws {
+    double* partial = nullptr;   // (JMAX_ALL + 2) * nb
+    double* h1 = nullptr;        // JMAX_ALL
+    double* h2 = nullptr;        // JMAX_ALL
+    double* scal = nullptr;      // [0] = ||w_in||^2, [1] = ||w_out||^2, [2] = 1/beta
+    double* t = nullptr;         // n
+    int nb = 0;
+};
+constexpr int CGS_JMAX_ALL = 256;
+int cgs_blocks(int64_t n);
+void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws);
+// Orthogonalise w against V[:, 0:j] (CGS2).  Writes the unnormalised result to
+// w_out (may equal w), the Hessenberg column (j+1 entries: h, beta) to
+// Hcol_d (device), and 1/beta (0 on breakdown) to ws.scal[2].  If v_next is
+// non-null it receives w_out * (1/beta).
+void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* w_out,
+                 double* Hcol_d, double* v_next, double breakdown_tol, Cgs2Ws& ws,
+                 hipStream_t s);
+
+// C = V Q  (V n x kin, Q device kin x kout col-major ld kin) -- MFMA FP64
+void launch_gemm_tall(int64_t n, int kin, int kout, const double* V, int64_t ldv,
+                      const double* Q_d, double* C, int64_t ldc, hipStream_t s);
+
+// Several dot products <a_i, b_i> of n-vectors, deterministic.
+constexpr int MAX_DOTS = 64;
+struct DotList {
+    const double* a[MAX_DOTS];
+    const double* b[MAX_DOTS];
+    int count;
+};
+void launch_dots(int64_t n, const DotList& L, double* partial, int nb, double* out_d,
+                 hipStream_t s);
+// Norms^2 of linear combinations sum_t c_t v_t (up to 3 terms each).
+constexpr int MAX_COMBOS = 32;
+struct ComboList {
+    const double* v[MAX_COMBOS][3];
+    double c[MAX_COMBOS][3];
+    int count;
+};
+void launch_combo_norms(int64_t n, const ComboList& L, double* partial, int nb, double* out_d,
+                        hipStream_t s);
+void launch_copy_cols_complex(int64_t n, const double* Y, int64_t ldy, const int* colmap_re,
+                              const int* colmap_im, const double* scale, int ncols,
+                              double* X, hipStream_t s);
+void launch_zero(double* p, int64_t count, hipStream_t s);
+
+// ---------------------------------------------------------------- host LA
+// Real nonsymmetric eigenproblem of a small dense matrix (column-major).
+// Eigenvalues: conjugate pairs adjacent, Im > 0 first.  Vectors optional.
+void dense_eig(int n, const double* a, std::vector<cplx>& w, std::vector<cplx>* V);
+// Eigenvalues of an upper Hessenberg matrix (column-major), no vectors.
+void hessenberg_eigvals(int n, std::vector<double>& h, std::vector<cplx>& w);
+// Solve M x = b by Gaussian elimination with partial pivoting (column-major).
+bool lu_solve(int n, std::vector<double> M, std::vector<double>& b);
+// Orthonormal basis of the columns of B (m x k, column-major), Householder QR.
+void orthonormal_basis(int m, int k, const std::vector<double>& B, std::vector<double>& Q);
+
+// ---------------------------------------------------------------- method
+std::vector<cplx> harmonic_ritz(int d, const std::vector<double>& Hbar /*(d+1) x d col-major*/);
+std::vector<cplx> leja_order(const std::vector<cplx>& theta);
+// Apply pi(A) (or pi_2(tau(A))) to v: FP64 or FP32 chain.
+struct ApplyWs {
+    void* buf[6] = {};   // n-vectors of the chain's element type
+};
+int apply_buffers(const Poly& p);
+void carve_apply(Carver& c, int64_t n, const Poly& p, VecT t, ApplyWs& ws);
+// in/out types: vin/vout select the element type of v and y; the chain runs in
+// `chain` precision (F32 chain = FP32 matrix values).
+void apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vout, void* y,
+                VecT chain, ApplyWs& ws, hipStream_t s);
+// y = c * pi(A) v + gamma z for a single root list, all FP64 (the operator
+// tau(A) = I - pi_1(A) of section 8 is c = -1, gamma = 1, z = v).
+void apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
+                           double* y, double c, double gamma, const double* z, ApplyWs& ws,
+                           hipStream_t s);
+// polynomial construction and Arnoldi drivers (eigs.cpp)
+size_t poly_build_ws(int64_t n, int d, bool dbl);
+int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
+               hipStream_t s, Poly& out);
+size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o);
+int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v0, void* ws,
+         size_t ws_bytes, hipStream_t s, ppa_eigs_result& r);
+
+}  // namespace ppa

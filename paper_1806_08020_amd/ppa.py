@@ -1,0 +1,353 @@
+"""Thin ctypes binding of libppa.so (C ABI in include/ppa.h).
+
+Argument marshalling only: every step of the method runs in the library (HIP
+kernels on the device, small projected problems on the host in C++).  PyTorch
+supplies device memory and the current stream.  There is no fallback: if the
+built library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch  # loads torch's HIP runtime first, so libppa binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppa.so")
+
+PPA_OK = 0
+PPA_WARN_DEGREE_REDUCED = 1
+PPA_WARN_NOT_CONVERGED = 2
+PPA_WARN_BREAKDOWN = 3
+PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
+_PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
+
+vp = C.c_void_p
+
+
+class EigsOpts(C.Structure):
+    _fields_ = [("m", C.c_int), ("k", C.c_int), ("nev", C.c_int), ("max_cycles", C.c_int),
+                ("rtol", C.c_double), ("anorm", C.c_double), ("precision", C.c_int),
+                ("flags", C.c_int)]
+
+
+class EigsResult(C.Structure):
+    _fields_ = [("lam_re", C.POINTER(C.c_double)), ("lam_im", C.POINTER(C.c_double)),
+                ("resid", C.POINTER(C.c_double)), ("ritz_re", C.POINTER(C.c_double)),
+                ("ritz_im", C.POINTER(C.c_double)), ("X_d", vp),
+                ("nconv", C.c_int), ("cycles", C.c_int), ("mvps", C.c_int64),
+                ("dots", C.c_int64), ("vops", C.c_int64), ("max_resid", C.c_double),
+                ("fp32_cycles", C.c_int), ("reserved", C.c_int),
+                ("spmv_passes", C.c_int64), ("t_apply_ms", C.c_double), ("t_cgs_ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    i, i64, d, sz = C.c_int, C.c_int64, C.c_double, C.c_size_t
+    P = C.POINTER
+    sig = {
+        "ppa_abi_version": (i, []),
+        "ppa_last_error": (C.c_char_p, []),
+        "ppa_matrix_create": (i, [i64, vp, vp, vp, vp, i, vp, P(vp)]),
+        "ppa_matrix_destroy": (i, [vp]),
+        "ppa_matrix_info": (i, [vp, P(i64), P(i64), P(d), P(i64)]),
+        "ppa_poly_from_roots": (i, [i, P(d), P(d), i, P(d), P(d), P(vp)]),
+        "ppa_poly_destroy": (i, [vp]),
+        "ppa_poly_degree": (i, [vp, P(i), P(i)]),
+        "ppa_poly_roots": (i, [vp, i, P(d), P(d), i, P(i)]),
+        "ppa_poly_build_workspace_bytes": (i, [vp, i, i, P(sz)]),
+        "ppa_poly_build": (i, [vp, i, vp, vp, sz, vp, P(vp)]),
+        "ppa_poly_build_double": (i, [vp, i, i, vp, vp, sz, vp, P(vp)]),
+        "ppa_poly_apply_workspace_bytes": (i, [vp, vp, i, P(sz)]),
+        "ppa_poly_apply": (i, [vp, vp, i, vp, vp, vp, sz, vp]),
+        "ppa_fused_spmv": (i, [vp, i, i, d, vp, d, vp, d, vp, d, vp, vp, vp]),
+        "ppa_cgs2_workspace_bytes": (i, [i64, i, P(sz)]),
+        "ppa_cgs2": (i, [i64, i, vp, i64, vp, P(d), P(d), vp, sz, vp]),
+        "ppa_gemm_workspace_bytes": (i, [i, i, P(sz)]),
+        "ppa_gemm_tall": (i, [i64, i, i, vp, i64, P(d), vp, i64, vp, sz, vp]),
+        "ppa_eigs_workspace_bytes": (i, [vp, vp, P(EigsOpts), P(sz)]),
+        "ppa_eigs": (i, [vp, vp, P(EigsOpts), vp, vp, sz, vp, P(EigsResult)]),
+        "ppa_dense_eig": (i, [i, P(d), P(d), P(d), P(d), P(d)]),
+        "ppa_leja_order": (i, [i, P(d), P(d)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class PPAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libppa status {status}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st < 0:
+        raise PPAError(st, _lib.ppa_last_error().decode())
+    return st
+
+
+def _stream():
+    return vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return vp(t.data_ptr()) if t is not None else None
+
+
+def _dptr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _workspace(nbytes):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+def abi_version() -> int:
+    return _lib.ppa_abi_version()
+
+
+# ---------------------------------------------------------------- matrix
+class Matrix:
+    """Device CSR matrix handle.  ``csr`` is a workloads.CSR (host arrays);
+    the device copies are owned by this object and borrowed by the handle."""
+
+    def __init__(self, csr, want_f32: bool = False):
+        dev = torch.device("cuda")
+        self.n = int(csr.n)
+        self.rowptr = torch.as_tensor(np.asarray(csr.rowptr, dtype=np.int32)).to(dev)
+        self.colind = torch.as_tensor(np.asarray(csr.colind, dtype=np.int32)).to(dev)
+        self.vals = torch.as_tensor(np.asarray(csr.vals, dtype=np.float64)).to(dev)
+        if self.colind.numel() == 0:      # keep valid pointers for empty matrices
+            self.colind = torch.zeros(1, dtype=torch.int32, device=dev)
+            self.vals = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.vals32 = self.vals.float() if want_f32 else None
+        h = vp()
+        _check(_lib.ppa_matrix_create(self.n, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.vals),
+                                      _ptr(self.vals32), 0, _stream(), C.byref(h)))
+        self.h = h
+        n, nnz, nrm, nb = C.c_int64(), C.c_int64(), C.c_double(), C.c_int64()
+        _check(_lib.ppa_matrix_info(self.h, C.byref(n), C.byref(nnz), C.byref(nrm), C.byref(nb)))
+        self.nnz, self.norm_inf, self.nblocks = nnz.value, nrm.value, nb.value
+
+    @property
+    def has_f32(self):
+        return self.vals32 is not None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _lib.ppa_matrix_destroy(h)
+            self.h = None
+
+
+# ---------------------------------------------------------------- polynomial
+class Poly:
+    def __init__(self, h, status=PPA_OK):
+        self.h = h
+        self.status = status
+        deg, d1 = C.c_int(), C.c_int()
+        _check(_lib.ppa_poly_degree(h, C.byref(deg), C.byref(d1)))
+        self.degree, self.d1 = deg.value, d1.value
+
+    @classmethod
+    def from_roots(cls, roots, roots1=None):
+        r = np.asarray(roots, dtype=complex)
+        re, pre = _dptr(r.real)
+        im, pim = _dptr(r.imag)
+        if roots1 is not None:
+            r1 = np.asarray(roots1, dtype=complex)
+            re1, pre1 = _dptr(r1.real)
+            im1, pim1 = _dptr(r1.imag)
+            d1 = r1.size
+        else:
+            pre1 = pim1 = None
+            d1 = 0
+        h = vp()
+        _check(_lib.ppa_poly_from_roots(r.size, pre, pim, d1, pre1, pim1, C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def build(cls, A: Matrix, d: int, b: torch.Tensor):
+        nb = C.c_size_t()
+        _check(_lib.ppa_poly_build_workspace_bytes(A.h, d, 0, C.byref(nb)))
+        ws = _workspace(nb.value)
+        h = vp()
+        st = _check(_lib.ppa_poly_build(A.h, d, _ptr(b), _ptr(ws), ws.numel(), _stream(), C.byref(h)))
+        return cls(h, st)
+
+    @classmethod
+    def build_double(cls, A: Matrix, d1: int, d2: int, b: torch.Tensor):
+        nb = C.c_size_t()
+        _check(_lib.ppa_poly_build_workspace_bytes(A.h, max(d1, d2), 1, C.byref(nb)))
+        ws = _workspace(nb.value)
+        h = vp()
+        st = _check(_lib.ppa_poly_build_double(A.h, d1, d2, _ptr(b), _ptr(ws), ws.numel(), _stream(),
+                                               C.byref(h)))
+        return cls(h, st)
+
+    def roots(self, level: int = 2) -> np.ndarray:
+        cnt = self.degree if level == 2 else self.d1
+        re = np.zeros(max(cnt, 1))
+        im = np.zeros(max(cnt, 1))
+        c = C.c_int()
+        _check(_lib.ppa_poly_roots(self.h, level, re.ctypes.data_as(C.POINTER(C.c_double)),
+                                   im.ctypes.data_as(C.POINTER(C.c_double)), re.size, C.byref(c)))
+        return (re + 1j * im)[: c.value]
+
+    @property
+    def is_double(self):
+        return self.d1 > 0
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _lib.ppa_poly_destroy(h)
+            self.h = None
+
+
+def apply(A: Matrix, p: Poly, v: torch.Tensor, precision: str = "f64", out=None, ws=None):
+    """y = pi(A) v on the device (FP64 or FP32 vectors)."""
+    prec = _PREC[precision]
+    dt = torch.float64 if prec == PPA_F64 else torch.float32
+    if v.dtype != dt or not v.is_cuda or v.numel() != A.n:
+        raise ValueError("v must be a contiguous device vector of length n and matching dtype")
+    y = torch.empty_like(v) if out is None else out
+    if ws is None:
+        ws = apply_workspace(A, p, precision)
+    _check(_lib.ppa_poly_apply(A.h, p.h, prec, _ptr(v), _ptr(y), _ptr(ws), ws.numel(), _stream()))
+    return y
+
+
+def apply_workspace(A: Matrix, p: Poly, precision: str = "f64"):
+    nb = C.c_size_t()
+    _check(_lib.ppa_poly_apply_workspace_bytes(A.h, p.h, _PREC[precision], C.byref(nb)))
+    return _workspace(nb.value)
+
+
+def fused_spmv(A: Matrix, alpha, x, beta, u, gamma=0.0, z=None, delta=0.0, z2=None, out=None,
+               out_dtype=None):
+    """out = alpha x + beta (A u) + gamma z + delta z2 (one fused pass)."""
+    in_f32 = u.dtype == torch.float32
+    odt = out_dtype or u.dtype
+    o = torch.empty(A.n, dtype=odt, device=u.device) if out is None else out
+    _check(_lib.ppa_fused_spmv(A.h, int(in_f32), int(o.dtype == torch.float32), alpha, _ptr(x), beta,
+                               _ptr(u), gamma, _ptr(z), delta, _ptr(z2), _ptr(o), _stream()))
+    return o
+
+
+def cgs2(V: torch.Tensor, j: int, w: torch.Tensor):
+    """Orthogonalise w (in place) against the first j columns of V, given as
+    a (ncols, ld) device tensor (row c = column c).  Returns (h[0..j], ||w_in||)."""
+    n = w.numel()
+    ld = V.shape[1]
+    nb = C.c_size_t()
+    _check(_lib.ppa_cgs2_workspace_bytes(n, j, C.byref(nb)))
+    ws = _workspace(nb.value)
+    h = np.zeros(j + 1)
+    w0 = C.c_double()
+    _check(_lib.ppa_cgs2(n, j, _ptr(V), ld, _ptr(w), h.ctypes.data_as(C.POINTER(C.c_double)),
+                         C.byref(w0), _ptr(ws), ws.numel(), _stream()))
+    return h, w0.value
+
+
+def gemm_tall(V: torch.Tensor, Q: np.ndarray, n: int) -> torch.Tensor:
+    """C = V[:, :kin] Q with V given as (kin, ld) device tensor (row c = column c
+    of the column-major block); returns C as (kout, n)."""
+    Q = np.asfortranarray(Q, dtype=np.float64)
+    kin, kout = Q.shape
+    ld = V.shape[1]
+    C_ = torch.empty((kout, n), dtype=torch.float64, device="cuda")
+    nb = C.c_size_t()
+    _check(_lib.ppa_gemm_workspace_bytes(kin, kout, C.byref(nb)))
+    ws = _workspace(nb.value)
+    qf = np.ascontiguousarray(Q.T).ravel()   # column-major kin x kout
+    _check(_lib.ppa_gemm_tall(n, kin, kout, _ptr(V), ld, qf.ctypes.data_as(C.POINTER(C.c_double)),
+                              _ptr(C_), n, _ptr(ws), ws.numel(), _stream()))
+    torch.cuda.current_stream().synchronize()
+    return C_
+
+
+@dataclass
+class EigsOut:
+    status: int
+    mu: np.ndarray
+    resid: np.ndarray
+    nu: np.ndarray
+    nconv: int
+    cycles: int
+    mvps: int
+    dots: int
+    vops: int
+    max_resid: float
+    fp32_cycles: int
+    spmv_passes: int = 0
+    t_apply_ms: float = 0.0
+    t_cgs_ms: float = 0.0
+    X: torch.Tensor | None = None
+    converged: bool = field(default=False)
+
+
+def eigs_workspace(A: Matrix, p: Poly | None, m, k, nev, precision="f64"):
+    o = EigsOpts(m, k, nev, 1, 1e-8, 0.0, _PREC[precision], 0)
+    nb = C.c_size_t()
+    _check(_lib.ppa_eigs_workspace_bytes(A.h, p.h if p else None, C.byref(o), C.byref(nb)))
+    return _workspace(nb.value)
+
+
+def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, rtol: float = 1e-8,
+         max_cycles: int = 100, precision: str = "f64", anorm: float = 0.0,
+         want_vectors: bool = False, ws=None, timing: bool = False) -> EigsOut:
+    """Thick-restarted Arnoldi(m,k) on pi(A) for nev eigenpairs of A."""
+    o = EigsOpts(m, k, nev, max_cycles, rtol, anorm, _PREC[precision], 1 if timing else 0)
+    if ws is None:
+        nb = C.c_size_t()
+        _check(_lib.ppa_eigs_workspace_bytes(A.h, p.h if p else None, C.byref(o), C.byref(nb)))
+        ws = _workspace(nb.value)
+    lre, lim, res, nre, nim = (np.zeros(nev) for _ in range(5))
+    X = torch.empty((nev, A.n), dtype=torch.complex128, device="cuda") if want_vectors else None
+    r = EigsResult()
+    P = C.POINTER(C.c_double)
+    r.lam_re, r.lam_im, r.resid = lre.ctypes.data_as(P), lim.ctypes.data_as(P), res.ctypes.data_as(P)
+    r.ritz_re, r.ritz_im = nre.ctypes.data_as(P), nim.ctypes.data_as(P)
+    r.X_d = X.data_ptr() if X is not None else None
+    st = _check(_lib.ppa_eigs(A.h, p.h if p else None, C.byref(o), _ptr(v0), _ptr(ws), ws.numel(),
+                              _stream(), C.byref(r)))
+    return EigsOut(status=st, mu=lre + 1j * lim, resid=res.copy(), nu=nre + 1j * nim, nconv=r.nconv,
+                   cycles=r.cycles, mvps=r.mvps, dots=r.dots, vops=r.vops, max_resid=r.max_resid,
+                   fp32_cycles=r.fp32_cycles, spmv_passes=r.spmv_passes, t_apply_ms=r.t_apply_ms,
+                   t_cgs_ms=r.t_cgs_ms, X=X, converged=(st == PPA_OK))
+
+
+# ---------------------------------------------------------------- host helpers
+def dense_eig(a: np.ndarray, vectors: bool = True):
+    a = np.asfortranarray(a, dtype=np.float64)
+    n = a.shape[0]
+    wr, wi = np.zeros(n), np.zeros(n)
+    vr = np.zeros((n, n), order="F") if vectors else None
+    vi = np.zeros((n, n), order="F") if vectors else None
+    P = C.POINTER(C.c_double)
+    _check(_lib.ppa_dense_eig(n, a.ctypes.data_as(P), wr.ctypes.data_as(P), wi.ctypes.data_as(P),
+                              vr.ctypes.data_as(P) if vectors else None,
+                              vi.ctypes.data_as(P) if vectors else None))
+    w = wr + 1j * wi
+    return (w, vr + 1j * vi) if vectors else w
+
+
+def leja_order(roots) -> np.ndarray:
+    r = np.asarray(roots, dtype=complex)
+    re = np.ascontiguousarray(r.real.copy())
+    im = np.ascontiguousarray(r.imag.copy())
+    P = C.POINTER(C.c_double)
+    _check(_lib.ppa_leja_order(r.size, re.ctypes.data_as(P), im.ctypes.data_as(P)))
+    return re + 1j * im

@@ -1,0 +1,386 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Marked gpu; run on an MI355X."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1806_08020_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.asarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_chain(mv, roots, v):
+    """Oracle pi(A) v factor by factor; also the largest intermediate |w|."""
+    w = np.array(v, dtype=float)
+    g = np.abs(w).max()
+    i = 0
+    while i < len(roots):
+        step = 2 if roots[i].imag != 0 else 1
+        w = O.apply_poly(mv, roots[i:i + step], w)
+        g = max(g, np.abs(w).max())
+        i += step
+    return w, g
+
+
+def chain_tol(csr, roots, growth, eps):
+    """First-order rounding bound of the factored product: each factor adds at
+    most (nnzr + 3) eps (1 + ||A||/|theta|) |w|, d factors."""
+    nnzr = max(1.0, csr.nnz / csr.n)
+    amp = 1.0 + O.infnorm(csr) / np.min(np.abs(roots))
+    return (nnzr + 3) * len(roots) * eps * growth * amp
+
+
+def matrices():
+    rng = np.random.default_rng(0)
+    out = {
+        "lap_7x9": W.laplacian_2d(7, 9),
+        "lap_50": W.laplacian_2d(50),
+        "cd2_37": W.convdiff_2d(37, 0.5),
+        "cd3_13": W.convdiff_3d(13, 0.3),
+        "band_9000": W.random_banded(9000, 27, 700, seed=4),
+        "diag_5000": W.diag_csr(np.linspace(0.1, 9.0, 5000)),
+        "n1": W.diag_csr(np.array([2.5])),
+    }
+    # empty rows and a row longer than one LDS chunk (2048 nonzeros)
+    n = 6000
+    A = np.zeros((n, n))
+    A[np.arange(n), np.arange(n)] = 3.0
+    A[7, :] = rng.standard_normal(n)
+    A[1234, :] = 0.0
+    A[4000, ::2] = 1.0
+    A[5999, :] = 0.0
+    out["long_rows"] = W.dense_csr(A)
+    return out
+
+
+MATS = matrices()
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_fused_spmv_fp64(lib, name):
+    csr = MATS[name]
+    A = lib.Matrix(csr)
+    rng = np.random.default_rng(1)
+    u, x, z, z2 = (rng.standard_normal(csr.n) for _ in range(4))
+    S = csr.to_scipy()
+    y = lib.fused_spmv(A, 0.7, dev(x), -1.3, dev(u), 0.25, dev(z), -2.0, dev(z2))
+    ref = 0.7 * x - 1.3 * (S @ u) + 0.25 * z - 2.0 * z2
+    scale = np.abs(x) + 1.3 * (abs(S) @ np.abs(u)) + np.abs(z) + 2 * np.abs(z2)
+    nnzr = max(1, int(np.diff(csr.rowptr).max()))
+    assert np.all(np.abs(host(y) - ref) <= (nnzr + 4) * EPS64 * scale + 1e-300)
+    # pure SpMV (alpha = 0, no x)
+    y2 = lib.fused_spmv(A, 0.0, None, 1.0, dev(u))
+    assert np.all(np.abs(host(y2) - S @ u) <= (nnzr + 1) * EPS64 * (abs(S) @ np.abs(u)) + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["lap_50", "cd3_13", "band_9000", "long_rows"])
+def test_fused_spmv_fp32(lib, name):
+    csr = MATS[name]
+    A = lib.Matrix(csr, want_f32=True)
+    rng = np.random.default_rng(2)
+    u, x = rng.standard_normal(csr.n), rng.standard_normal(csr.n)
+    S = csr.to_scipy()
+    ref = x - 0.4 * (S @ u)
+    scale = np.abs(x) + 0.4 * (abs(S) @ np.abs(u))
+    nnzr = max(1, int(np.diff(csr.rowptr).max()))
+    for in_t, out_t in [(torch.float32, torch.float32), (torch.float64, torch.float32),
+                        (torch.float32, torch.float64)]:
+        y = lib.fused_spmv(A, 1.0, dev(x, in_t), -0.4, dev(u, in_t), out_dtype=out_t)
+        assert y.dtype == out_t
+        assert np.all(np.abs(host(y).astype(float) - ref) <= (nnzr + 6) * 2 * EPS32 * scale + 1e-30)
+
+
+def test_fused_spmv_rejects_aliasing(lib):
+    A = lib.Matrix(MATS["lap_7x9"])
+    u = dev(np.ones(63))
+    with pytest.raises(lib.PPAError):
+        lib.fused_spmv(A, 1.0, u, 1.0, u, out=u)
+
+
+def test_malformed_csr_rejected(lib):
+    csr = W.laplacian_2d(6)
+    bad = W.CSR(csr.n, csr.rowptr.copy(), csr.colind.copy(), csr.vals.copy())
+    bad.colind[5] = bad.colind[4]           # repeated / unsorted index
+    with pytest.raises(lib.PPAError):
+        lib.Matrix(bad)
+    bad2 = W.CSR(csr.n, csr.rowptr.copy(), csr.colind.copy(), csr.vals.copy())
+    bad2.colind[0] = csr.n                  # out of range
+    with pytest.raises(lib.PPAError):
+        lib.Matrix(bad2)
+
+
+# ---------------------------------------------------------------- pi(A) v
+APPLY_CASES = [("lap_50", 10, 1), ("cd2_37", 15, 2), ("cd3_13", 12, 3), ("band_9000", 20, 4)]
+
+
+@pytest.mark.parametrize("name,d,seed", APPLY_CASES)
+def test_apply_fp64_same_roots(lib, name, d, seed):
+    """pi(A) v with the oracle's roots fed to both sides."""
+    csr = MATS[name]
+    mv = O.csr_matvec(csr)
+    b, v = W.start_vectors(csr.n, seed)
+    roots, _ = O.gmres_poly(mv, b, d)
+    A = lib.Matrix(csr)
+    P = lib.Poly.from_roots(roots)
+    y = host(lib.apply(A, P, dev(v)))
+    ref, g = oracle_chain(mv, roots, v)
+    assert np.max(np.abs(y - ref)) <= chain_tol(csr, roots, g, EPS64)
+
+
+@pytest.mark.parametrize("name,d,seed", APPLY_CASES)
+def test_apply_fp32(lib, name, d, seed):
+    csr = MATS[name]
+    mv = O.csr_matvec(csr)
+    b, v = W.start_vectors(csr.n, seed)
+    roots, _ = O.gmres_poly(mv, b, d)
+    A = lib.Matrix(csr, want_f32=True)
+    P = lib.Poly.from_roots(roots)
+    y = host(lib.apply(A, P, dev(v, torch.float32), precision="f32")).astype(float)
+    ref, g = oracle_chain(mv, roots, v)
+    assert np.max(np.abs(y - ref)) <= 2 * chain_tol(csr, roots, g, EPS32)
+
+
+def test_apply_complex_pairs(lib):
+    """Roots with conjugate pairs (nonsymmetric A): pair passes in real
+    arithmetic against the oracle."""
+    csr = W.convdiff_2d(30, 1.6)
+    mv = O.csr_matvec(csr)
+    b, v = W.start_vectors(csr.n, 5)
+    roots, _ = O.gmres_poly(mv, b, 14)
+    assert np.any(roots.imag != 0)
+    A = lib.Matrix(csr)
+    P = lib.Poly.from_roots(roots)
+    y = host(lib.apply(A, P, dev(v)))
+    ref, g = oracle_chain(mv, roots, v)
+    assert np.max(np.abs(y - ref)) <= chain_tol(csr, roots, g, EPS64)
+
+
+def test_apply_double_poly(lib):
+    csr = MATS["cd2_37"]
+    mv = O.csr_matvec(csr)
+    b, v = W.start_vectors(csr.n, 6)
+    r1, r2 = O.double_poly(mv, b, 4, 5)
+    A = lib.Matrix(csr, want_f32=True)
+    P = lib.Poly.from_roots(r2, roots1=r1)
+    assert P.is_double and P.degree == 5 and P.d1 == 4
+    y = host(lib.apply(A, P, dev(v)))
+    ref = O.apply_double(mv, r1, r2, v)
+    tau = lambda x: O.tau_apply(mv, r1, x)
+    _, g = oracle_chain(tau, r2, v)
+    tol = chain_tol(csr, r1, g, EPS64) * len(r2) * 4
+    assert np.max(np.abs(y - ref)) <= tol
+    y32 = host(lib.apply(A, P, dev(v, torch.float32), precision="f32")).astype(float)
+    assert np.max(np.abs(y32 - ref)) <= tol * (EPS32 / EPS64) * 2
+
+
+# ---------------------------------------------------------------- CGS2, GEMM
+@pytest.mark.parametrize("n,j", [(1000, 1), (5003, 7), (20000, 30), (4097, 64), (3000, 100)])
+def test_cgs2_vs_oracle(lib, n, j):
+    rng = np.random.default_rng(n + j)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, j)))
+    w = rng.standard_normal(n) + Q @ rng.standard_normal(j) * 3
+    ld = ((n + 31) // 32) * 32
+    Vd = torch.zeros((j, ld), dtype=torch.float64, device="cuda")
+    Vd[:, :n] = dev(Q.T)
+    wd = dev(w)
+    h, w0 = lib.cgs2(Vd, j, wd)
+    hr, wr, br = O.cgs2(Q, w)
+    assert np.allclose(h[:j], hr, rtol=0, atol=1e-12 * np.linalg.norm(w))
+    assert abs(h[j] - br) <= 1e-12 * np.linalg.norm(w)
+    assert np.max(np.abs(host(wd) - wr)) <= 1e-12 * np.linalg.norm(w)
+    assert abs(w0 - np.linalg.norm(w)) <= 1e-12 * np.linalg.norm(w)
+
+
+@pytest.mark.parametrize("n,kin,kout", [(1, 1, 1), (37, 5, 3), (1000, 61, 26), (12345, 41, 21),
+                                        (4096, 65, 64), (999, 128, 17)])
+def test_gemm_tall_mfma(lib, n, kin, kout):
+    """V Q on FP64 MFMA against a plain product (checks the MFMA lane layout)."""
+    rng = np.random.default_rng(kin * 100 + kout)
+    V = rng.standard_normal((n, kin))
+    Q = rng.standard_normal((kin, kout))
+    ld = ((n + 31) // 32) * 32
+    Vd = torch.zeros((kin, ld), dtype=torch.float64, device="cuda")
+    Vd[:, :n] = dev(V.T)
+    C = host(lib.gemm_tall(Vd, Q, n)).T
+    ref = V @ Q
+    assert np.max(np.abs(C - ref)) <= (kin + 2) * EPS64 * (np.abs(V) @ np.abs(Q)).max()
+
+
+# ---------------------------------------------------------------- polynomial build
+def roots_match(a, b, tol):
+    pool = list(b)
+    for z in a:
+        k = int(np.argmin(np.abs(np.array(pool) - z)))
+        assert abs(pool[k] - z) <= tol * max(1.0, abs(z)), (z, pool[k])
+        pool.pop(k)
+
+
+def leja_valid(r):
+    """Each placed root (Im >= 0 representative) maximises sum log|z - c| among
+    the remaining ones, up to rounding; conjugates adjacent."""
+    r = np.asarray(r)
+    i = 0
+    while i < len(r):
+        if r[i].imag != 0:
+            assert r[i].imag > 0 and r[i + 1] == np.conj(r[i])
+            i += 2
+        else:
+            i += 1
+    assert abs(r[0]) >= np.abs(r).max() * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("name,d,seed", [("lap_50", 10, 1), ("cd2_37", 12, 2), ("band_9000", 16, 4)])
+def test_poly_build_vs_oracle(lib, name, d, seed):
+    csr = MATS[name]
+    b, _ = W.start_vectors(csr.n, seed)
+    ref, de = O.gmres_poly(O.csr_matvec(csr), b, d)
+    A = lib.Matrix(csr)
+    P = lib.Poly.build(A, d, dev(b))
+    got = P.roots()
+    assert P.degree == de == d
+    roots_match(got, ref, 1e-9)
+    leja_valid(got)
+
+
+def test_poly_build_complex_and_breakdown(lib):
+    csr = W.convdiff_2d(30, 1.6)
+    b, _ = W.start_vectors(csr.n, 5)
+    ref, _ = O.gmres_poly(O.csr_matvec(csr), b, 14)
+    A = lib.Matrix(csr)
+    got = lib.Poly.build(A, 14, dev(b)).roots()
+    roots_match(got, ref, 1e-8)
+    leja_valid(got)
+    # b spans a 3-dimensional invariant subspace: degree reduced to 3
+    D = W.diag_csr(np.arange(1.0, 41.0))
+    bb = np.zeros(40); bb[:3] = 1.0
+    P = lib.Poly.build(lib.Matrix(D), 6, dev(bb))
+    assert P.status == lib.PPA_WARN_DEGREE_REDUCED and P.degree == 3
+    assert np.allclose(np.sort(P.roots().real), [1, 2, 3], atol=1e-10)
+
+
+def test_poly_build_double_vs_oracle(lib):
+    csr = MATS["cd2_37"]
+    b, _ = W.start_vectors(csr.n, 7)
+    r1, r2 = O.double_poly(O.csr_matvec(csr), b, 4, 6)
+    P = lib.Poly.build_double(lib.Matrix(csr), 4, 6, dev(b))
+    roots_match(P.roots(1), r1, 1e-9)
+    roots_match(P.roots(2), r2, 1e-7)
+
+
+# ---------------------------------------------------------------- eigs
+def lap_closed(nx, ny):
+    i = np.arange(1, nx + 1)[:, None]
+    j = np.arange(1, ny + 1)[None, :]
+    return np.sort((4 - 2 * np.cos(i * np.pi / (nx + 1)) - 2 * np.cos(j * np.pi / (ny + 1))).ravel())
+
+
+def test_eigs_config1_laplacian(lib):
+    """50x50 Laplacian, d=10, Arnoldi(30,15), nev=10, rtol 1e-8 (the small
+    configuration): each GPU eigenvalue is a closed-form eigenvalue, the
+    distinct values agree with the oracle to 1e-10 relative, and the counters
+    match the oracle's."""
+    csr = W.laplacian_2d(50)
+    b, v0 = W.start_vectors(csr.n, 1)
+    ores, oroots = O.pp_eigs(csr, b, v0, m=30, k=15, nev=10, d=10, rtol=1e-8, max_cycles=100)
+    A = lib.Matrix(csr)
+    P = lib.Poly.build(A, 10, dev(b))
+    r = lib.eigs(A, P, dev(v0), m=30, k=15, nev=10, rtol=1e-8, max_cycles=100, want_vectors=True)
+    assert r.converged and r.nconv == 10
+    assert np.all(r.resid <= 1e-8 * A.norm_inf)
+    lam = lap_closed(50, 50)
+    for mu in r.mu:
+        assert abs(mu.imag) < 1e-12
+        assert np.min(np.abs(lam - mu.real)) <= 1e-10 * abs(mu.real)
+    gd = np.unique(np.round(r.mu.real, 9))
+    od = np.unique(np.round(ores.mu.real, 9))
+    assert np.array_equal(gd, od)
+    if r.cycles == ores.cycles:
+        assert (r.mvps, r.dots, r.vops) == (ores.counters.mvps - 10, ores.counters.dots - sum(
+            2 * j + 1 for j in range(1, 11)), ores.counters.vops - sum(4 * j + 2 for j in range(1, 11)))
+    # eigenvectors returned on the device: unit norm, A x = mu x
+    X = host(r.X).T
+    S = csr.to_scipy()
+    for t in range(10):
+        x = X[:, t]
+        assert abs(np.linalg.norm(x) - 1) < 1e-12
+        assert np.linalg.norm(S @ x - r.mu[t] * x) <= 1e-8 * A.norm_inf * 1.01
+
+
+def test_eigs_distinct_spectrum_strict(lib):
+    csr = W.laplacian_2d(50, 51)
+    b, v0 = W.start_vectors(csr.n, 11)
+    ores, _ = O.pp_eigs(csr, b, v0, m=30, k=15, nev=10, d=10, rtol=1e-8, max_cycles=100)
+    A = lib.Matrix(csr)
+    r = lib.eigs(A, lib.Poly.build(A, 10, dev(b)), dev(v0), 30, 15, 10, rtol=1e-8)
+    assert r.converged
+    assert np.allclose(r.mu.real, ores.mu.real, rtol=1e-10, atol=0)
+    assert np.allclose(r.mu.real, lap_closed(50, 51)[:10], rtol=1e-10, atol=0)
+    assert r.cycles == ores.cycles
+
+
+def test_eigs_nonsymmetric_complex(lib):
+    """Dense-brute-force case with a complex pair among the wanted values."""
+    rng = np.random.default_rng(1)
+    n = 300
+    lam = np.concatenate([rng.uniform(0.5, 10.0, n - 6), [0.11, 0.2, 0.27, 0.35]])
+    X = np.eye(n) + 0.3 * rng.standard_normal((n, n)) / np.sqrt(n)
+    D = np.diag(np.concatenate([lam[: n - 2], [0.0, 0.0]]))
+    D[n - 2:, n - 2:] = [[0.3, 0.15], [-0.15, 0.3]]
+    Ad = X @ D @ np.linalg.inv(X)
+    csr = W.dense_csr(Ad, drop_zeros=False)
+    b, v0 = W.start_vectors(n, 1)
+    ores, _ = O.pp_eigs(csr, b, v0, m=30, k=12, nev=6, d=6, rtol=1e-10, max_cycles=100)
+    A = lib.Matrix(csr)
+    r = lib.eigs(A, lib.Poly.build(A, 6, dev(b)), dev(v0), 30, 12, 6, rtol=1e-10)
+    assert r.converged
+    ev = np.linalg.eigvals(Ad)
+    ev = ev[np.lexsort((ev.imag, ev.real, np.abs(ev)))][:6]
+    assert np.allclose(np.sort_complex(r.mu), np.sort_complex(ev), rtol=1e-8, atol=1e-10)
+    assert np.allclose(np.sort_complex(r.mu), np.sort_complex(ores.mu), rtol=1e-9, atol=1e-11)
+
+
+def test_eigs_standard_arnoldi(lib):
+    csr = W.laplacian_2d(20, 21)
+    b, v0 = W.start_vectors(csr.n, 12)
+    ores, _ = O.pp_eigs(csr, b, v0, m=40, k=15, nev=5, d=0, rtol=1e-8, max_cycles=400)
+    A = lib.Matrix(csr)
+    r = lib.eigs(A, None, dev(v0), 40, 15, 5, rtol=1e-8, max_cycles=400)
+    assert r.converged == ores.converged
+    assert np.allclose(r.mu.real, lap_closed(20, 21)[:5], rtol=1e-9)
+
+
+def test_eigs_double_poly(lib):
+    csr = W.laplacian_2d(30, 31)
+    b, v0 = W.start_vectors(csr.n, 9)
+    ores, _ = O.pp_eigs(csr, b, v0, m=20, k=10, nev=6, d1=4, d2=5, rtol=1e-8, max_cycles=60)
+    A = lib.Matrix(csr)
+    P = lib.Poly.build_double(A, 4, 5, dev(b))
+    r = lib.eigs(A, P, dev(v0), 20, 10, 6, rtol=1e-8, max_cycles=60)
+    assert r.converged and ores.converged
+    assert np.allclose(r.mu.real, ores.mu.real, rtol=1e-10)
+
+
+def test_eigs_mixed_precision(lib):
+    """pi(A)v in FP32, the rest FP64, closing FP64 cycles: every pair meets
+    rtol and matches the FP64 oracle."""
+    csr = W.convdiff_3d(14, 0.3)
+    b, v0 = W.start_vectors(csr.n, 3)
+    ores, _ = O.pp_eigs(csr, b, v0, m=30, k=12, nev=6, d=10, rtol=1e-8, max_cycles=200)
+    A = lib.Matrix(csr, want_f32=True)
+    P = lib.Poly.build(A, 10, dev(b))
+    r = lib.eigs(A, P, dev(v0), 30, 12, 6, rtol=1e-8, max_cycles=200, precision="mixed")
+    assert r.converged and r.nconv == 6
+    assert np.all(r.resid <= 1e-8 * A.norm_inf)
+    assert r.fp32_cycles >= 1
+    assert np.allclose(np.sort(r.mu.real), np.sort(ores.mu.real), rtol=1e-7)
