@@ -79,6 +79,26 @@ def cpu_baseline(csr, roots, bytes_per_apply, budget_s):
     return reps, dt, bytes_per_apply * reps / dt / 1e9
 
 
+def copy_probe(torch, reps):
+    """A plain device-to-device copy of 2^30 bytes, `reps` times: the HBM
+    traffic counters of this known-size kernel calibrate the counters read for
+    the SpMV kernel (1 GiB read + 1 GiB written per dispatch)."""
+    n = 2 ** 27
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_probe_bytes_per_dispatch": 2 * 8 * n, "avg_ms": round(ms, 4),
+                      "GBps": round(2 * 8 * n / ms / 1e6, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,12 +108,17 @@ def main():
     ap.add_argument("--max-cycles", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 1 GiB device copy instead (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        copy_probe(torch, args.steps)
+        return
     from paper_1806_08020_amd import ppa
     from paper_1806_08020_amd import workloads as W
 

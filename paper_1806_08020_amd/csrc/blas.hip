@@ -51,96 +51,104 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NC], int count,
 struct RowRange {
     int64_t beg, end;
 };
+// contiguous row range of block blockIdx.x when n rows are split over nb blocks
 __device__ __forceinline__ RowRange rows_of_block(int64_t n, int nb) {
     const int64_t per = (n + nb - 1) / nb;
     const int64_t beg = (int64_t)blockIdx.x * per;
     return {beg, min(n, beg + per)};
 }
 
-// partial[(c0 + c) * nb + b] = sum_r V[c0 + c][r] w[r]; optional ||w||^2 at
-// column `normcol`.
-template <int TJ>
+// Row mapping of the streaming kernels: block b owns rows
+// [b * BS * RPT, (b + 1) * BS * RPT); thread t handles rows base + t + i * BS.
+// Rows past n are clamped to n - 1 for loads (always in bounds) and carry a
+// zero weight, so every load can be issued unconditionally.
+#ifndef PPA_CGS_RPT
+#define PPA_CGS_RPT 8
+#endif
+#ifndef PPA_CGS_CT
+#define PPA_CGS_CT 8
+#endif
+constexpr int RPT = PPA_CGS_RPT;   // rows per thread
+constexpr int CT = PPA_CGS_CT;     // column tile of the projection
+
+// partial[c * nb + b] = sum over the block's rows of V[c][r] w[r] (c < j),
+// and partial[j * nb + b] = sum w[r]^2 when with_norm.
 __global__ __launch_bounds__(BS) void k_proj(const double* __restrict__ V, int64_t ldv, int64_t n,
                                              int j, const double* __restrict__ w,
-                                             double* __restrict__ partial, int nb, int normcol) {
-    __shared__ double red[NW * (TJ + 1)];
-    const int c0 = blockIdx.y * TJ;
-    const int nc = min(TJ, j - c0);
-    const bool wn = normcol >= 0 && blockIdx.y == 0;
-    double acc[TJ + 1];
+                                             double* __restrict__ partial, int nb, int with_norm) {
+    __shared__ double red[NW * CT];
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + threadIdx.x;
+    double wr[RPT];
+    int64_t rr[RPT];
 #pragma unroll
-    for (int c = 0; c <= TJ; ++c) acc[c] = 0.0;
-    const RowRange rr = rows_of_block(n, nb);
-    for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
-        const double wr = w[r];
-#pragma unroll
-        for (int c = 0; c < TJ; ++c)
-            if (c < nc) acc[c] += V[(int64_t)(c0 + c) * ldv + r] * wr;
-        acc[TJ] += wr * wr;
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t r = base + (int64_t)i * BS;
+        rr[i] = r < n ? r : n - 1;
+        wr[i] = r < n ? w[rr[i]] : 0.0;
     }
-    block_reduce_store<TJ + 1>(acc, nc, red, partial + (int64_t)c0 * nb + blockIdx.x, nb);
-    if (wn) {
+    if (with_norm) {
+        double a[1] = {0.0};
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) a[0] += wr[i] * wr[i];
+        block_reduce_store<1>(a, 1, red, partial + (int64_t)j * nb + blockIdx.x, nb);
         __syncthreads();
-        double tmp[1] = {acc[TJ]};
-        block_reduce_store<1>(tmp, 1, red, partial + (int64_t)normcol * nb + blockIdx.x, nb);
+    }
+    for (int c0 = 0; c0 < j; c0 += CT) {
+        double acc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, j - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) acc[c] += col[rr[i]] * wr[i];
+        }
+        block_reduce_store<CT>(acc, min(CT, j - c0), red, partial + (int64_t)c0 * nb + blockIdx.x, nb);
+        __syncthreads();
     }
 }
 
-// t = w - V h (h of length j, device), then partial = V^T t.  j <= JMAX.
-template <int JMAX>
-__global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V, int64_t ldv,
-                                                    int64_t n, int j, const double* __restrict__ h,
-                                                    const double* __restrict__ w,
-                                                    double* __restrict__ t,
-                                                    double* __restrict__ partial, int nb) {
-    __shared__ double hs[JMAX];
-    __shared__ double red[NW * JMAX];
-    for (int c = threadIdx.x; c < j; c += BS) hs[c] = h[c];
-    __syncthreads();
-    double acc[JMAX];
-#pragma unroll
-    for (int c = 0; c < JMAX; ++c) acc[c] = 0.0;
-    const RowRange rr = rows_of_block(n, nb);
-    for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
-        double tv = w[r];
-#pragma unroll
-        for (int c = 0; c < JMAX; ++c)
-            if (c < j) tv -= V[(int64_t)c * ldv + r] * hs[c];
-        t[r] = tv;
-#pragma unroll
-        for (int c = 0; c < JMAX; ++c)
-            if (c < j) acc[c] += V[(int64_t)c * ldv + r] * tv;
-    }
-    block_reduce_store<JMAX>(acc, j, red, partial + blockIdx.x, nb);
-}
-
-// out = t - V h (any j); partial[0 * nb + b] = ||out||^2 over the block's rows
-// when partial is non-null.
+// out = t - V h (h of length j, device); partial[b] = ||out||^2 over the
+// block's rows when partial is non-null.  out may equal t.
 __global__ __launch_bounds__(BS) void k_update(const double* __restrict__ V, int64_t ldv, int64_t n,
                                                int j, const double* __restrict__ h,
-                                               const double* __restrict__ t,
-                                               double* __restrict__ out,
+                                               const double* t, double* out,
                                                double* __restrict__ partial, int nb) {
-    __shared__ double hs[CGS_JMAX_ALL];
+    __shared__ double hs[CGS_JMAX_ALL + 8];
     __shared__ double red[NW];
-    for (int c = threadIdx.x; c < j; c += BS) hs[c] = h[c];
+    for (int c = threadIdx.x; c < CGS_JMAX_ALL + 8; c += BS) hs[c] = c < j ? h[c] : 0.0;
     __syncthreads();
-    double nrm = 0.0;
-    const RowRange rr = rows_of_block(n, nb);
-    for (int64_t r = rr.beg + threadIdx.x; r < rr.end; r += BS) {
-        double tv = t[r];
-        int c = 0;
-        for (; c + 4 <= j; c += 4) {
-            const double a0 = V[(int64_t)c * ldv + r], a1 = V[(int64_t)(c + 1) * ldv + r];
-            const double a2 = V[(int64_t)(c + 2) * ldv + r], a3 = V[(int64_t)(c + 3) * ldv + r];
-            tv -= a0 * hs[c];
-            tv -= a1 * hs[c + 1];
-            tv -= a2 * hs[c + 2];
-            tv -= a3 * hs[c + 3];
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + threadIdx.x;
+    double tv[RPT];
+    int64_t rr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t r = base + (int64_t)i * BS;
+        rr[i] = r < n ? r : n - 1;
+        tv[i] = t[rr[i]];
+    }
+    for (int c0 = 0; c0 < j; c0 += 8) {
+        double v[8][RPT];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, j - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) v[c][i] = col[rr[i]];
         }
-        for (; c < j; ++c) tv -= V[(int64_t)c * ldv + r] * hs[c];
-        out[r] = tv;
-        nrm += tv * tv;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double hc = hs[c0 + c];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) tv[i] -= v[c][i] * hc;
+        }
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        if (base + (int64_t)i * BS < n) {
+            out[rr[i]] = tv[i];
+            nrm += tv[i] * tv[i];
+        }
     }
     if (partial) {
         double acc[1] = {nrm};
@@ -192,8 +200,10 @@ __global__ void k_scale(const double* __restrict__ in, double* __restrict__ out,
 }  // namespace
 
 int cgs_blocks(int64_t n) {
-    const int64_t nb = (n + BS * 8 - 1) / (BS * 8);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 1024));
+    // one block per BS * RPT rows; the partial sums are reduced in a second kernel
+    const int64_t nb = (n + BS * RPT - 1) / (BS * RPT);
+    PPA_REQUIRE(nb <= (int64_t(1) << 24), "vector too long for the Gram-Schmidt kernels");
+    return (int)std::max<int64_t>(1, nb);
 }
 
 void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws) {
@@ -209,20 +219,15 @@ static unsigned sgrid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
 }
 
-template <int TJ>
 static void proj(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* partial,
-                 int nb, int normcol, hipStream_t s) {
-    const int tiles = std::max(1, (j + TJ - 1) / TJ);
-    hipLaunchKernelGGL((k_proj<TJ>), dim3(nb, tiles), dim3(BS), 0, s, V, ldv, n, j, w, partial, nb,
-                       normcol);
+                 int nb, int with_norm, hipStream_t s) {
+    hipLaunchKernelGGL(k_proj, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, w, partial, nb, with_norm);
     PPA_HIP(hipGetLastError());
 }
 
-template <int JMAX>
-static void update_proj(int64_t n, int j, const double* V, int64_t ldv, const double* h,
-                        const double* w, double* t, double* partial, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_update_proj<JMAX>), dim3(nb), dim3(BS), 0, s, V, ldv, n, j, h, w, t,
-                       partial, nb);
+static void update(int64_t n, int j, const double* V, int64_t ldv, const double* h, const double* t,
+                   double* out, double* partial, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, h, t, out, partial, nb);
     PPA_HIP(hipGetLastError());
 }
 
@@ -236,29 +241,15 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
                  hipStream_t s) {
     PPA_REQUIRE(j >= 1 && j <= CGS_JMAX_ALL - 1, "cgs2: basis size %d out of range", j);
     const int nb = ws.nb;
-    // pass 1: h1 = V^T w and ||w||^2
-    proj<32>(n, j, V, ldv, w, ws.partial, nb, j, s);
+    // pass 1: h1 = V^T w and ||w_in||^2
+    proj(n, j, V, ldv, w, ws.partial, nb, 1, s);
     reduce_cols(ws.partial, nb, j + 1, ws.h1, s);   // h1[0..j-1], h1[j] = ||w_in||^2
-    // pass 2: t = w - V h1, h2 = V^T t
-    if (j <= 8)
-        update_proj<8>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
-    else if (j <= 16)
-        update_proj<16>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
-    else if (j <= 32)
-        update_proj<32>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
-    else if (j <= 64)
-        update_proj<64>(n, j, V, ldv, ws.h1, w, ws.t, ws.partial, nb, s);
-    else {
-        hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, ws.h1, w, ws.t,
-                           (double*)nullptr, nb);
-        PPA_HIP(hipGetLastError());
-        proj<32>(n, j, V, ldv, ws.t, ws.partial, nb, -1, s);
-    }
+    // reorthogonalisation: t = w - V h1, h2 = V^T t
+    update(n, j, V, ldv, ws.h1, w, ws.t, nullptr, nb, s);
+    proj(n, j, V, ldv, ws.t, ws.partial, nb, 0, s);
     reduce_cols(ws.partial, nb, j, ws.h2, s);
-    // pass 3: w_out = t - V h2 and ||w_out||^2
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, ws.h2, ws.t, w_out,
-                       ws.partial, nb);
-    PPA_HIP(hipGetLastError());
+    // w_out = t - V h2 and ||w_out||^2
+    update(n, j, V, ldv, ws.h2, ws.t, w_out, ws.partial, nb, s);
     reduce_cols(ws.partial, nb, 1, ws.scal + 1, s);
     hipLaunchKernelGGL(k_cgs_finalize, dim3(1), dim3(256), 0, s, ws.h1, ws.h2, j, ws.scal, Hcol_d,
                        breakdown_tol);

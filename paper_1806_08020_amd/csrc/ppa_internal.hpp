@@ -31,9 +31,15 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 // ---------------------------------------------------------------- handles
 // SpMV row-block partition: each block holds at most SPMV_CHUNK nonzeros and
 // at most SPMV_MAXROWS rows, or exactly one row longer than SPMV_CHUNK.
-constexpr int SPMV_BS = 256;
-constexpr int SPMV_CHUNK = 2048;
-constexpr int SPMV_MAXROWS = 2048;
+#ifndef PPA_SPMV_BS
+#define PPA_SPMV_BS 256
+#endif
+#ifndef PPA_SPMV_CHUNK
+#define PPA_SPMV_CHUNK 2048
+#endif
+constexpr int SPMV_BS = PPA_SPMV_BS;
+constexpr int SPMV_CHUNK = PPA_SPMV_CHUNK;
+constexpr int SPMV_MAXROWS = PPA_SPMV_CHUNK;
 // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin.
 constexpr int NUM_XCD = 8;
 
