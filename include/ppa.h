@@ -69,22 +69,34 @@ const char* ppa_last_error(void);
  * colind_d    int32[nnz], column indices in [0, n), strictly increasing in a row
  * val64_d     double[nnz] values (required)
  * val32_d     float[nnz] values for the FP32 / mixed paths, or NULL.  When NULL
- *             and `want_f32` is nonzero, the library converts val64_d into an
- *             internal FP32 copy it owns.
- * stream      stream used for validation; the call synchronises it.
+ *             and flags has PPA_MATRIX_F32, the library converts val64_d into
+ *             an internal FP32 copy it owns.
+ * flags       PPA_MATRIX_* bits.
+ * stream      stream used for validation and tuning; the call synchronises it.
  * out         receives the handle.
  *
  * Validates the CSR structure on the device (PPA_ERR_INVALID if malformed),
- * computes ||A||_inf, and builds the row-block partition used by the SpMV
- * kernels (allocated by the library, freed by ppa_matrix_destroy).
+ * computes ||A||_inf, and builds the row-block partitions used by the SpMV
+ * kernels (allocated by the library, freed by ppa_matrix_destroy).  For large
+ * matrices (n >= 200000, nnz >= 10^6) whose row blocks touch narrow column
+ * ranges it also times the LDS-windowed SpMV against the plain one and keeps
+ * the faster; both sum each row in column order, so they agree bitwise on
+ * every row of at most 2048 nonzeros (longer rows are tree-reduced by the
+ * plain kernel and agree to rounding).
  * ------------------------------------------------------------------------ */
+#define PPA_MATRIX_F32 1            /* build an FP32 copy of the values           */
+#define PPA_MATRIX_WINDOW_FORCE 2   /* use the windowed SpMV whenever it fits     */
+#define PPA_MATRIX_WINDOW_OFF 4     /* never use the windowed SpMV                */
 int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
-                      const double* val64_d, const float* val32_d, int want_f32,
+                      const double* val64_d, const float* val32_d, int flags,
                       void* stream, ppa_matrix** out);
 int ppa_matrix_destroy(ppa_matrix* A);
 /* n, nnz, ||A||_inf (largest absolute row sum) and the number of row blocks. */
 int ppa_matrix_info(const ppa_matrix* A, int64_t* n, int64_t* nnz, double* norm_inf,
                     int64_t* nblocks);
+/* SpMV variant in use for FP64 (precision PPA_F64) or FP32 (PPA_F32) values:
+ * *windowed = 1 for the LDS-windowed kernel, 0 for the plain one. */
+int ppa_matrix_spmv_variant(const ppa_matrix* A, int precision, int* windowed);
 
 /* ------------------------------------------------------------------------
  * Polynomial pi in factored form, eq. (2.1): pi(z) = prod_i (1 - z/theta_i),

@@ -52,7 +52,7 @@ int ppa_abi_version(void) { return PPA_ABI_VERSION; }
 const char* ppa_last_error(void) { return g_err.c_str(); }
 
 int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
-                      const double* val64_d, const float* val32_d, int want_f32, void* stream,
+                      const double* val64_d, const float* val32_d, int flags, void* stream,
                       ppa_matrix** out) {
     return guarded([&] {
         PPA_REQUIRE(out != nullptr, "out is NULL");
@@ -69,15 +69,18 @@ int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_
             A->v32 = val32_d;
             PPA_HIP(hipGetDevice(&A->device));
             matrix_setup(*A, s);
-            if (!A->v32 && want_f32 && A->nnz > 0) {
+            if (!A->v32 && (flags & PPA_MATRIX_F32) && A->nnz > 0) {
                 PPA_HIP(hipMalloc(&A->v32_owned, A->nnz * sizeof(float)));
                 launch_cast_f64_f32(A->v64, A->v32_owned, A->nnz, s);
                 PPA_HIP(hipStreamSynchronize(s));
                 A->v32 = A->v32_owned;
             }
+            const int wmode = (flags & PPA_MATRIX_WINDOW_OFF) ? -1 : (flags & PPA_MATRIX_WINDOW_FORCE) ? 1 : 0;
+            matrix_tune(*A, wmode, s);
+            A->rp_host.clear();
+            A->rp_host.shrink_to_fit();
         } catch (...) {
-            if (A->blk) (void)hipFree(A->blk);
-            if (A->v32_owned) (void)hipFree(A->v32_owned);
+            matrix_release(*A);
             delete A;
             throw;
         }
@@ -90,8 +93,7 @@ int ppa_matrix_destroy(ppa_matrix* h) {
     return guarded([&] {
         if (!h) return PPA_OK;
         Matrix* A = reinterpret_cast<Matrix*>(h);
-        if (A->blk) PPA_HIP(hipFree(A->blk));
-        if (A->v32_owned) PPA_HIP(hipFree(A->v32_owned));
+        matrix_release(*A);
         delete A;
         return PPA_OK;
     });
@@ -106,6 +108,15 @@ int ppa_matrix_info(const ppa_matrix* h, int64_t* n, int64_t* nnz, double* norm_
         if (nnz) *nnz = A->nnz;
         if (norm_inf) *norm_inf = A->norm_inf;
         if (nblocks) *nblocks = A->nblocks;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_spmv_variant(const ppa_matrix* h, int precision, int* windowed) {
+    return guarded([&] {
+        PPA_REQUIRE(h && windowed, "matrix and windowed are required");
+        const Matrix* A = reinterpret_cast<const Matrix*>(h);
+        *windowed = precision == PPA_F64 ? (A->win64.on ? 1 : 0) : (A->win32.on ? 1 : 0);
         return PPA_OK;
     });
 }

@@ -43,6 +43,22 @@ constexpr int SPMV_MAXROWS = PPA_SPMV_CHUNK;
 // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin.
 constexpr int NUM_XCD = 8;
 
+// Windowed SpMV (matrices whose row blocks touch a narrow column range, e.g.
+// band matrices with scattered columns): a block stages u[cmin .. cmax] of its
+// rows in LDS and gathers from there.
+constexpr int SPMV_WBS = 512;              // threads per windowed block
+constexpr int SPMV_WCHUNK_F32 = 8192;      // nonzeros per windowed block, FP32 values
+constexpr int SPMV_WCHUNK_F64 = 4096;      // nonzeros per windowed block, FP64 values
+
+struct Window {
+    bool on = false;                 // selected for this value type
+    int32_t* blk = nullptr;          // device, nblocks + 1 row starts
+    int32_t* meta = nullptr;         // device, per block: cmin, span
+    int64_t nblocks = 0;
+    int span_max = 0;
+    size_t lds_bytes = 0;
+};
+
 struct Matrix {
     int64_t n = 0, nnz = 0;
     const int32_t* rowptr = nullptr;
@@ -54,6 +70,8 @@ struct Matrix {
     int64_t nblocks = 0;
     double norm_inf = 0.0;
     int device = 0;
+    Window win64, win32;
+    std::vector<int32_t> rp_host;    // host copy of rowptr (setup only)
 };
 
 struct Poly {
@@ -101,6 +119,11 @@ void launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const v
                        double beta, const void* u, double gamma, const void* z, double delta,
                        const void* z2, void* o, hipStream_t s);
 void matrix_setup(Matrix& A, hipStream_t s);   // validate, norm, partition
+// Choose between the plain and the windowed SpMV for each available value
+// type: mode 0 times both on a scratch vector (large matrices only), mode 1
+// forces the windowed kernel whenever it fits, mode -1 keeps the plain one.
+void matrix_tune(Matrix& A, int mode, hipStream_t s);
+void matrix_release(Matrix& A);
 void launch_cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
 void launch_cast_f32_f64(const float* in, double* out, int64_t n, hipStream_t s);
 

@@ -12,12 +12,19 @@
 //    with unit-stride, non-temporal loads, multiplies by the gathered u and
 //    stages the products in LDS, then each thread sums whole rows from LDS and
 //    applies the axpy epilogue -- every global access but the gather of u is
-//    coalesced;
+//    coalesced.  The row pointers and streamed vectors of a thread's first
+//    rows are loaded before the LDS barrier so their latency overlaps the
+//    product phase;
 //  * a row with more than SPMV_CHUNK nonzeros gets a block of its own that
 //    reduces it across the block;
 //  * block ids are remapped so that each of the 8 XCDs walks one contiguous
 //    range of rows: neighbouring row blocks share gathered u lines in the same
 //    XCD's L2;
+//  * windowed variant: when every row block of a (larger) partition touches a
+//    column range that fits in LDS, the block first copies u[cmin..cmax] into
+//    LDS with coalesced loads and gathers from LDS.  For band matrices with
+//    scattered columns this replaces one L2 line transfer per nonzero by a
+//    streaming copy of the window;
 //  * the row sum is accumulated in the value precision (FP64, or FP32 for the
 //    FP32 / mixed path), in column order, so results are deterministic.
 #include "ppa_internal.hpp"
@@ -38,6 +45,34 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Epilogue values of one row, loaded ahead of the product phase.
+template <typename VT>
+struct RowPre {
+    int a, e;
+    VT x, z, z2;
+};
+
+template <typename VT, typename IT>
+__device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr, int r, int p0,
+                                              const IT* __restrict__ x, const IT* __restrict__ z,
+                                              const IT* __restrict__ z2) {
+    RowPre<VT> q;
+    q.a = rowptr[r] - p0;
+    q.e = rowptr[r + 1] - p0;
+    q.x = x ? (VT)x[r] : (VT)0;
+    q.z = z ? (VT)z[r] : (VT)0;
+    q.z2 = z2 ? (VT)z2[r] : (VT)0;
+    return q;
+}
+
+template <typename VT, typename OT>
+__device__ __forceinline__ void row_out(const RowPre<VT>& q, const VT* prod, int r, OT* out,
+                                        VT alpha, VT beta, VT gamma, VT delta) {
+    VT s = 0;
+    for (int k = q.a; k < q.e; ++k) s += prod[k];
+    out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
 }
 
 template <typename VT, typename IT, typename OT>
@@ -65,21 +100,22 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
                 v[k] = __builtin_nontemporal_load(val + p0 + i);
             }
         }
+        // the thread's first two rows: epilogue operands ahead of the barrier
+        const int ra = r0 + tid, rb = r0 + tid + SPMV_BS;
+        RowPre<VT> qa, qb;
+        if (ra < r1) qa = row_pre<VT>(rowptr, ra, p0, x, z, z2);
+        if (rb < r1) qb = row_pre<VT>(rowptr, rb, p0, x, z, z2);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + k * SPMV_BS;
             if (i < cnt) prod[i] = v[k] * (VT)u[c[k]];
         }
         __syncthreads();
-        for (int r = r0 + tid; r < r1; r += SPMV_BS) {
-            const int a = rowptr[r] - p0, e = rowptr[r + 1] - p0;
-            VT s = 0;
-            for (int q = a; q < e; ++q) s += prod[q];
-            VT o = beta * s;
-            if (x) o += alpha * (VT)x[r];
-            if (z) o += gamma * (VT)z[r];
-            if (z2) o += delta * (VT)z2[r];
-            out[r] = (OT)o;
+        if (ra < r1) row_out(qa, prod, ra, out, alpha, beta, gamma, delta);
+        if (rb < r1) row_out(qb, prod, rb, out, alpha, beta, gamma, delta);
+        for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
+            const RowPre<VT> q = row_pre<VT>(rowptr, r, p0, x, z, z2);
+            row_out(q, prod, r, out, alpha, beta, gamma, delta);
         }
     } else {
         // one long row: r1 == r0 + 1
@@ -91,24 +127,76 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
         if (tid == 0) {
             VT t = 0;
             for (int w = 0; w < SPMV_BS / 64; ++w) t += red[w];
-            VT o = beta * t;
-            if (x) o += alpha * (VT)x[r0];
-            if (z) o += gamma * (VT)z[r0];
-            if (z2) o += delta * (VT)z2[r0];
-            out[r0] = (OT)o;
+            const RowPre<VT> q = row_pre<VT>(rowptr, r0, p0, x, z, z2);
+            out[r0] = (OT)(beta * t + alpha * q.x + gamma * q.z + delta * q.z2);
         }
     }
 }
 
+// Windowed variant: block b covers rows [blk[b], blk[b+1]) whose columns lie
+// in [meta[2b], meta[2b] + meta[2b+1]); dynamic LDS holds CH products and
+// the window.  The partition guarantees at most CH nonzeros per block.
+template <typename VT, typename IT, typename OT, int CH>
+__global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const VT* __restrict__ val, const int32_t* __restrict__ blk, const int32_t* __restrict__ meta,
+    int nblk, const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
+    const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    VT* prod = reinterpret_cast<VT*>(smem);
+    VT* win = prod + CH;
+    const int b = xcd_remap(blockIdx.x, nblk);
+    const int r0 = blk[b], r1 = blk[b + 1];
+    const int p0 = rowptr[r0], p1 = rowptr[r1];
+    const int cnt = p1 - p0;
+    const int cmin = meta[2 * b], span = meta[2 * b + 1];
+    const int tid = threadIdx.x;
+    constexpr int PER = CH / SPMV_WBS;
+    int32_t c[PER];
+    VT v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = tid + k * SPMV_WBS;
+        if (i < cnt) {
+            c[k] = __builtin_nontemporal_load(colind + p0 + i);
+            v[k] = __builtin_nontemporal_load(val + p0 + i);
+        }
+    }
+    for (int i = tid; i < span; i += SPMV_WBS) win[i] = (VT)u[cmin + i];
+    const int ra = r0 + tid;
+    RowPre<VT> qa;
+    if (ra < r1) qa = row_pre<VT>(rowptr, ra, p0, x, z, z2);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = tid + k * SPMV_WBS;
+        if (i < cnt) prod[i] = v[k] * win[c[k] - cmin];
+    }
+    __syncthreads();
+    if (ra < r1) row_out(qa, prod, ra, out, alpha, beta, gamma, delta);
+    for (int r = ra + SPMV_WBS; r < r1; r += SPMV_WBS) {
+        const RowPre<VT> q = row_pre<VT>(rowptr, r, p0, x, z, z2);
+        row_out(q, prod, r, out, alpha, beta, gamma, delta);
+    }
+}
+
 template <typename VT, typename IT, typename OT>
-static void run_fused(const Matrix& A, const VT* val, double alpha, const void* x, double beta,
-                      const void* u, double gamma, const void* z, double delta, const void* z2,
-                      void* o, hipStream_t s) {
+static void run_fused(const Matrix& A, const VT* val, const Window& W, double alpha, const void* x,
+                      double beta, const void* u, double gamma, const void* z, double delta,
+                      const void* z2, void* o, hipStream_t s) {
     if (A.nblocks == 0) return;
-    hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT>), dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0,
-                       s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks, (const IT*)x,
-                       (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta,
-                       (VT)gamma, (VT)delta);
+    if (W.on) {
+        constexpr int CH = sizeof(VT) == 4 ? SPMV_WCHUNK_F32 : SPMV_WCHUNK_F64;
+        hipLaunchKernelGGL((k_fused_spmv_win<VT, IT, OT, CH>), dim3((unsigned)W.nblocks),
+                           dim3(SPMV_WBS), W.lds_bytes, s, A.rowptr, A.colind, val, W.blk, W.meta,
+                           (int)W.nblocks, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2,
+                           (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+    } else {
+        hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT>), dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0,
+                           s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks, (const IT*)x,
+                           (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta,
+                           (VT)gamma, (VT)delta);
+    }
     PPA_HIP(hipGetLastError());
 }
 
@@ -118,18 +206,20 @@ void launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const v
     PPA_REQUIRE(u != nullptr && o != nullptr, "fused spmv: u and out are required");
     PPA_REQUIRE(o != u, "fused spmv: out must not alias u");
     if (in == VecT::F64 && out == VecT::F64) {
-        run_fused<double, double, double>(A, A.v64, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<double, double, double>(A, A.v64, A.win64, alpha, x, beta, u, gamma, z, delta, z2,
+                                          o, s);
         return;
     }
     PPA_REQUIRE(A.v32 != nullptr, "FP32 path needs FP32 matrix values (want_f32 at create)");
+    const Window& W = A.win32;
     if (in == VecT::F32 && out == VecT::F32)
-        run_fused<float, float, float>(A, A.v32, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, float, float>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else if (in == VecT::F64 && out == VecT::F32)
-        run_fused<float, double, float>(A, A.v32, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, double, float>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else if (in == VecT::F32 && out == VecT::F64)
-        run_fused<float, float, double>(A, A.v32, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, float, double>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else
-        run_fused<float, double, double>(A, A.v32, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, double, double>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
 }
 
 // ---------------------------------------------------------------- setup
@@ -174,6 +264,37 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ ro
     }
 }
 
+// Column range of each row block: meta[2b] = min column, meta[2b+1] = span.
+__global__ __launch_bounds__(256) void k_block_span(const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ colind,
+                                                    const int32_t* __restrict__ blk,
+                                                    int32_t* __restrict__ meta) {
+    __shared__ int smin[256], smax[256];
+    const int b = blockIdx.x;
+    const int p0 = rowptr[blk[b]], p1 = rowptr[blk[b + 1]];
+    int mn = 0x7fffffff, mx = -1;
+    for (int i = p0 + threadIdx.x; i < p1; i += 256) {
+        const int c = colind[i];
+        mn = min(mn, c);
+        mx = max(mx, c);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + w]);
+            smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool empty = smax[0] < 0;
+        meta[2 * b] = empty ? 0 : smin[0];
+        meta[2 * b + 1] = empty ? 0 : smax[0] - smin[0] + 1;
+    }
+}
+
 __global__ void k_cast_f64_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -183,6 +304,11 @@ __global__ void k_cast_f32_f64(const float* __restrict__ in, double* __restrict_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         out[i] = (double)in[i];
+}
+__global__ void k_fill_ramp(double* __restrict__ v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = 1.0 + (double)(i % 7) * 0.125;
 }
 
 static unsigned stream_grid(int64_t n) {
@@ -200,9 +326,94 @@ void launch_cast_f32_f64(const float* in, double* out, int64_t n, hipStream_t s)
     PPA_HIP(hipGetLastError());
 }
 
+// Greedy row-block partition: at most `chunk` nonzeros and `maxrows` rows per
+// block; a row longer than `chunk` forms a block of its own (returned via
+// *has_long).
+static std::vector<int32_t> partition(const std::vector<int32_t>& rp, int64_t n, int chunk,
+                                      int maxrows, bool* has_long) {
+    std::vector<int32_t> blk;
+    blk.reserve(n / 64 + 2);
+    blk.push_back(0);
+    int64_t r = 0;
+    bool lg = false;
+    while (r < n) {
+        const int64_t start = r, base = rp[r];
+        if (rp[r + 1] - base > chunk) {
+            ++r;
+            lg = true;
+        } else {
+            while (r < n && rp[r + 1] - base <= chunk && r - start < maxrows) ++r;
+        }
+        blk.push_back((int32_t)r);
+    }
+    if (has_long) *has_long = lg;
+    return blk;
+}
+
+// Allow the windowed kernels of one value type to use `bytes` of dynamic LDS.
+template <typename VT, int CH>
+static bool allow_lds(size_t bytes) {
+    const int b = (int)bytes;
+    bool ok = true;
+    if (sizeof(VT) == 8) {
+        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<double, double, double, CH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+    } else {
+        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, float, float, CH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, double, float, CH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, float, double, CH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, double, double, CH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+    }
+    (void)hipGetLastError();
+    return ok;
+}
+
+// Windowed partition for one value type: on success W holds device arrays and
+// the LDS size, but stays off until matrix_tune selects it.
+static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStream_t s) {
+    bool lg = false;
+    std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, &lg);
+    if (lg) return;
+    int maxlds = 0;
+    PPA_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, A.device));
+    const int64_t nb = (int64_t)blk.size() - 1;
+    int32_t* dblk = nullptr;
+    int32_t* dmeta = nullptr;
+    PPA_HIP(hipMalloc(&dblk, blk.size() * sizeof(int32_t)));
+    PPA_HIP(hipMalloc(&dmeta, 2 * nb * sizeof(int32_t)));
+    PPA_HIP(hipMemcpyAsync(dblk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_block_span, dim3((unsigned)nb), dim3(256), 0, s, A.rowptr, A.colind, dblk, dmeta);
+    PPA_HIP(hipGetLastError());
+    std::vector<int32_t> meta(2 * nb);
+    PPA_HIP(hipMemcpyAsync(meta.data(), dmeta, meta.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    int smax = 0;
+    for (int64_t b = 0; b < nb; ++b) smax = std::max(smax, meta[2 * b + 1]);
+    const size_t lds = (size_t)chunk * vbytes + (size_t)smax * vbytes;
+    bool ok = lds <= (size_t)maxlds && lds <= 96 * 1024;
+    if (ok)
+        ok = vbytes == 8 ? allow_lds<double, SPMV_WCHUNK_F64>(lds) : allow_lds<float, SPMV_WCHUNK_F32>(lds);
+    if (!ok) {
+        PPA_HIP(hipFree(dblk));
+        PPA_HIP(hipFree(dmeta));
+        return;
+    }
+    W.blk = dblk;
+    W.meta = dmeta;
+    W.nblocks = nb;
+    W.span_max = smax;
+    W.lds_bytes = lds;
+    W.on = false;
+}
+
 void matrix_setup(Matrix& A, hipStream_t s) {
     const int64_t n = A.n;
-    std::vector<int32_t> rp(n + 1);
+    std::vector<int32_t>& rp = A.rp_host;
+    rp.resize(n + 1);
     PPA_HIP(hipMemcpyAsync(rp.data(), A.rowptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PPA_HIP(hipStreamSynchronize(s));
     PPA_REQUIRE(rp[0] == 0, "rowptr[0] must be 0");
@@ -236,24 +447,88 @@ void matrix_setup(Matrix& A, hipStream_t s) {
                 "indices or non-finite values",
                 (long long)nbad);
     A.norm_inf = nrm;
-    // greedy row-block partition
-    std::vector<int32_t> blk;
-    blk.reserve(n / 64 + 2);
-    blk.push_back(0);
-    int64_t r = 0;
-    while (r < n) {
-        const int64_t start = r, base = rp[r];
-        if (rp[r + 1] - base > SPMV_CHUNK) {
-            ++r;
-        } else {
-            while (r < n && rp[r + 1] - base <= SPMV_CHUNK && r - start < SPMV_MAXROWS) ++r;
-        }
-        blk.push_back((int32_t)r);
-    }
+    std::vector<int32_t> blk = partition(rp, n, SPMV_CHUNK, SPMV_MAXROWS, nullptr);
     A.nblocks = (int64_t)blk.size() - 1;
     PPA_HIP(hipMalloc(&A.blk, blk.size() * sizeof(int32_t)));
     PPA_HIP(hipMemcpyAsync(A.blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     PPA_HIP(hipStreamSynchronize(s));
+}
+
+// Average time of `reps` passes u -> y with the current kernel choice.
+static float time_passes(const Matrix& A, bool f32, void* u, void* y, int reps, hipStream_t s) {
+    hipEvent_t e0, e1;
+    PPA_HIP(hipEventCreate(&e0));
+    PPA_HIP(hipEventCreate(&e1));
+    const VecT t = f32 ? VecT::F32 : VecT::F64;
+    launch_fused_spmv(A, t, t, 1.0, u, -0.5, u, 0.0, nullptr, 0.0, nullptr, y, s);
+    PPA_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i)
+        launch_fused_spmv(A, t, t, 1.0, u, -0.5, u, 0.0, nullptr, 0.0, nullptr, y, s);
+    PPA_HIP(hipEventRecord(e1, s));
+    PPA_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PPA_HIP(hipEventElapsedTime(&ms, e0, e1));
+    PPA_HIP(hipEventDestroy(e0));
+    PPA_HIP(hipEventDestroy(e1));
+    return ms / reps;
+}
+
+void matrix_tune(Matrix& A, int mode, hipStream_t s) {
+    // Only large matrices are timed: the windowed kernel pays off when gathers
+    // miss the cache, and the timing costs a few passes.
+    if (mode < 0 || A.nnz == 0) return;
+    if (mode == 0 && (A.n < 200000 || A.nnz < 1000000)) return;
+    build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
+    if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
+    if (!A.win64.blk && !A.win32.blk) return;
+    if (mode == 1) {
+        A.win64.on = A.win64.blk != nullptr;
+        A.win32.on = A.win32.blk != nullptr;
+        return;
+    }
+    double* u = nullptr;
+    double* y = nullptr;
+    // u: the FP64 test vector; y: output (FP64) or, for FP32, an FP32 copy of
+    // u followed by the FP32 output at a 64-element aligned offset
+    PPA_HIP(hipMalloc(&u, A.n * sizeof(double)));
+    PPA_HIP(hipMalloc(&y, (A.n + 128) * sizeof(double)));
+    hipLaunchKernelGGL(k_fill_ramp, dim3(stream_grid(A.n)), dim3(256), 0, s, u, A.n);
+    PPA_HIP(hipGetLastError());
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool f32 = pass == 1;
+        Window& W = f32 ? A.win32 : A.win64;
+        if (!W.blk) continue;
+        void* uu = u;
+        if (f32) launch_cast_f64_f32(u, (float*)y, A.n, s), uu = y;   // FP32 copy of the ramp
+        void* yy = f32 ? (void*)((float*)y + ((A.n + 63) & ~int64_t(63))) : (void*)y;
+        W.on = false;
+        const float t_plain = time_passes(A, f32, uu, yy, 4, s);
+        W.on = true;
+        float t_win = 0.f;
+        try {
+            t_win = time_passes(A, f32, uu, yy, 4, s);
+        } catch (const Error&) {
+            (void)hipGetLastError();
+            W.on = false;
+            continue;
+        }
+        W.on = t_win < 0.95f * t_plain;
+    }
+    PPA_HIP(hipStreamSynchronize(s));
+    PPA_HIP(hipFree(u));
+    PPA_HIP(hipFree(y));
+}
+
+void matrix_release(Matrix& A) {
+    if (A.blk) (void)hipFree(A.blk);
+    if (A.v32_owned) (void)hipFree(A.v32_owned);
+    for (Window* W : {&A.win64, &A.win32}) {
+        if (W->blk) (void)hipFree(W->blk);
+        if (W->meta) (void)hipFree(W->meta);
+        W->blk = W->meta = nullptr;
+    }
+    A.blk = nullptr;
+    A.v32_owned = nullptr;
 }
 
 }  // namespace ppa

@@ -22,6 +22,7 @@ PPA_WARN_DEGREE_REDUCED = 1
 PPA_WARN_NOT_CONVERGED = 2
 PPA_WARN_BREAKDOWN = 3
 PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
+PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF = 1, 2, 4
 _PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
 
 vp = C.c_void_p
@@ -55,6 +56,7 @@ def _load():
         "ppa_matrix_create": (i, [i64, vp, vp, vp, vp, i, vp, P(vp)]),
         "ppa_matrix_destroy": (i, [vp]),
         "ppa_matrix_info": (i, [vp, P(i64), P(i64), P(d), P(i64)]),
+        "ppa_matrix_spmv_variant": (i, [vp, i, P(i)]),
         "ppa_poly_from_roots": (i, [i, P(d), P(d), i, P(d), P(d), P(vp)]),
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
@@ -122,7 +124,9 @@ class Matrix:
     """Device CSR matrix handle.  ``csr`` is a workloads.CSR (host arrays);
     the device copies are owned by this object and borrowed by the handle."""
 
-    def __init__(self, csr, want_f32: bool = False):
+    def __init__(self, csr, want_f32: bool = False, window: str = "auto"):
+        """window: "auto" (time both SpMV variants on large matrices),
+        "force" (windowed whenever it fits) or "off"."""
         dev = torch.device("cuda")
         self.n = int(csr.n)
         self.rowptr = torch.as_tensor(np.asarray(csr.rowptr, dtype=np.int32)).to(dev)
@@ -133,8 +137,9 @@ class Matrix:
             self.vals = torch.zeros(1, dtype=torch.float64, device=dev)
         self.vals32 = self.vals.float() if want_f32 else None
         h = vp()
+        flags = {"auto": 0, "force": PPA_MATRIX_WINDOW_FORCE, "off": PPA_MATRIX_WINDOW_OFF}[window]
         _check(_lib.ppa_matrix_create(self.n, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.vals),
-                                      _ptr(self.vals32), 0, _stream(), C.byref(h)))
+                                      _ptr(self.vals32), flags, _stream(), C.byref(h)))
         self.h = h
         n, nnz, nrm, nb = C.c_int64(), C.c_int64(), C.c_double(), C.c_int64()
         _check(_lib.ppa_matrix_info(self.h, C.byref(n), C.byref(nnz), C.byref(nrm), C.byref(nb)))
@@ -143,6 +148,11 @@ class Matrix:
     @property
     def has_f32(self):
         return self.vals32 is not None
+
+    def windowed(self, precision: str = "f64") -> bool:
+        w = C.c_int()
+        _check(_lib.ppa_matrix_spmv_variant(self.h, _PREC[precision], C.byref(w)))
+        return bool(w.value)
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -384,3 +384,61 @@ def test_eigs_mixed_precision(lib):
     assert np.all(r.resid <= 1e-8 * A.norm_inf)
     assert r.fp32_cycles >= 1
     assert np.allclose(np.sort(r.mu.real), np.sort(ores.mu.real), rtol=1e-7)
+
+
+# ---------------------------------------------------------------- windowed SpMV
+@pytest.mark.parametrize("name", ["band_9000", "lap_50", "cd3_13", "diag_5000"])
+def test_windowed_spmv_bitwise_equal(lib, name):
+    """The LDS-windowed SpMV and the plain one sum in the same order: results
+    are bitwise identical, in FP64 and FP32, and match the CSR product."""
+    csr = MATS[name]
+    Aw = lib.Matrix(csr, want_f32=True, window="force")
+    Ap = lib.Matrix(csr, want_f32=True, window="off")
+    assert Aw.windowed("f64") and Aw.windowed("f32")
+    assert not Ap.windowed("f64") and not Ap.windowed("f32")
+    rng = np.random.default_rng(3)
+    u, x, z = (rng.standard_normal(csr.n) for _ in range(3))
+    for dt in (torch.float64, torch.float32):
+        yw = lib.fused_spmv(Aw, 0.5, dev(x, dt), -2.0, dev(u, dt), 1.5, dev(z, dt))
+        yp = lib.fused_spmv(Ap, 0.5, dev(x, dt), -2.0, dev(u, dt), 1.5, dev(z, dt))
+        assert torch.equal(yw, yp)
+    S = csr.to_scipy()
+    ref = 0.5 * x - 2.0 * (S @ u) + 1.5 * z
+    nnzr = max(1, int(np.diff(csr.rowptr).max()))
+    yw = host(lib.fused_spmv(Aw, 0.5, dev(x), -2.0, dev(u), 1.5, dev(z)))
+    scale = 0.5 * np.abs(x) + 2 * (abs(S) @ np.abs(u)) + 1.5 * np.abs(z)
+    assert np.all(np.abs(yw - ref) <= (nnzr + 4) * EPS64 * scale)
+
+
+def test_windowed_with_long_rows(lib):
+    """Rows longer than the FP64 windowed block (4096 nonzeros) disable the
+    FP64 window; the FP32 window (8192 nonzeros per block) still takes them.
+    The plain kernel reduces rows longer than 2048 nonzeros with a block-wide
+    tree, so those rows agree to rounding, all others bitwise."""
+    csr = MATS["long_rows"]
+    A = lib.Matrix(csr, want_f32=True, window="force")
+    Ap = lib.Matrix(csr, want_f32=True, window="off")
+    assert not A.windowed("f64") and A.windowed("f32")
+    rng = np.random.default_rng(4)
+    uh = rng.standard_normal(csr.n).astype(np.float32)
+    u = dev(uh, torch.float32)
+    yw = host(lib.fused_spmv(A, 0.0, None, 1.0, u))
+    yp = host(lib.fused_spmv(Ap, 0.0, None, 1.0, u))
+    lens = np.diff(csr.rowptr)
+    short = lens <= 2048
+    assert np.array_equal(yw[short], yp[short])
+    S = csr.to_scipy()
+    bound = lens * 2 * EPS32 * (abs(S) @ np.abs(uh.astype(float)))
+    assert np.all(np.abs(yw - yp) <= bound)
+
+
+def test_windowed_apply_matches_oracle(lib):
+    csr = MATS["band_9000"]
+    mv = O.csr_matvec(csr)
+    b, v = W.start_vectors(csr.n, 8)
+    roots, _ = O.gmres_poly(mv, b, 12)
+    A = lib.Matrix(csr, want_f32=True, window="force")
+    P = lib.Poly.from_roots(roots)
+    y = host(lib.apply(A, P, dev(v)))
+    ref, g = oracle_chain(mv, roots, v)
+    assert np.max(np.abs(y - ref)) <= chain_tol(csr, roots, g, EPS64)
