@@ -27,6 +27,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
+# HBM traffic of the fused SpMV kernel per launch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this benchmark, scaled by
+# the factors the same counters give for a plain 2 GiB device copy (FETCH_SIZE
+# reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config and
+# by the hash of the kernel source the counters were taken on: any change of
+# the kernel makes the entry stale and the field null.
+MEASURED_TRAFFIC = {
+    ("c2", "45c99c7879fab0d1"): {"fetch_kib": 37049.65, "write_kib": 7812.64, "fetch_factor": 2.0,
+                   "write_factor": 1.0},
+}
+
 CONFIGS = {
     # name: (builder, seed, d or (d1, d2), m, k, nev, precision, description)
     "c1": dict(mat=("laplacian_2d", (50,)), seed=1, d=10, m=30, k=15, nev=10, precision="f64",
@@ -130,8 +141,9 @@ def main():
     bt = torch.as_tensor(b, device="cuda")
     vt = torch.as_tensor(v0, device="cuda")
     dbl = isinstance(cfg["d"], tuple)
-    vbytes = 8 if prec == "f64" else 4
-    pb = pass_bytes(csr.n, csr.nnz, vbytes, vbytes)
+    pb64 = pass_bytes(csr.n, csr.nnz, 8, 8)
+    pb32 = pass_bytes(csr.n, csr.nnz, 4, 4)
+    pb = pb64 if prec == "f64" else pb32
 
     def one_step():
         if dbl:
@@ -158,12 +170,19 @@ def main():
     wall = time.perf_counter() - t0
 
     passes = sum(r.spmv_passes for r in results)
+    passes32 = sum(r.spmv_passes_f32 for r in results)
     t_apply = sum(r.t_apply_ms for r in results) / 1e3
-    pi_bytes = passes * pb
+    pi_bytes = passes32 * pb32 + (passes - passes32) * pb64
     value = pi_bytes / wall / 1e9
-    kern_gbs = (pb * passes / t_apply / 1e9) if t_apply > 0 else None
+    kern_gbs = (pi_bytes / t_apply / 1e9) if t_apply > 0 else None
     avg_pass_us = t_apply / passes * 1e6 if passes else None
     nconv = sum(r.nconv for r in results)
+    import hashlib
+    ksrc = os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")
+    khash = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
+    tr = MEASURED_TRAFFIC.get((args.config, khash))
+    traffic = (round(1024 * (tr["fetch_kib"] * tr["fetch_factor"] + tr["write_kib"] * tr["write_factor"]))
+               if tr else None)
     line = {
         "metric": "pi(A)v HBM GB/s; eigenpairs/s at rtol 1e-8 (mixed vs FP64); p99 latency",
         "value": round(value, 2),
@@ -185,17 +204,19 @@ def main():
                   "cycles": [r.cycles for r in results],
                   "max_resid_rel": [r.max_resid / A.norm_inf for r in results],
                   "mvps": results[-1].mvps, "dots": results[-1].dots,
+                  "mu_head": [[round(z.real, 10), round(z.imag, 10)] for z in results[-1].mu[:4]],
                   "fp32_cycles": results[-1].fp32_cycles},
         "roofline": {"kernel": "k_fused_spmv", "bound": "hbm",
                      "achieved": round(kern_gbs, 1) if kern_gbs else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4) if kern_gbs else None,
-                     "traffic": None, "bytes_per_launch": pb,
+                     "traffic": traffic, "bytes_per_launch": round(pi_bytes / max(passes, 1)),
+                     "launches_f32": passes32,
                      "avg_launch_us": round(avg_pass_us, 3) if avg_pass_us else None,
                      "launches": passes},
     }
     if not args.no_cpu_baseline:
         roots = (P.roots(1), P.roots(2)) if dbl else P.roots()
-        bpa = pb * (cfg["d"][0] * cfg["d"][1] if dbl else cfg["d"])
+        bpa = pb64 * (cfg["d"][0] * cfg["d"][1] if dbl else cfg["d"])
         reps, dt, gbs = cpu_baseline(csr, roots, bpa, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{reps} FP64 pi(A)v applications of the same polynomial on "

@@ -223,6 +223,7 @@ typedef struct ppa_eigs_result {
     int fp32_cycles;     /* cycles run with FP32 pi(A)v (PPA_MIXED)          */
     int reserved;
     int64_t spmv_passes; /* fused SpMV passes issued by the operator applications */
+    int64_t spmv_passes_f32; /* of which with FP32 values and vectors (PPA_MIXED) */
     double t_apply_ms;   /* PPA_FLAG_TIMING: device time of all operator applications */
     double t_cgs_ms;     /* PPA_FLAG_TIMING: device time of all CGS2 steps   */
 } ppa_eigs_result;

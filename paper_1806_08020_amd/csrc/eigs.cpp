@@ -285,7 +285,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
             op_vops = p->roots.size();
         }
     }
-    int64_t mvps = 0, dots = 0, vops = 0, passes = 0;
+    int64_t mvps = 0, dots = 0, vops = 0, passes = 0, passes32 = 0;
     bool fp32 = o.precision == PPA_MIXED;
     const bool timing = (o.flags & PPA_FLAG_TIMING) != 0;
     struct Events {
@@ -313,6 +313,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         mvps += op_mvps;
         vops += op_vops;
         passes += op_mvps;
+        if (fp32 && p) passes32 += op_mvps;
     };
 
     launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
@@ -653,6 +654,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     r.max_resid = maxres;
     r.fp32_cycles = fp32_cycles;
     r.spmv_passes = passes;
+    r.spmv_passes_f32 = passes32;
     r.t_apply_ms = t_apply;
     r.t_cgs_ms = t_cgs;
     if (converged) return PPA_OK;

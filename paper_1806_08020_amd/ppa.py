@@ -41,7 +41,8 @@ class EigsResult(C.Structure):
                 ("nconv", C.c_int), ("cycles", C.c_int), ("mvps", C.c_int64),
                 ("dots", C.c_int64), ("vops", C.c_int64), ("max_resid", C.c_double),
                 ("fp32_cycles", C.c_int), ("reserved", C.c_int),
-                ("spmv_passes", C.c_int64), ("t_apply_ms", C.c_double), ("t_cgs_ms", C.c_double)]
+                ("spmv_passes", C.c_int64), ("spmv_passes_f32", C.c_int64),
+                ("t_apply_ms", C.c_double), ("t_cgs_ms", C.c_double)]
 
 
 def _load():
@@ -302,6 +303,7 @@ class EigsOut:
     max_resid: float
     fp32_cycles: int
     spmv_passes: int = 0
+    spmv_passes_f32: int = 0
     t_apply_ms: float = 0.0
     t_cgs_ms: float = 0.0
     X: torch.Tensor | None = None
@@ -335,7 +337,8 @@ def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, 
                               _stream(), C.byref(r)))
     return EigsOut(status=st, mu=lre + 1j * lim, resid=res.copy(), nu=nre + 1j * nim, nconv=r.nconv,
                    cycles=r.cycles, mvps=r.mvps, dots=r.dots, vops=r.vops, max_resid=r.max_resid,
-                   fp32_cycles=r.fp32_cycles, spmv_passes=r.spmv_passes, t_apply_ms=r.t_apply_ms,
+                   fp32_cycles=r.fp32_cycles, spmv_passes=r.spmv_passes,
+                   spmv_passes_f32=r.spmv_passes_f32, t_apply_ms=r.t_apply_ms,
                    t_cgs_ms=r.t_cgs_ms, X=X, converged=(st == PPA_OK))
 
 
