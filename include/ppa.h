@@ -43,7 +43,8 @@ typedef enum ppa_status {
     PPA_ERR_WORKSPACE = -3,       /* workspace missing or too small                 */
     PPA_ERR_NONFINITE = -4,       /* NaN/Inf met in the input or during the solve   */
     PPA_ERR_SINGULAR = -5,        /* H_d singular in the harmonic Ritz solve        */
-    PPA_ERR_NUMERIC = -6          /* small dense eigensolver did not converge       */
+    PPA_ERR_NUMERIC = -6,         /* small dense eigensolver did not converge       */
+    PPA_ERR_BUSY = -7             /* batched engine: no free slot                   */
 } ppa_status;
 
 typedef enum ppa_precision {
@@ -244,6 +245,49 @@ int ppa_eigs_workspace_bytes(const ppa_matrix* A, const ppa_poly* p, const ppa_e
 int ppa_eigs(const ppa_matrix* A, const ppa_poly* p, const ppa_eigs_opts* o,
              const double* v0_d, void* ws_d, size_t ws_bytes, void* stream,
              ppa_eigs_result* r);
+
+/* ------------------------------------------------------------------------
+ * Batched engine for many small solves (the served form; section 2 algorithm
+ * and section 4 Arnoldi(m,k) for each request).  One launch advances every
+ * admitted solve by one phase -- GMRES(d) build, Krylov steps on pi(A) up to
+ * a pass budget, or the Ritz test -- with one workgroup per solve and every
+ * reduction inside that workgroup, so a solve's result does not depend on the
+ * other solves in the batch.  The host handles the small projected problems
+ * between launches.  Requests join free slots and leave between launches
+ * (continuous batching).  FP64 throughout; no eigenvectors are returned.
+ * ------------------------------------------------------------------------ */
+typedef struct ppa_batch ppa_batch;
+
+typedef struct ppa_batch_request {
+    int64_t n;                /* rows of A (n > m, n > d)                        */
+    const int32_t* rowptr_d;  /* CSR of A (device, borrowed until the result is taken) */
+    const int32_t* colind_d;
+    const double* val_d;
+    double anorm;             /* norm for rtol; <= 0: ||A||_inf computed at submit */
+    int d;                    /* GMRES polynomial degree, 1 <= d <= 126          */
+    int m, k, nev;            /* Arnoldi(m,k), nev wanted; m <= 64, nev <= 32    */
+    int max_cycles;
+    double rtol;
+    const double* b_d;        /* GMRES start vector (device)                     */
+    const double* v0_d;       /* Arnoldi start vector (device)                   */
+    void* ws_d;               /* device workspace of ppa_batch_workspace_bytes  */
+    size_t ws_bytes;
+} ppa_batch_request;
+
+int ppa_batch_workspace_bytes(int64_t n, int d, int m, int nev, size_t* bytes);
+/* Engine with up to max_slots concurrent solves; all its work goes to `stream`. */
+int ppa_batch_create(int max_slots, void* stream, ppa_batch** out);
+int ppa_batch_destroy(ppa_batch* b);
+/* Admit a request into a free slot (*slot); PPA_ERR_BUSY when none is free. */
+int ppa_batch_submit(ppa_batch* b, const ppa_batch_request* rq, int* slot);
+/* One launch for all admitted solves, then the host work of the phase ends.
+ * finished[0 .. min(*nfinished, cap)) receive slots whose solve ended (their
+ * results are ready); *nactive the number of solves that took part.
+ * Synchronises the stream. */
+int ppa_batch_step(ppa_batch* b, int* finished, int cap, int* nfinished, int* nactive);
+/* Results of a finished slot (lam/resid/ritz arrays of capacity nev; X_d is
+ * ignored); frees the slot.  Returns the solve's status. */
+int ppa_batch_result(ppa_batch* b, int slot, ppa_eigs_result* r);
 
 /* ------------------------------------------------------------------------
  * Host small dense eigensolver used for the projected problems (exported for

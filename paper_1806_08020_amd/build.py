@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libppa.so")
-SOURCES = ["spmv.hip", "blas.hip", "dense.cpp", "poly.cpp", "eigs.cpp", "api.cpp"]
+SOURCES = ["spmv.hip", "blas.hip", "dense.cpp", "ritz.cpp", "poly.cpp", "eigs.cpp", "batch.hip", "api.cpp"]
 ARCH = "gfx950"
 
 COMMON = [

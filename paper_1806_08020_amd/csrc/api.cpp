@@ -355,6 +355,50 @@ int ppa_eigs(const ppa_matrix* h, const ppa_poly* ph, const ppa_eigs_opts* o, co
     });
 }
 
+int ppa_batch_workspace_bytes(int64_t n, int d, int m, int nev, size_t* bytes) {
+    return guarded([&] {
+        PPA_REQUIRE(bytes && n >= 1 && d >= 1 && m >= 2 && nev >= 1, "bad arguments");
+        *bytes = batch_ws_bytes(n, d, m, nev);
+        return PPA_OK;
+    });
+}
+
+int ppa_batch_create(int max_slots, void* stream, ppa_batch** out) {
+    return guarded([&] {
+        PPA_REQUIRE(out != nullptr, "out is NULL");
+        *out = reinterpret_cast<ppa_batch*>(batch_create(max_slots, (hipStream_t)stream));
+        return PPA_OK;
+    });
+}
+
+int ppa_batch_destroy(ppa_batch* b) {
+    return guarded([&] {
+        batch_destroy(reinterpret_cast<Batch*>(b));
+        return PPA_OK;
+    });
+}
+
+int ppa_batch_submit(ppa_batch* b, const ppa_batch_request* rq, int* slot) {
+    return guarded([&] {
+        PPA_REQUIRE(b && rq && slot, "batch, request and slot are required");
+        return batch_submit(*reinterpret_cast<Batch*>(b), *rq, slot);
+    });
+}
+
+int ppa_batch_step(ppa_batch* b, int* finished, int cap, int* nfinished, int* nactive) {
+    return guarded([&] {
+        PPA_REQUIRE(b && nfinished, "batch and nfinished are required");
+        return batch_step(*reinterpret_cast<Batch*>(b), finished, cap, nfinished, nactive);
+    });
+}
+
+int ppa_batch_result(ppa_batch* b, int slot, ppa_eigs_result* r) {
+    return guarded([&] {
+        PPA_REQUIRE(b && r, "batch and result are required");
+        return batch_result(*reinterpret_cast<Batch*>(b), slot, *r);
+    });
+}
+
 int ppa_dense_eig(int n, const double* a, double* wr, double* wi, double* vr, double* vi) {
     return guarded([&] {
         PPA_REQUIRE(n >= 1 && a && wr && wi, "bad arguments");

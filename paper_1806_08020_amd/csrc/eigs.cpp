@@ -217,33 +217,6 @@ void carve_eigs(Carver& c, const Matrix& A, const Poly* p, const ppa_eigs_opts& 
     e.cscale = c.take<double>((size_t)2 * o.nev);
 }
 
-// Ordering of Ritz values of the operator (section 4): increasing |target - nu|,
-// ties larger Im first, then smaller Re.
-std::vector<int> sort_ritz(const std::vector<cplx>& nu, double target) {
-    std::vector<int> idx(nu.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        const double da = std::abs(target - nu[a]), db = std::abs(target - nu[b]);
-        if (da != db) return da < db;
-        if (nu[a].imag() != nu[b].imag()) return nu[a].imag() > nu[b].imag();
-        return nu[a].real() < nu[b].real();
-    });
-    return idx;
-}
-
-struct Wanted {
-    // per wanted Ritz value i: Y columns holding Re / Im of its vector
-    std::vector<int> cre, cim;
-    std::vector<double> imsign;   // +1 or -1 (conjugate member)
-    int ycols = 0;
-};
-
-struct RitzOut {
-    std::vector<cplx> mu;
-    std::vector<double> res;
-    std::vector<double> ynorm;
-};
-
 }  // namespace
 
 size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o) {
@@ -321,8 +294,13 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     int j0 = 0;
     std::vector<double> H((size_t)(m + 1) * m);
     std::vector<double> hist;
+    struct RitzOut {
+        std::vector<cplx> mu;
+        std::vector<double> res;
+        std::vector<double> ynorm;
+    };
     RitzOut last;
-    Wanted lastw;
+    RitzPlan lastw;
     std::vector<cplx> lastnu;
     bool converged = false, broke = false;
     int cycle = 0;
@@ -366,166 +344,57 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         std::vector<double> Hm((size_t)mc * mc);
         for (int jj = 0; jj < mc; ++jj)
             for (int i = 0; i < mc; ++i) Hm[i + (size_t)jj * mc] = H[i + (size_t)jj * (m + 1)];
-        std::vector<cplx> nu0, G0;
-        dense_eig(mc, Hm.data(), nu0, &G0);
-        const std::vector<int> ord = sort_ritz(nu0, target);
-        std::vector<cplx> nu(mc);
-        std::vector<cplx> G((size_t)mc * mc);
-        for (int i = 0; i < mc; ++i) {
-            nu[i] = nu0[ord[i]];
-            for (int q = 0; q < mc; ++q) G[q + (size_t)i * mc] = G0[q + (size_t)ord[i] * mc];
-        }
-        // wanted Ritz vectors y = V_m g as real columns of Y
-        const int nw = std::min(nev, mc);
-        Wanted W;
-        std::vector<double> Gw;   // mc x ycols
-        for (int i = 0; i < nw; ++i) {
-            if (nu[i].imag() == 0.0) {
-                W.cre.push_back(W.ycols);
-                W.cim.push_back(-1);
-                W.imsign.push_back(0.0);
-                for (int q = 0; q < mc; ++q) Gw.push_back(G[q + (size_t)i * mc].real());
-                W.ycols += 1;
-            } else if (nu[i].imag() > 0.0 || i == 0 || nu[i - 1] != std::conj(nu[i])) {
-                // y = V g with columns Re g, Im g
-                W.cre.push_back(W.ycols);
-                W.cim.push_back(W.ycols + 1);
-                W.imsign.push_back(1.0);
-                for (int q = 0; q < mc; ++q) Gw.push_back(G[q + (size_t)i * mc].real());
-                for (int q = 0; q < mc; ++q) Gw.push_back(G[q + (size_t)i * mc].imag());
-                W.ycols += 2;
-            } else {
-                // conjugate of the previous wanted value: same columns
-                W.cre.push_back(W.cre.back());
-                W.cim.push_back(W.cim.back());
-                W.imsign.push_back(-1.0);
-            }
-        }
-        PPA_HIP(hipMemcpyAsync(e.Qd, Gw.data(), Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gemm_tall(n, mc, W.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);
-        for (int cc = 0; cc < W.ycols; ++cc)
+        RitzPlan R = plan_ritz(Hm, mc, nev, target);
+        const int nw = R.nw;
+        PPA_HIP(hipMemcpyAsync(e.Qd, R.Gw.data(), R.Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemm_tall(n, mc, R.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);
+        for (int cc = 0; cc < R.ycols; ++cc)
             launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, e.Y + (size_t)cc * e.ld, 0.0,
                               nullptr, 0.0, nullptr, e.AY + (size_t)cc * e.ld, s);
-        // dots: per column pair (re, im) or single re column; an entry
-        // {a, b} is y_a . (A y)_b, {a, b + 1000} is y_a . y_b
-        std::vector<std::array<int, 2>> dspec;
-        for (int i = 0; i < nw; ++i) {
-            if (i > 0 && W.cre[i] == W.cre[i - 1]) continue;
-            const int a = W.cre[i], b = W.cim[i];
-            dspec.push_back({a, a + 1000});       // y_a . y_a
-            dspec.push_back({a, a});              // y_a . Ay_a
-            if (b >= 0) {
-                dspec.push_back({b, b + 1000});
-                dspec.push_back({b, b});
-                dspec.push_back({a, b});          // y_a . Ay_b
-                dspec.push_back({b, a});          // y_b . Ay_a
-            }
-        }
+        const std::vector<DotSpec> dspec = ritz_dots(R);
         std::vector<double> dv(dspec.size());
         for (size_t off = 0; off < dspec.size(); off += MAX_DOTS) {
             DotList L{};
             L.count = (int)std::min<size_t>(MAX_DOTS, dspec.size() - off);
             for (int t = 0; t < L.count; ++t) {
-                const auto& q = dspec[off + t];
-                L.a[t] = e.Y + (size_t)q[0] * e.ld;
-                L.b[t] = q[1] >= 1000 ? e.Y + (size_t)(q[1] - 1000) * e.ld : e.AY + (size_t)q[1] * e.ld;
+                const DotSpec& q = dspec[off + t];
+                L.a[t] = e.Y + (size_t)q.a * e.ld;
+                L.b[t] = (q.kind == 1 ? e.Y : e.AY) + (size_t)q.b * e.ld;
             }
             launch_dots(n, L, e.dpart, nb, e.dout, s);
             PPA_HIP(hipMemcpyAsync(dv.data() + off, e.dout, L.count * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         PPA_HIP(hipStreamSynchronize(s));
-        // Rayleigh quotients mu = y^* A y / y^* y
-        RitzOut R;
-        R.mu.resize(nw);
-        R.res.resize(nw);
-        R.ynorm.resize(nw);
-        {
-            size_t t = 0;
-            std::vector<cplx> mu_col(W.ycols);
-            std::vector<double> yy_col(W.ycols);
-            for (int i = 0; i < nw; ++i) {
-                if (i > 0 && W.cre[i] == W.cre[i - 1]) {
-                    R.mu[i] = std::conj(R.mu[i - 1]);
-                    R.ynorm[i] = R.ynorm[i - 1];
-                    continue;
-                }
-                if (W.cim[i] < 0) {
-                    const double yy = dv[t], yAy = dv[t + 1];
-                    t += 2;
-                    R.mu[i] = cplx(yAy / yy, 0.0);
-                    R.ynorm[i] = std::sqrt(yy);
-                } else {
-                    const double aa = dv[t], aAa = dv[t + 1], bb = dv[t + 2], bAb = dv[t + 3];
-                    const double aAb = dv[t + 4], bAa = dv[t + 5];
-                    t += 6;
-                    const double yy = aa + bb;
-                    R.mu[i] = cplx(aAa + bAb, aAb - bAa) / yy;
-                    R.ynorm[i] = std::sqrt(yy);
-                }
-            }
-        }
-        for (int i = 0; i < nw; ++i) mvps += (nu[i].imag() == 0.0) ? 1 : 2;
+        RitzOut Rr;
+        ritz_mu(R, dv, Rr.mu, Rr.ynorm);
+        mvps += ritz_mvps(R);
         // residual norms ||A y - mu y|| / ||y||
         {
-            struct Combo {
-                const double* v[3];
-                double c[3];
-            };
-            std::vector<Combo> L;
-            std::vector<int> owner;
-            for (int i = 0; i < nw; ++i) {
-                if (i > 0 && W.cre[i] == W.cre[i - 1]) continue;
-                const int a = W.cre[i], b = W.cim[i];
-                const double mr = R.mu[i].real(), mi = R.mu[i].imag();
-                const double* Ya = e.Y + (size_t)a * e.ld;
-                const double* AYa = e.AY + (size_t)a * e.ld;
-                if (b < 0) {
-                    L.push_back({{AYa, Ya, nullptr}, {1.0, -mr, 0.0}});
-                    owner.push_back(i);
-                } else {
-                    const double* Yb = e.Y + (size_t)b * e.ld;
-                    const double* AYb = e.AY + (size_t)b * e.ld;
-                    // A y - mu y with y = a + i b, mu = mr + i mi:
-                    // real part A a - mr a + mi b, imaginary part A b - mr b - mi a
-                    L.push_back({{AYa, Ya, Yb}, {1.0, -mr, mi}});
-                    L.push_back({{AYb, Yb, Ya}, {1.0, -mr, -mi}});
-                    owner.push_back(i);
-                    owner.push_back(i);
-                }
-            }
-            const int nl = (int)L.size();
+            const std::vector<ComboSpec> cs = ritz_combos(R, Rr.mu);
+            const int nl = (int)cs.size();
             std::vector<double> rn(nl);
-            // split into launches of at most MAX_COMBOS
-            int done = 0;
-            while (done < nl) {
+            for (int done = 0; done < nl;) {
                 ComboList P{};
                 P.count = std::min(MAX_COMBOS, nl - done);
                 for (int q = 0; q < P.count; ++q)
                     for (int t = 0; t < 3; ++t) {
-                        P.v[q][t] = L[done + q].v[t];
-                        P.c[q][t] = L[done + q].c[t];
+                        const ComboSpec& c = cs[done + q];
+                        P.v[q][t] = t < c.nterms ? (c.kind[t] == 0 ? e.AY : e.Y) + (size_t)c.col[t] * e.ld : nullptr;
+                        P.c[q][t] = t < c.nterms ? c.c[t] : 0.0;
                     }
                 launch_combo_norms(n, P, e.dpart, nb, e.dout, s);
                 PPA_HIP(hipMemcpyAsync(rn.data() + done, e.dout, P.count * sizeof(double), hipMemcpyDeviceToHost, s));
                 done += P.count;
             }
             PPA_HIP(hipStreamSynchronize(s));
-            std::vector<double> acc(nw, 0.0);
-            for (size_t q = 0; q < owner.size(); ++q) acc[owner[q]] += rn[q];
-            for (int i = 0; i < nw; ++i) {
-                if (i > 0 && W.cre[i] == W.cre[i - 1]) {
-                    R.res[i] = R.res[i - 1];
-                    continue;
-                }
-                R.res[i] = std::sqrt(acc[i]) / R.ynorm[i];
-            }
+            ritz_resid(R, cs, rn, Rr.ynorm, Rr.res);
         }
         double mx = 0.0;
-        for (int i = 0; i < nw; ++i) mx = std::max(mx, R.res[i]);
+        for (int i = 0; i < nw; ++i) mx = std::max(mx, Rr.res[i]);
         hist.push_back(mx);
-        last = R;
-        lastw = W;
-        lastnu.assign(nu.begin(), nu.begin() + nw);
+        last = Rr;
+        lastw = R;
+        lastnu.assign(R.nu.begin(), R.nu.begin() + nw);
         converged = (nw == nev) && mx <= rtol_abs;
         if (converged || broke || cycle == o.max_cycles) break;
 
@@ -538,14 +407,14 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
             const bool stall = hc >= 3 && hist[hc - 1] > 0.5 * hist[hc - 3];
             if (floor || stall) {
                 fp32 = false;
-                std::vector<double> coef(W.ycols, 0.0);
+                std::vector<double> coef(R.ycols, 0.0);
                 for (int i = 0; i < nw; ++i) {
-                    if (i > 0 && W.cre[i] == W.cre[i - 1]) continue;
-                    coef[W.cre[i]] += 1.0 / R.ynorm[i];
-                    if (W.cim[i] >= 0) coef[W.cim[i]] += 1.0 / R.ynorm[i];
+                    if (R.dup[i]) continue;
+                    coef[R.cre[i]] += 1.0 / Rr.ynorm[i];
+                    if (R.cim[i] >= 0) coef[R.cim[i]] += 1.0 / Rr.ynorm[i];
                 }
                 PPA_HIP(hipMemcpyAsync(e.Qd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
-                launch_gemm_tall(n, W.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
+                launch_gemm_tall(n, R.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
                 launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
                 set_unit(n, e.V2, e.V, e.dpart, nb, e.dout, s);
                 j0 = 0;
@@ -554,46 +423,12 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         }
 
         // thick restart: keep k (k-1 if a conjugate pair would be split)
-        int kk = std::min(k, mc - 1);
-        if (kk < mc && nu[kk - 1].imag() > 0.0) kk -= 1;
-        if (kk == 0) kk = std::min(2, mc - 1);
-        std::vector<double> B;
-        for (int i = 0; i < kk; ++i) {
-            if (nu[i].imag() == 0.0) {
-                for (int q = 0; q < mc; ++q) B.push_back(G[q + (size_t)i * mc].real());
-            } else if (nu[i].imag() > 0.0) {
-                for (int q = 0; q < mc; ++q) B.push_back(G[q + (size_t)i * mc].real());
-                for (int q = 0; q < mc; ++q) B.push_back(G[q + (size_t)i * mc].imag());
-            }
-        }
-        std::vector<double> Q;
-        orthonormal_basis(mc, kk, B, Q);
-        // Q' = [[Q, 0], [0, 1]]  ((m+1) x (kk+1)): V2 = [V_m Q, v_{m+1}]
-        std::vector<double> Qp((size_t)(m + 1) * (kk + 1), 0.0);
-        for (int jj = 0; jj < kk; ++jj)
-            for (int i = 0; i < mc; ++i) Qp[i + (size_t)jj * (m + 1)] = Q[i + (size_t)jj * mc];
-        Qp[m + (size_t)kk * (m + 1)] = 1.0;
-        PPA_HIP(hipMemcpyAsync(e.Qd, Qp.data(), Qp.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gemm_tall(n, m + 1, kk + 1, e.V, e.ld, e.Qd, e.V2, e.ld, s);
+        const RestartPlan RP = plan_restart(R, Hm, H[m + (size_t)(m - 1) * (m + 1)], m, k);
+        PPA_HIP(hipMemcpyAsync(e.Qd, RP.Qp.data(), RP.Qp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemm_tall(n, m + 1, RP.kk + 1, e.V, e.ld, e.Qd, e.V2, e.ld, s);
         std::swap(e.V, e.V2);
-        // H_k = Q^T H_m Q and the spike row h_{m+1,m} e_m^T Q
-        std::vector<double> HQ((size_t)mc * kk, 0.0), Hn((size_t)(m + 1) * m, 0.0);
-        for (int jj = 0; jj < kk; ++jj)
-            for (int i = 0; i < mc; ++i) {
-                double sacc = 0.0;
-                for (int q = 0; q < mc; ++q) sacc += Hm[i + (size_t)q * mc] * Q[q + (size_t)jj * mc];
-                HQ[i + (size_t)jj * mc] = sacc;
-            }
-        for (int jj = 0; jj < kk; ++jj)
-            for (int i = 0; i < kk; ++i) {
-                double sacc = 0.0;
-                for (int q = 0; q < mc; ++q) sacc += Q[q + (size_t)i * mc] * HQ[q + (size_t)jj * mc];
-                Hn[i + (size_t)jj * (m + 1)] = sacc;
-            }
-        const double hm = H[m + (size_t)(m - 1) * (m + 1)];
-        for (int jj = 0; jj < kk; ++jj) Hn[kk + (size_t)jj * (m + 1)] = hm * Q[(m - 1) + (size_t)jj * mc];
-        PPA_HIP(hipMemcpyAsync(e.Hd, Hn.data(), Hn.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        j0 = kk;
+        PPA_HIP(hipMemcpyAsync(e.Hd, RP.Hn.data(), RP.Hn.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        j0 = RP.kk;
     }
     if (cycle > o.max_cycles) cycle = o.max_cycles;
 
@@ -633,7 +468,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
             cim[t] = lastw.cim[i];
             const double inv = 1.0 / last.ynorm[i];
             sc[2 * t] = inv;
-            sc[2 * t + 1] = (lastw.imsign[i] < 0.0 ? -1.0 : 1.0) * inv;
+            sc[2 * t + 1] = (lastw.dup[i] ? -1.0 : 1.0) * inv;
         }
         // Y still holds the wanted columns of the last cycle
         std::vector<int> maps(2 * nw);

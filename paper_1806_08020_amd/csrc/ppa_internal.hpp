@@ -203,6 +203,47 @@ void apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vo
 void apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
                            double* y, double c, double gamma, const double* z, ApplyWs& ws,
                            hipStream_t s);
+// ---------------------------------------------------------------- projected problem (ritz.cpp)
+// Ordering of Ritz values (section 4): increasing |target - nu|, ties larger
+// Im first, then smaller Re.  target = 1 for pi(A), 0 for A itself.
+std::vector<int> sort_ritz(const std::vector<cplx>& nu, double target);
+struct RitzPlan {
+    int mc = 0, nw = 0;
+    std::vector<cplx> nu;        // sorted Ritz values of the operator (mc)
+    std::vector<cplx> G;         // mc x mc eigenvectors of H_m, sorted columns
+    std::vector<int> cre, cim;   // wanted i: columns of Y holding Re / Im of y_i (cim = -1: real)
+    std::vector<int> dup;        // wanted i is the conjugate of wanted i-1 (same columns)
+    int ycols = 0;
+    std::vector<double> Gw;      // mc x ycols: Y = V_m Gw
+};
+RitzPlan plan_ritz(const std::vector<double>& Hm, int mc, int nev, double target);
+// Ritz-test dot products: kind 0 is y_a . (A y)_b, kind 1 is y_a . y_b.
+struct DotSpec {
+    int a, b, kind;
+};
+std::vector<DotSpec> ritz_dots(const RitzPlan& R);
+void ritz_mu(const RitzPlan& R, const std::vector<double>& dv, std::vector<cplx>& mu,
+             std::vector<double>& ynorm);
+// ||sum_t c_t v_t||^2 with v_t column col[t] of AY (kind 0) or Y (kind 1).
+struct ComboSpec {
+    int owner;
+    int col[3];
+    int kind[3];
+    double c[3];
+    int nterms;
+};
+std::vector<ComboSpec> ritz_combos(const RitzPlan& R, const std::vector<cplx>& mu);
+void ritz_resid(const RitzPlan& R, const std::vector<ComboSpec>& cs, const std::vector<double>& rn,
+                const std::vector<double>& ynorm, std::vector<double>& res);
+int64_t ritz_mvps(const RitzPlan& R);
+struct RestartPlan {
+    int kk = 0;
+    std::vector<double> Q;    // mc x kk orthonormal basis of the kept Ritz vectors
+    std::vector<double> Qp;   // (m+1) x (kk+1): [[Q, 0], [0, 1]]
+    std::vector<double> Hn;   // (m+1) x m: new projected matrix (first kk columns)
+};
+RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, double hm, int m, int k);
+
 // polynomial construction and Arnoldi drivers (eigs.cpp)
 size_t poly_build_ws(int64_t n, int d, bool dbl);
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
@@ -210,5 +251,14 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
 size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o);
 int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v0, void* ws,
          size_t ws_bytes, hipStream_t s, ppa_eigs_result& r);
+
+// ---------------------------------------------------------------- batched engine (batch.hip)
+struct Batch;
+size_t batch_ws_bytes(int64_t n, int d, int m, int nev);
+Batch* batch_create(int max_slots, hipStream_t s);
+void batch_destroy(Batch* B);
+int batch_submit(Batch& B, const ppa_batch_request& rq, int* slot);
+int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive);
+int batch_result(Batch& B, int slot, ppa_eigs_result& r);
 
 }  // namespace ppa

@@ -45,6 +45,13 @@ class EigsResult(C.Structure):
                 ("t_apply_ms", C.c_double), ("t_cgs_ms", C.c_double)]
 
 
+class BatchRequest(C.Structure):
+    _fields_ = [("n", C.c_int64), ("rowptr_d", vp), ("colind_d", vp), ("val_d", vp),
+                ("anorm", C.c_double), ("d", C.c_int), ("m", C.c_int), ("k", C.c_int),
+                ("nev", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double),
+                ("b_d", vp), ("v0_d", vp), ("ws_d", vp), ("ws_bytes", C.c_size_t)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
@@ -74,6 +81,12 @@ def _load():
         "ppa_gemm_tall": (i, [i64, i, i, vp, i64, P(d), vp, i64, vp, sz, vp]),
         "ppa_eigs_workspace_bytes": (i, [vp, vp, P(EigsOpts), P(sz)]),
         "ppa_eigs": (i, [vp, vp, P(EigsOpts), vp, vp, sz, vp, P(EigsResult)]),
+        "ppa_batch_workspace_bytes": (i, [i64, i, i, i, P(sz)]),
+        "ppa_batch_create": (i, [i, vp, P(vp)]),
+        "ppa_batch_destroy": (i, [vp]),
+        "ppa_batch_submit": (i, [vp, P(BatchRequest), P(i)]),
+        "ppa_batch_step": (i, [vp, P(i), i, P(i), P(i)]),
+        "ppa_batch_result": (i, [vp, i, P(EigsResult)]),
         "ppa_dense_eig": (i, [i, P(d), P(d), P(d), P(d), P(d)]),
         "ppa_leja_order": (i, [i, P(d), P(d)]),
     }
@@ -340,6 +353,74 @@ def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, 
                    fp32_cycles=r.fp32_cycles, spmv_passes=r.spmv_passes,
                    spmv_passes_f32=r.spmv_passes_f32, t_apply_ms=r.t_apply_ms,
                    t_cgs_ms=r.t_cgs_ms, X=X, converged=(st == PPA_OK))
+
+
+# ---------------------------------------------------------------- batched engine
+PPA_ERR_BUSY = -7
+
+
+def batch_workspace_bytes(n: int, d: int, m: int, nev: int) -> int:
+    nb = C.c_size_t()
+    _check(_lib.ppa_batch_workspace_bytes(n, d, m, nev, C.byref(nb)))
+    return nb.value
+
+
+class Batch:
+    """Batched engine for many small solves: one launch per step advances
+    every admitted solve by one phase (one workgroup each).  All work goes to
+    the stream current at construction (or the given torch stream)."""
+
+    def __init__(self, max_slots: int, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = vp()
+        _check(_lib.ppa_batch_create(max_slots, vp(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.max_slots = max_slots
+        self._keep = {}
+        self._fin = (C.c_int * max_slots)()
+
+    def submit(self, rowptr, colind, vals, d, m, k, nev, b, v0, rtol=1e-8, max_cycles=50,
+               anorm=0.0, ws=None):
+        """Admit one solve; device tensors stay referenced until its result is
+        taken.  Returns the slot, or None when the engine is full."""
+        n = rowptr.numel() - 1
+        if ws is None:
+            ws = _workspace(batch_workspace_bytes(n, d, m, nev))
+        rq = BatchRequest(n, _ptr(rowptr), _ptr(colind), _ptr(vals), anorm, d, m, k, nev, max_cycles,
+                          rtol, _ptr(b), _ptr(v0), _ptr(ws), ws.numel())
+        slot = C.c_int(-1)
+        st = _lib.ppa_batch_submit(self.h, C.byref(rq), C.byref(slot))
+        if st == PPA_ERR_BUSY:
+            return None
+        _check(st)
+        self._keep[slot.value] = (rowptr, colind, vals, b, v0, ws, nev)
+        return slot.value
+
+    def step(self):
+        """One batched launch; returns (finished slots, number of active solves)."""
+        nf, na = C.c_int(), C.c_int()
+        _check(_lib.ppa_batch_step(self.h, self._fin, self.max_slots, C.byref(nf), C.byref(na)))
+        return [self._fin[i] for i in range(min(nf.value, self.max_slots))], na.value
+
+    def result(self, slot: int) -> EigsOut:
+        nev = self._keep[slot][6]
+        lre, lim, res, nre, nim = (np.zeros(nev) for _ in range(5))
+        r = EigsResult()
+        P = C.POINTER(C.c_double)
+        r.lam_re, r.lam_im, r.resid = lre.ctypes.data_as(P), lim.ctypes.data_as(P), res.ctypes.data_as(P)
+        r.ritz_re, r.ritz_im = nre.ctypes.data_as(P), nim.ctypes.data_as(P)
+        r.X_d = None
+        st = _check(_lib.ppa_batch_result(self.h, slot, C.byref(r)))
+        del self._keep[slot]
+        return EigsOut(status=st, mu=lre + 1j * lim, resid=res.copy(), nu=nre + 1j * nim, nconv=r.nconv,
+                       cycles=r.cycles, mvps=r.mvps, dots=r.dots, vops=r.vops, max_resid=r.max_resid,
+                       fp32_cycles=0, spmv_passes=r.spmv_passes, converged=(st == PPA_OK))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _lib.ppa_batch_destroy(h)
+            self.h = None
 
 
 # ---------------------------------------------------------------- host helpers

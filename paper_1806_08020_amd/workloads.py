@@ -76,27 +76,37 @@ def _stencil(dims, center, lower, upper) -> CSR:
     center : diagonal coefficient
     lower  : coefficient of the -1 neighbour along each axis (tuple per axis)
     upper  : coefficient of the +1 neighbour along each axis
+
+    Rows are built in place: the neighbour offsets, sorted, give each row's
+    columns in increasing order, so no global sort is needed.
     """
     dims = tuple(int(d) for d in dims)
     n = int(np.prod(dims))
     idx = np.arange(n, dtype=np.int64)
+    strides = np.cumprod((1,) + dims[:-1])
+    # (offset, coefficient, validity mask) for every neighbour, offsets ascending
+    entries = []
+    rem = idx
     coords = []
-    rem = idx.copy()
     for d in dims:
         coords.append(rem % d)
-        rem //= d
-    rows = [idx]
-    cols = [idx]
-    vals = [np.full(n, center, dtype=np.float64)]
-    stride = 1
-    for ax, d in enumerate(dims):
-        c = coords[ax]
-        m = c > 0
-        rows.append(idx[m]); cols.append(idx[m] - stride); vals.append(np.full(m.sum(), lower[ax]))
-        m = c < d - 1
-        rows.append(idx[m]); cols.append(idx[m] + stride); vals.append(np.full(m.sum(), upper[ax]))
-        stride *= d
-    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+        rem = rem // d
+    for ax in reversed(range(len(dims))):
+        entries.append((-int(strides[ax]), lower[ax], coords[ax] > 0))
+    entries.append((0, center, np.ones(n, dtype=bool)))
+    for ax in range(len(dims)):
+        entries.append((int(strides[ax]), upper[ax], coords[ax] < dims[ax] - 1))
+    mask = np.stack([e[2] for e in entries], axis=1)                 # n x s
+    offs = np.array([e[0] for e in entries], dtype=np.int64)
+    coef = np.array([e[1] for e in entries], dtype=np.float64)
+    cols = (idx[:, None] + offs[None, :])[mask]
+    vals = np.broadcast_to(coef, mask.shape)[mask]
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    if rowptr[-1] >= 2**31:
+        raise ValueError("nnz does not fit int32 indices")
+    return CSR(n, rowptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64))
 
 
 def laplacian_2d(nx: int, ny: int | None = None) -> CSR:
