@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 
 #include "ppa_internal.hpp"
 
@@ -373,6 +374,7 @@ struct BReqState {
     int nconv = 0;
     int64_t mvps = 0, dots = 0, vops = 0;
     int build_status = PPA_OK;
+    std::string err;
 };
 
 size_t carve_batch(Carver& c, int64_t n, int d, int m, int nev, BReqState* s) {
@@ -728,6 +730,7 @@ int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive) {
             }
         } catch (const Error& e) {
             q.status = e.code;
+            q.err = e.what();
             q.state = ST_DONE;
             if (nf < cap && finished) finished[nf] = slot;
             ++nf;
@@ -743,7 +746,12 @@ int batch_result(Batch& B, int slot, ppa_eigs_result& r) {
     PPA_REQUIRE(q.state == ST_DONE, "batch: slot %d has no finished solve", slot);
     PPA_REQUIRE(r.lam_re && r.lam_im && r.resid, "batch: result arrays are required");
     const int status = q.status;
-    if (status >= 0) {
+    if (status < 0) {
+        const std::string msg = q.err;
+        B.st[slot] = BReqState();
+        fail(status, "%s", msg.c_str());
+    }
+    {
         const int nw = (int)q.mu.size(), nev = q.rq.nev;
         std::vector<int> ord(nw);
         for (int i = 0; i < nw; ++i) ord[i] = i;

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdint>
 
 #include "ppa_internal.hpp"
 
@@ -138,6 +139,8 @@ bool schur(Mat& H, Mat* Z, std::vector<cplx>& w) {
     for (int j = 0; j < n; ++j)
         for (int i = 0; i <= std::min(j + 1, n - 1); ++i) anorm += std::fabs(H(i, j));
     const double eps = DBL_EPSILON;
+    const double smlnum = DBL_MIN * ((double)n / eps);
+    const int itmax = 30 * std::max(10, n);
     int hi = n - 1, its = 0, total = 0;
     double v[3];
     while (hi >= 0) {
@@ -145,7 +148,7 @@ bool schur(Mat& H, Mat* Z, std::vector<cplx>& w) {
         for (; l > 0; --l) {
             double s = std::fabs(H(l - 1, l - 1)) + std::fabs(H(l, l));
             if (s == 0.0) s = anorm;
-            if (std::fabs(H(l, l - 1)) <= eps * s) {
+            if (std::fabs(H(l, l - 1)) <= smlnum || std::fabs(H(l, l - 1)) <= eps * s) {
                 H(l, l - 1) = 0.0;
                 break;
             }
@@ -184,12 +187,16 @@ bool schur(Mat& H, Mat* Z, std::vector<cplx>& w) {
             its = 0;
             continue;
         }
-        if (its >= 80 || total >= 200 * n) return false;
+        if (total >= itmax) return false;
         double s, t;
-        if (its == 10 || its == 20 || its == 40) {
-            // exceptional shifts: a conjugate pair near the trailing corner
-            const double ex = std::fabs(H(hi, hi - 1)) + std::fabs(H(hi - 1, hi - 2));
-            const double re = H(hi, hi) + 0.75 * ex, im = 0.66 * ex;
+        if (its > 0 && its % 10 == 0) {
+            // exceptional shifts (a conjugate pair) from the trailing or, every
+            // other time, the leading corner of the active window
+            const bool top = (its / 10) % 2 == 0;
+            const double ex = top ? std::fabs(H(l + 1, l)) + std::fabs(H(l + 2, l + 1))
+                                  : std::fabs(H(hi, hi - 1)) + std::fabs(H(hi - 1, hi - 2));
+            const double base = top ? H(l, l) : H(hi, hi);
+            const double re = base + 0.75 * ex, im = 0.66 * ex;
             s = 2.0 * re;
             t = re * re + im * im;
         } else {
@@ -289,14 +296,15 @@ void tri_eigvec(const Mat& T, const std::vector<cplx>& w, int p, double smin, st
 
 }  // namespace
 
-void dense_eig(int n, const double* a, std::vector<cplx>& w, std::vector<cplx>* V) {
-    Mat H(n, n), Q(n, n);
-    std::copy(a, a + (size_t)n * n, H.a.begin());
-    for (double e : H.a)
-        if (!std::isfinite(e)) fail(PPA_ERR_NONFINITE, "dense_eig: non-finite matrix entry");
+// One attempt: Hessenberg reduction, Francis QR, eigenvectors.  (No diagonal
+// balancing: after a thick restart H_m is nearly block triangular, and the
+// large scalings balancing would pick make the mapped-back eigenvectors
+// inaccurate in norm, which is the accuracy the restart needs.)
+static bool eig_attempt(int n, const Mat& A0, std::vector<cplx>& w, std::vector<cplx>* V) {
+    Mat H = A0, Q(n, n);
     hessenberg_reduce(H, Q);
-    if (!schur(H, V ? &Q : nullptr, w)) fail(PPA_ERR_NUMERIC, "dense_eig: QR iteration did not converge (n=%d)", n);
-    if (!V) return;
+    if (!schur(H, V ? &Q : nullptr, w)) return false;
+    if (!V) return true;
     double tn = 0.0;
     for (double e : H.a) tn = std::max(tn, std::fabs(e));
     const double smin = std::max(DBL_EPSILON * tn, DBL_MIN);
@@ -320,12 +328,61 @@ void dense_eig(int n, const double* a, std::vector<cplx>& w, std::vector<cplx>* 
         if (nrm > 0.0)
             for (int i = 0; i < n; ++i) (*V)[i + (size_t)p * n] /= nrm;
     }
+    return true;
+}
+
+void dense_eig(int n, const double* a, std::vector<cplx>& w, std::vector<cplx>* V) {
+    Mat A(n, n);
+    std::copy(a, a + (size_t)n * n, A.a.begin());
+    for (double e : A.a)
+        if (!std::isfinite(e)) fail(PPA_ERR_NONFINITE, "dense_eig: non-finite matrix entry");
+    if (eig_attempt(n, A, w, V)) return;
+    // Rare stagnation of the shifted QR: retry on orthogonally similar
+    // matrices Z^T A Z (same eigenvalues; eigenvectors mapped back by Z).
+    for (int attempt = 1; attempt <= 3; ++attempt) {
+        Mat Z(n, n), B(n, n), T(n, n);
+        uint64_t state = 0x9E3779B97F4A7C15ull * (uint64_t)attempt + (uint64_t)n;
+        for (double& e : Z.a) {
+            state ^= state << 13; state ^= state >> 7; state ^= state << 17;
+            e = (double)(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        std::vector<double> Zq;
+        orthonormal_basis(n, n, Z.a, Zq);
+        Z.a = Zq;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int k = 0; k < n; ++k) t += A(i, k) * Z(k, j);
+                T(i, j) = t;
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int k = 0; k < n; ++k) t += Z(k, i) * T(k, j);
+                B(i, j) = t;
+            }
+        std::vector<cplx> Vb;
+        if (!eig_attempt(n, B, w, V ? &Vb : nullptr)) continue;
+        if (V) {
+            V->assign((size_t)n * n, cplx(0.0, 0.0));
+            for (int p = 0; p < n; ++p)
+                for (int i = 0; i < n; ++i) {
+                    cplx s = 0.0;
+                    for (int k = 0; k < n; ++k) s += Z(i, k) * Vb[k + (size_t)p * n];
+                    (*V)[i + (size_t)p * n] = s;
+                }
+        }
+        return;
+    }
+    fail(PPA_ERR_NUMERIC, "dense_eig: QR iteration did not converge (n=%d)", n);
 }
 
 void hessenberg_eigvals(int n, std::vector<double>& h, std::vector<cplx>& w) {
     Mat H(n, n);
     H.a = h;
-    if (!schur(H, nullptr, w)) fail(PPA_ERR_NUMERIC, "QR iteration did not converge (n=%d)", n);
+    if (schur(H, nullptr, w)) return;
+    // fall back to the general path (retries on similar matrices)
+    dense_eig(n, h.data(), w, nullptr);
 }
 
 bool lu_solve(int n, std::vector<double> M, std::vector<double>& b) {

@@ -90,3 +90,22 @@ def test_host_leja_matches_oracle(cdll, seed):
     th = np.array(th, dtype=complex)
     rng.shuffle(th)
     assert np.array_equal(ppa.leja_order(th), O.leja_order(th))
+
+
+def test_host_eigvecs_accurate_on_restarted_arnoldi(cdll):
+    """After a thick restart H_m is nearly block triangular (tiny spike row);
+    the host eigenvectors must stay accurate in norm, which the restart basis
+    and the Ritz test rely on."""
+    import oracle as O
+    from paper_1806_08020_amd import ppa
+    from paper_1806_08020_amd import workloads as W
+    csr = W.convdiff_2d(36, 0.6)
+    b, v0 = W.start_vectors(csr.n, 21)
+    mats = []
+    O.pp_eigs(csr, b, v0, m=38, k=19, nev=14, d=27, rtol=1e-12, max_cycles=6,
+              hook=lambda ev, V, H, j: mats.append(H[:j, :j].copy()) if ev == "cycle" else None)
+    assert len(mats) >= 3
+    for Hm in mats:
+        w, V = ppa.dense_eig(Hm)
+        R = Hm @ V - V * w
+        assert np.linalg.norm(R, axis=0).max() <= 1e-13 * np.linalg.norm(Hm)
