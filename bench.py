@@ -60,13 +60,6 @@ def make_matrix(cfg):
     return getattr(W, name)(*args)
 
 
-def pass_bytes(n, nnz, val_bytes, vec_bytes):
-    """Algorithmic bytes of one fused SpMV + axpy pass: CSR arrays once
-    (values, int32 column indices, int32 row pointers), the gathered vector
-    once, the streamed vector once, the output once."""
-    return nnz * (val_bytes + 4) + 4 * (n + 1) + 3 * n * vec_bytes
-
-
 def cpu_baseline(csr, roots, bytes_per_apply, budget_s):
     import oracle as O
     mv = O.csr_matvec(csr)
@@ -110,6 +103,43 @@ def copy_probe(torch, reps):
                       "GBps": round(2 * 8 * n / ms / 1e6, 1)}), flush=True)
 
 
+def served_mix_report(count):
+    """Served mix (2-D convection-diffusion solves of random size, degree and
+    nev, seeded): capacity from a closed-loop run (all requests at t = 0),
+    then Poisson arrivals at 0.7 x capacity, FP64 and mixed precision (mixed
+    applies to the single-solve path; the batched small solves run FP64)."""
+    from paper_1806_08020_amd import serve as S
+    reqs = S.served_mix(count=count, seed=5, rate=1e9, max_cycles=30)
+    budget = 200 * 2**30
+
+    def run(rs):
+        srv = S.Server(hbm_budget=budget, max_slots=256, small_n=16384, stream_workers=3)
+        t0 = time.perf_counter()
+        done = srv.run(rs)
+        wall = time.perf_counter() - t0
+        srv.close()
+        out = S.summarize(done, wall)
+        out.update(srv.stats)
+        return out
+
+    for r in reqs:
+        r.arrival = 0.0
+    closed = run(reqs)
+    capacity = count / closed["wall_s"]
+    rate = 0.7 * capacity
+    rng = np.random.default_rng([5, 3])
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    rep = {"requests": count, "capacity_req_per_s": round(capacity, 2), "rate_req_per_s": round(rate, 2),
+           "closed_loop": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in closed.items()}}
+    for prec in ("f64", "mixed"):
+        for r, t in zip(reqs, arr):
+            r.arrival = float(t)
+            r.precision = prec
+        o = run(reqs)
+        rep[prec] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in o.items()}
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +151,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy instead (HBM counter calibration)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the solve in the other precision (mixed vs FP64)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served mix")
+    ap.add_argument("--serve-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -141,9 +175,6 @@ def main():
     bt = torch.as_tensor(b, device="cuda")
     vt = torch.as_tensor(v0, device="cuda")
     dbl = isinstance(cfg["d"], tuple)
-    pb64 = pass_bytes(csr.n, csr.nnz, 8, 8)
-    pb32 = pass_bytes(csr.n, csr.nnz, 4, 4)
-    pb = pb64 if prec == "f64" else pb32
 
     def one_step():
         if dbl:
@@ -172,7 +203,7 @@ def main():
     passes = sum(r.spmv_passes for r in results)
     passes32 = sum(r.spmv_passes_f32 for r in results)
     t_apply = sum(r.t_apply_ms for r in results) / 1e3
-    pi_bytes = passes32 * pb32 + (passes - passes32) * pb64
+    pi_bytes = sum(r.spmv_bytes for r in results)
     value = pi_bytes / wall / 1e9
     kern_gbs = (pi_bytes / t_apply / 1e9) if t_apply > 0 else None
     avg_pass_us = t_apply / passes * 1e6 if passes else None
@@ -200,6 +231,8 @@ def main():
         "eigenpairs_per_s": round(nconv / wall, 4),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+        "latency_note": "latency_ms: per whole solve of the headline workload; served.*.p50_ms/p99_ms: "
+                        "arrival-to-result latency of the served mix",
         "solve": {"converged": [bool(r.converged) for r in results], "nconv": [r.nconv for r in results],
                   "cycles": [r.cycles for r in results],
                   "max_resid_rel": [r.max_resid / A.norm_inf for r in results],
@@ -214,9 +247,37 @@ def main():
                      "avg_launch_us": round(avg_pass_us, 3) if avg_pass_us else None,
                      "launches": passes},
     }
+    line["eigenpairs_per_s_by_precision"] = {prec: round(nconv / wall, 4)}
+    if not args.no_compare:
+        alt = "mixed" if prec == "f64" else "f64"
+        if alt == "mixed" and not A.has_f32:
+            A = ppa.Matrix(csr, want_f32=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        if dbl:
+            Pa = ppa.Poly.build_double(A, cfg["d"][0], cfg["d"][1], bt)
+        else:
+            Pa = ppa.Poly.build(A, cfg["d"], bt)
+        ra = ppa.eigs(A, Pa, vt, cfg["m"], cfg["k"], cfg["nev"], rtol=1e-8, max_cycles=args.max_cycles,
+                      precision=alt)
+        torch.cuda.synchronize()
+        wa = time.perf_counter() - ta
+        line["eigenpairs_per_s_by_precision"][alt] = round(ra.nconv / wa, 4)
+        r0 = results[-1]
+        line["precision_compare"] = {
+            "ms_per_solve": {prec: round(wall / args.steps * 1e3, 2), alt: round(wa * 1e3, 2)},
+            "converged": {prec: r0.nconv, alt: ra.nconv},
+            "cycles": {prec: r0.cycles, alt: ra.cycles},
+            "fp32_cycles": {prec: r0.fp32_cycles, alt: ra.fp32_cycles},
+            "max_resid_rel": {prec: r0.max_resid / A.norm_inf, alt: ra.max_resid / A.norm_inf},
+            "max_rel_diff_sorted_eigenvalues": float(np.max(np.abs(np.sort_complex(ra.mu) - np.sort_complex(r0.mu))
+                                                            / np.abs(np.sort_complex(r0.mu)))),
+        }
+    if not args.no_serve:
+        line["served"] = served_mix_report(args.serve_requests)
     if not args.no_cpu_baseline:
         roots = (P.roots(1), P.roots(2)) if dbl else P.roots()
-        bpa = pb64 * (cfg["d"][0] * cfg["d"][1] if dbl else cfg["d"])
+        bpa = ppa.apply_bytes(A, P, "f64")
         reps, dt, gbs = cpu_baseline(csr, roots, bpa, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{reps} FP64 pi(A)v applications of the same polynomial on "

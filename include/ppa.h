@@ -151,6 +151,13 @@ int ppa_poly_apply_workspace_bytes(const ppa_matrix* A, const ppa_poly* p, int p
 int ppa_poly_apply(const ppa_matrix* A, const ppa_poly* p, int precision,
                    const void* v_d, void* y_d, void* ws_d, size_t ws_bytes, void* stream);
 
+/* Algorithmic HBM bytes of one ppa_poly_apply in `precision`, summed over its
+ * fused passes: the CSR arrays once per pass (values, int32 column indices,
+ * int32 row pointers), each distinct input vector once and the output once.
+ * A real root moves 2 vectors, a conjugate pair 2 + 3.  Host only: launches
+ * nothing. */
+int ppa_poly_apply_bytes(const ppa_matrix* A, const ppa_poly* p, int precision, double* bytes);
+
 /* One fused pass, the building block of ppa_poly_apply:
  *   out = alpha x + beta (A u) + gamma z + delta z2
  * (x, z, z2 may be NULL, dropping their term).  Types: in_f32 selects
@@ -225,6 +232,8 @@ typedef struct ppa_eigs_result {
     int reserved;
     int64_t spmv_passes; /* fused SpMV passes issued by the operator applications */
     int64_t spmv_passes_f32; /* of which with FP32 values and vectors (PPA_MIXED) */
+    double spmv_bytes;   /* algorithmic bytes of those passes: CSR arrays once, each
+                            distinct input vector once, the output once, per pass */
     double t_apply_ms;   /* PPA_FLAG_TIMING: device time of all operator applications */
     double t_cgs_ms;     /* PPA_FLAG_TIMING: device time of all CGS2 steps   */
 } ppa_eigs_result;

@@ -271,6 +271,17 @@ int ppa_poly_apply(const ppa_matrix* h, const ppa_poly* ph, int precision, const
     });
 }
 
+int ppa_poly_apply_bytes(const ppa_matrix* h, const ppa_poly* ph, int precision, double* bytes) {
+    return guarded([&] {
+        PPA_REQUIRE(h && ph && bytes, "matrix, poly and bytes are required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be F64 or F32");
+        const Matrix& A = *reinterpret_cast<const Matrix*>(h);
+        *bytes = (double)apply_poly_bytes(A, *reinterpret_cast<const Poly*>(ph),
+                                          precision == PPA_F64 ? VecT::F64 : VecT::F32);
+        return PPA_OK;
+    });
+}
+
 int ppa_fused_spmv(const ppa_matrix* h, int in_f32, int out_f32, double alpha, const void* x_d,
                    double beta, const void* u_d, double gamma, const void* z_d, double delta,
                    const void* z2_d, void* out_d, void* stream) {

@@ -259,6 +259,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         }
     }
     int64_t mvps = 0, dots = 0, vops = 0, passes = 0, passes32 = 0;
+    double spmv_bytes = 0.0;
     bool fp32 = o.precision == PPA_MIXED;
     const bool timing = (o.flags & PPA_FLAG_TIMING) != 0;
     struct Events {
@@ -276,12 +277,12 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
 
     auto apply_op = [&](const double* x, double* y) {
         if (!p) {
-            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, x, 0.0, nullptr, 0.0,
-                              nullptr, y, s);
+            spmv_bytes += launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, x, 0.0, nullptr,
+                                            0.0, nullptr, y, s);
         } else if (fp32) {
-            apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F32, e.aw32, s);
+            spmv_bytes += apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F32, e.aw32, s);
         } else {
-            apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F64, e.aw64, s);
+            spmv_bytes += apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F64, e.aw64, s);
         }
         mvps += op_mvps;
         vops += op_vops;
@@ -490,6 +491,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     r.fp32_cycles = fp32_cycles;
     r.spmv_passes = passes;
     r.spmv_passes_f32 = passes32;
+    r.spmv_bytes = spmv_bytes;
     r.t_apply_ms = t_apply;
     r.t_cgs_ms = t_cgs;
     if (converged) return PPA_OK;

@@ -112,9 +112,14 @@ struct Chain {
     VecT ct;            // chain element type
     hipStream_t s;
     std::vector<void*> pool;
+    size_t bytes = 0;
+    bool dry = false;   // count bytes only
     void pass(double alpha, const void* x, double beta, const void* u, double gamma, const void* z,
               double delta, const void* z2, void* out, VecT out_t) {
-        launch_fused_spmv(A, ct, out_t, alpha, x, beta, u, gamma, z, delta, z2, out, s);
+        if (dry)
+            bytes += fused_spmv_bytes(A, ct, out_t, x, u, z, z2);
+        else
+            bytes += launch_fused_spmv(A, ct, out_t, alpha, x, beta, u, gamma, z, delta, z2, out, s);
     }
 };
 
@@ -168,32 +173,21 @@ void pi_chain(Chain& ch, const std::vector<cplx>& roots, const void* u0, double 
 
 }  // namespace
 
-void apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
-                           double* y, double c, double gamma, const double* z, ApplyWs& ws,
-                           hipStream_t s) {
+size_t apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
+                             double* y, double c, double gamma, const double* z, ApplyWs& ws,
+                             hipStream_t s) {
     PPA_REQUIRE(!roots.empty(), "apply: empty polynomial");
     Chain ch{A, VecT::F64, s, {}};
     for (int i = 0; i < 4; ++i) ch.pool.push_back(ws.buf[i]);
     pi_chain(ch, roots, v, c, gamma, z, 0.0, nullptr, y, VecT::F64, {v, z});
+    return ch.bytes;
 }
 
-void apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vout, void* y,
-                VecT chain, ApplyWs& ws, hipStream_t s) {
-    PPA_REQUIRE(p.degree() >= 1, "apply: empty polynomial");
-    Chain ch{A, chain, s, {}};
-    const int nb = apply_buffers(p);
-    for (int i = 0; i < nb; ++i) ch.pool.push_back(ws.buf[i]);
-    const void* v0 = v;
-    if (vin != chain) {
-        // bring the input into the chain precision (one streaming pass)
-        void* cv = ch.pool.back();
-        ch.pool.pop_back();
-        if (chain == VecT::F32)
-            launch_cast_f64_f32((const double*)v, (float*)cv, A.n, s);
-        else
-            launch_cast_f32_f64((const float*)v, (double*)cv, A.n, s);
-        v0 = cv;
-    }
+namespace {
+
+// pi(A) v0 -> y through the chain's buffer pool (single or double polynomial)
+void run_apply(Chain& ch, const Poly& p, const void* v0, VecT vout, void* y) {
+    const VecT chain = ch.ct;
     if (!p.is_double()) {
         pi_chain(ch, p.roots, v0, 1.0, 0.0, nullptr, 0.0, nullptr, y, vout, {v0});
         return;
@@ -240,6 +234,41 @@ void apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vo
             i += 2;
         }
     }
+}
+
+}  // namespace
+
+size_t apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vout, void* y,
+                  VecT chain, ApplyWs& ws, hipStream_t s) {
+    PPA_REQUIRE(p.degree() >= 1, "apply: empty polynomial");
+    Chain ch{A, chain, s, {}};
+    const int nb = apply_buffers(p);
+    for (int i = 0; i < nb; ++i) ch.pool.push_back(ws.buf[i]);
+    const void* v0 = v;
+    if (vin != chain) {
+        // bring the input into the chain precision (one streaming pass)
+        void* cv = ch.pool.back();
+        ch.pool.pop_back();
+        if (chain == VecT::F32)
+            launch_cast_f64_f32((const double*)v, (float*)cv, A.n, s);
+        else
+            launch_cast_f32_f64((const float*)v, (double*)cv, A.n, s);
+        v0 = cv;
+    }
+    run_apply(ch, p, v0, vout, y);
+    return ch.bytes;
+}
+
+size_t apply_poly_bytes(const Matrix& A, const Poly& p, VecT chain) {
+    PPA_REQUIRE(p.degree() >= 1, "apply: empty polynomial");
+    Chain ch{A, chain, nullptr, {}};
+    ch.dry = true;
+    // stand-in addresses: only their identity matters for the count
+    static char tags[8];
+    const int nb = apply_buffers(p);
+    for (int i = 0; i < nb; ++i) ch.pool.push_back(&tags[i]);
+    run_apply(ch, p, &tags[6], chain, &tags[7]);
+    return ch.bytes;
 }
 
 }  // namespace ppa

@@ -114,8 +114,12 @@ inline int64_t col_ld(int64_t n) { return round_up(n, 32); }
 // ---------------------------------------------------------------- kernels
 enum class VecT { F64, F32 };
 
-// out = alpha x + beta (A u) + gamma z + delta z2   (x, z, z2 may be null)
-void launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
+// out = alpha x + beta (A u) + gamma z + delta z2   (x, z, z2 may be null).
+// Returns the pass's algorithmic bytes: CSR arrays once (values, int32 column
+// indices, int32 row pointers), each distinct input vector once, the output once.
+size_t fused_spmv_bytes(const Matrix& A, VecT in, VecT out, const void* x, const void* u,
+                        const void* z, const void* z2);
+size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
                        double beta, const void* u, double gamma, const void* z, double delta,
                        const void* z2, void* o, hipStream_t s);
 void matrix_setup(Matrix& A, hipStream_t s);   // validate, norm, partition
@@ -196,13 +200,17 @@ int apply_buffers(const Poly& p);
 void carve_apply(Carver& c, int64_t n, const Poly& p, VecT t, ApplyWs& ws);
 // in/out types: vin/vout select the element type of v and y; the chain runs in
 // `chain` precision (F32 chain = FP32 matrix values).
-void apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vout, void* y,
-                VecT chain, ApplyWs& ws, hipStream_t s);
+// Algorithmic bytes of the fused SpMV passes of one apply_poly with chain
+// element type `chain` (nothing is launched).
+size_t apply_poly_bytes(const Matrix& A, const Poly& p, VecT chain);
+// Returns the algorithmic bytes of its fused SpMV passes.
+size_t apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT vout, void* y,
+                  VecT chain, ApplyWs& ws, hipStream_t s);
 // y = c * pi(A) v + gamma z for a single root list, all FP64 (the operator
 // tau(A) = I - pi_1(A) of section 8 is c = -1, gamma = 1, z = v).
-void apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
-                           double* y, double c, double gamma, const double* z, ApplyWs& ws,
-                           hipStream_t s);
+size_t apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
+                             double* y, double c, double gamma, const double* z, ApplyWs& ws,
+                             hipStream_t s);
 // ---------------------------------------------------------------- projected problem (ritz.cpp)
 // Ordering of Ritz values (section 4): increasing |target - nu|, ties larger
 // Im first, then smaller Re.  target = 1 for pi(A), 0 for A itself.

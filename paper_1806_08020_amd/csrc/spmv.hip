@@ -200,15 +200,37 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
     PPA_HIP(hipGetLastError());
 }
 
-void launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
-                       double beta, const void* u, double gamma, const void* z, double delta,
-                       const void* z2, void* o, hipStream_t s) {
+// distinct input vectors among x, u, z, z2 (u always present)
+static int distinct_inputs(const void* x, const void* u, const void* z, const void* z2) {
+    const void* v[4] = {u, x, z, z2};
+    int cnt = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (!v[i]) continue;
+        bool seen = false;
+        for (int j = 0; j < i; ++j) seen |= (v[j] == v[i]);
+        cnt += seen ? 0 : 1;
+    }
+    return cnt;
+}
+
+size_t fused_spmv_bytes(const Matrix& A, VecT in, VecT out, const void* x, const void* u,
+                        const void* z, const void* z2) {
+    const size_t sv = (in == VecT::F64 && out == VecT::F64) ? 8 : 4;
+    const size_t sin = in == VecT::F64 ? 8 : 4, sout = out == VecT::F64 ? 8 : 4;
+    return (size_t)A.nnz * (sv + 4) + 4 * (size_t)(A.n + 1) +
+           (size_t)A.n * (sin * distinct_inputs(x, u, z, z2) + sout);
+}
+
+size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
+                         double beta, const void* u, double gamma, const void* z, double delta,
+                         const void* z2, void* o, hipStream_t s) {
     PPA_REQUIRE(u != nullptr && o != nullptr, "fused spmv: u and out are required");
     PPA_REQUIRE(o != u, "fused spmv: out must not alias u");
+    const size_t bytes = fused_spmv_bytes(A, in, out, x, u, z, z2);
     if (in == VecT::F64 && out == VecT::F64) {
         run_fused<double, double, double>(A, A.v64, A.win64, alpha, x, beta, u, gamma, z, delta, z2,
                                           o, s);
-        return;
+        return bytes;
     }
     PPA_REQUIRE(A.v32 != nullptr, "FP32 path needs FP32 matrix values (want_f32 at create)");
     const Window& W = A.win32;
@@ -220,6 +242,7 @@ void launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const v
         run_fused<float, float, double>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else
         run_fused<float, double, double>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+    return bytes;
 }
 
 // ---------------------------------------------------------------- setup

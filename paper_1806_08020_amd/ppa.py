@@ -41,7 +41,7 @@ class EigsResult(C.Structure):
                 ("nconv", C.c_int), ("cycles", C.c_int), ("mvps", C.c_int64),
                 ("dots", C.c_int64), ("vops", C.c_int64), ("max_resid", C.c_double),
                 ("fp32_cycles", C.c_int), ("reserved", C.c_int),
-                ("spmv_passes", C.c_int64), ("spmv_passes_f32", C.c_int64),
+                ("spmv_passes", C.c_int64), ("spmv_passes_f32", C.c_int64), ("spmv_bytes", C.c_double),
                 ("t_apply_ms", C.c_double), ("t_cgs_ms", C.c_double)]
 
 
@@ -74,6 +74,7 @@ def _load():
         "ppa_poly_build_double": (i, [vp, i, i, vp, vp, sz, vp, P(vp)]),
         "ppa_poly_apply_workspace_bytes": (i, [vp, vp, i, P(sz)]),
         "ppa_poly_apply": (i, [vp, vp, i, vp, vp, vp, sz, vp]),
+        "ppa_poly_apply_bytes": (i, [vp, vp, i, P(d)]),
         "ppa_fused_spmv": (i, [vp, i, i, d, vp, d, vp, d, vp, d, vp, vp, vp]),
         "ppa_cgs2_workspace_bytes": (i, [i64, i, P(sz)]),
         "ppa_cgs2": (i, [i64, i, vp, i64, vp, P(d), P(d), vp, sz, vp]),
@@ -253,6 +254,13 @@ def apply(A: Matrix, p: Poly, v: torch.Tensor, precision: str = "f64", out=None,
     return y
 
 
+def apply_bytes(A: Matrix, p: Poly, precision: str = "f64") -> float:
+    """Algorithmic HBM bytes of one pi(A)v application (nothing is launched)."""
+    b = C.c_double()
+    _check(_lib.ppa_poly_apply_bytes(A.h, p.h, _PREC[precision], C.byref(b)))
+    return b.value
+
+
 def apply_workspace(A: Matrix, p: Poly, precision: str = "f64"):
     nb = C.c_size_t()
     _check(_lib.ppa_poly_apply_workspace_bytes(A.h, p.h, _PREC[precision], C.byref(nb)))
@@ -317,6 +325,7 @@ class EigsOut:
     fp32_cycles: int
     spmv_passes: int = 0
     spmv_passes_f32: int = 0
+    spmv_bytes: float = 0.0
     t_apply_ms: float = 0.0
     t_cgs_ms: float = 0.0
     X: torch.Tensor | None = None
@@ -351,7 +360,7 @@ def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, 
     return EigsOut(status=st, mu=lre + 1j * lim, resid=res.copy(), nu=nre + 1j * nim, nconv=r.nconv,
                    cycles=r.cycles, mvps=r.mvps, dots=r.dots, vops=r.vops, max_resid=r.max_resid,
                    fp32_cycles=r.fp32_cycles, spmv_passes=r.spmv_passes,
-                   spmv_passes_f32=r.spmv_passes_f32, t_apply_ms=r.t_apply_ms,
+                   spmv_passes_f32=r.spmv_passes_f32, spmv_bytes=r.spmv_bytes, t_apply_ms=r.t_apply_ms,
                    t_cgs_ms=r.t_cgs_ms, X=X, converged=(st == PPA_OK))
 
 

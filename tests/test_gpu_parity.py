@@ -166,6 +166,32 @@ def test_apply_complex_pairs(lib):
     assert np.max(np.abs(y - ref)) <= chain_tol(csr, roots, g, EPS64)
 
 
+def test_apply_bytes_closed_form(lib):
+    """Algorithmic bytes of one application: CSR arrays once per pass (8 or 4
+    bytes per value, 4 per column index, 4(n+1) row pointers), and per real
+    root two vectors (in, out), per conjugate pair 2 + 3 vectors.  The solver's
+    reported total is passes x this."""
+    csr = W.convdiff_2d(30, 1.6)
+    mv = O.csr_matvec(csr)
+    b, v = W.start_vectors(csr.n, 5)
+    roots, _ = O.gmres_poly(mv, b, 14)
+    npair = int(np.sum(roots.imag > 0))
+    nreal = len(roots) - 2 * npair
+    assert npair > 0 and nreal > 0
+    A = lib.Matrix(csr, want_f32=True)
+    P = lib.Poly.from_roots(roots)
+    for prec, sv in (("f64", 8), ("f32", 4)):
+        csr_b = csr.nnz * (sv + 4) + 4 * (csr.n + 1)
+        want = len(roots) * csr_b + csr.n * sv * (2 * nreal + 5 * npair)
+        assert lib.apply_bytes(A, P, prec) == want
+    r = lib.eigs(A, P, dev(v), m=20, k=10, nev=4, rtol=1e-8, max_cycles=3)
+    assert r.spmv_passes > 0
+    per_apply = lib.apply_bytes(A, P, "f64")
+    napply = r.spmv_passes // len(roots)
+    assert napply * len(roots) == r.spmv_passes
+    assert r.spmv_bytes == napply * per_apply
+
+
 def test_apply_double_poly(lib):
     csr = MATS["cd2_37"]
     mv = O.csr_matvec(csr)
