@@ -47,20 +47,24 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Epilogue values of one row, loaded ahead of the product phase.
+// Epilogue operands of one row, loaded ahead of the product phase.  The raw
+// row pointers are kept (not yet offset by the block start) so that nothing
+// consumes a loaded value before the gathers are issued: every load of a
+// block is in flight at once.
 template <typename VT>
 struct RowPre {
     int a, e;
     VT x, z, z2;
 };
 
+// Loads for row r (must be a valid row; callers clamp and mask).
 template <typename VT, typename IT>
-__device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr, int r, int p0,
+__device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr, int r,
                                               const IT* __restrict__ x, const IT* __restrict__ z,
                                               const IT* __restrict__ z2) {
     RowPre<VT> q;
-    q.a = rowptr[r] - p0;
-    q.e = rowptr[r + 1] - p0;
+    q.a = rowptr[r];
+    q.e = rowptr[r + 1];
     q.x = x ? (VT)x[r] : (VT)0;
     q.z = z ? (VT)z[r] : (VT)0;
     q.z2 = z2 ? (VT)z2[r] : (VT)0;
@@ -68,11 +72,46 @@ __device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr
 }
 
 template <typename VT, typename OT>
-__device__ __forceinline__ void row_out(const RowPre<VT>& q, const VT* prod, int r, OT* out,
+__device__ __forceinline__ void row_out(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
                                         VT alpha, VT beta, VT gamma, VT delta) {
     VT s = 0;
-    for (int k = q.a; k < q.e; ++k) s += prod[k];
+    for (int k = q.a - p0; k < q.e - p0; ++k) s += prod[k];
     out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
+}
+
+// One row longer than the block's nonzero budget: r1 == r0 + 1, reduced
+// across the block (per-thread strided partial sums, then a fixed tree).
+template <typename VT, typename IT, typename OT, int BS>
+__device__ __forceinline__ void long_row(const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ colind,
+                                         const VT* __restrict__ val, int r0, int p0, int p1,
+                                         const IT* __restrict__ x, const IT* __restrict__ u,
+                                         const IT* __restrict__ z, const IT* __restrict__ z2,
+                                         OT* __restrict__ out, VT alpha, VT beta, VT gamma,
+                                         VT delta, VT* red) {
+    const int tid = threadIdx.x;
+    VT s = 0;
+    int i = p0 + tid;
+    // four independent loads in flight per step; accumulation order unchanged
+    for (; i + 3 * BS < p1; i += 4 * BS) {
+        const int c0 = colind[i], c1 = colind[i + BS], c2 = colind[i + 2 * BS], c3 = colind[i + 3 * BS];
+        const VT v0 = val[i], v1 = val[i + BS], v2 = val[i + 2 * BS], v3 = val[i + 3 * BS];
+        const VT g0 = (VT)u[c0], g1 = (VT)u[c1], g2 = (VT)u[c2], g3 = (VT)u[c3];
+        s += v0 * g0;
+        s += v1 * g1;
+        s += v2 * g2;
+        s += v3 * g3;
+    }
+    for (; i < p1; i += BS) s += val[i] * (VT)u[colind[i]];
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+        VT t = 0;
+        for (int w = 0; w < BS / 64; ++w) t += red[w];
+        const RowPre<VT> q = row_pre<VT>(rowptr, r0, x, z, z2);
+        out[r0] = (OT)(beta * t + alpha * q.x + gamma * q.z + delta * q.z2);
+    }
 }
 
 template <typename VT, typename IT, typename OT>
@@ -88,54 +127,52 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     const int p0 = rowptr[r0], p1 = rowptr[r1];
     const int cnt = p1 - p0;
     const int tid = threadIdx.x;
-    if (cnt <= SPMV_CHUNK) {
-        constexpr int PER = SPMV_CHUNK / SPMV_BS;
-        int32_t c[PER];
-        VT v[PER];
+    if (cnt > SPMV_CHUNK) {
+        long_row<VT, IT, OT, SPMV_BS>(rowptr, colind, val, r0, p0, p1, x, u, z, z2, out, alpha,
+                                      beta, gamma, delta, red);
+        return;
+    }
+    constexpr int PER = SPMV_CHUNK / SPMV_BS;
+    // Branch-free issue: positions past the block's range re-read its last
+    // nonzero (in range, already in cache) and are masked to zero below.
+    const int last = p0 + (cnt > 0 ? cnt - 1 : 0);
+    int32_t c[PER];
+    VT v[PER];
+    if (cnt > 0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int j = min(p0 + tid + k * SPMV_BS, last);
+            c[k] = __builtin_nontemporal_load(colind + j);
+            v[k] = __builtin_nontemporal_load(val + j);
+        }
+    }
+    // the thread's first two rows (clamped into the block; masked at use)
+    const int ra = r0 + tid, rb = r0 + tid + SPMV_BS;
+    const RowPre<VT> qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
+    const RowPre<VT> qb = row_pre<VT>(rowptr, min(rb, r1 - 1), x, z, z2);
+    if (cnt > 0) {
+        VT g[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) g[k] = (VT)u[c[k]];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + k * SPMV_BS;
-            if (i < cnt) {
-                c[k] = __builtin_nontemporal_load(colind + p0 + i);
-                v[k] = __builtin_nontemporal_load(val + p0 + i);
-            }
+            prod[i] = i < cnt ? v[k] * g[k] : (VT)0;
         }
-        // the thread's first two rows: epilogue operands ahead of the barrier
-        const int ra = r0 + tid, rb = r0 + tid + SPMV_BS;
-        RowPre<VT> qa, qb;
-        if (ra < r1) qa = row_pre<VT>(rowptr, ra, p0, x, z, z2);
-        if (rb < r1) qb = row_pre<VT>(rowptr, rb, p0, x, z, z2);
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = tid + k * SPMV_BS;
-            if (i < cnt) prod[i] = v[k] * (VT)u[c[k]];
-        }
-        __syncthreads();
-        if (ra < r1) row_out(qa, prod, ra, out, alpha, beta, gamma, delta);
-        if (rb < r1) row_out(qb, prod, rb, out, alpha, beta, gamma, delta);
-        for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
-            const RowPre<VT> q = row_pre<VT>(rowptr, r, p0, x, z, z2);
-            row_out(q, prod, r, out, alpha, beta, gamma, delta);
-        }
-    } else {
-        // one long row: r1 == r0 + 1
-        VT s = 0;
-        for (int i = p0 + tid; i < p1; i += SPMV_BS) s += val[i] * (VT)u[colind[i]];
-        s = wave_sum(s);
-        if ((tid & 63) == 0) red[tid >> 6] = s;
-        __syncthreads();
-        if (tid == 0) {
-            VT t = 0;
-            for (int w = 0; w < SPMV_BS / 64; ++w) t += red[w];
-            const RowPre<VT> q = row_pre<VT>(rowptr, r0, p0, x, z, z2);
-            out[r0] = (OT)(beta * t + alpha * q.x + gamma * q.z + delta * q.z2);
-        }
+    }
+    __syncthreads();
+    if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
+    if (rb < r1) row_out(qb, prod, p0, rb, out, alpha, beta, gamma, delta);
+    for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
+        const RowPre<VT> q = row_pre<VT>(rowptr, r, x, z, z2);
+        row_out(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
 }
 
 // Windowed variant: block b covers rows [blk[b], blk[b+1]) whose columns lie
 // in [meta[2b], meta[2b] + meta[2b+1]); dynamic LDS holds CH products and
-// the window.  The partition guarantees at most CH nonzeros per block.
+// the window.  The partition guarantees at most CH nonzeros per block and at
+// least one nonzero (no long rows; empty blocks have span 0).
 template <typename VT, typename IT, typename OT, int CH>
 __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
@@ -152,31 +189,44 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     const int cmin = meta[2 * b], span = meta[2 * b + 1];
     const int tid = threadIdx.x;
     constexpr int PER = CH / SPMV_WBS;
+    const int last = p0 + (cnt > 0 ? cnt - 1 : 0);
     int32_t c[PER];
     VT v[PER];
+    if (cnt > 0) {
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int i = tid + k * SPMV_WBS;
-        if (i < cnt) {
-            c[k] = __builtin_nontemporal_load(colind + p0 + i);
-            v[k] = __builtin_nontemporal_load(val + p0 + i);
+        for (int k = 0; k < PER; ++k) {
+            const int j = min(p0 + tid + k * SPMV_WBS, last);
+            c[k] = __builtin_nontemporal_load(colind + j);
+            v[k] = __builtin_nontemporal_load(val + j);
         }
     }
-    for (int i = tid; i < span; i += SPMV_WBS) win[i] = (VT)u[cmin + i];
-    const int ra = r0 + tid;
-    RowPre<VT> qa;
-    if (ra < r1) qa = row_pre<VT>(rowptr, ra, p0, x, z, z2);
-    __syncthreads();
+    // window copy, 8 loads in flight per thread per step (clamped, masked)
+    constexpr int WU = 8;
+    for (int base = 0; base < span; base += WU * SPMV_WBS) {
+        VT t[WU];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int i = tid + k * SPMV_WBS;
-        if (i < cnt) prod[i] = v[k] * win[c[k] - cmin];
+        for (int q = 0; q < WU; ++q) t[q] = (VT)u[cmin + min(base + tid + q * SPMV_WBS, span - 1)];
+#pragma unroll
+        for (int q = 0; q < WU; ++q) {
+            const int i = base + tid + q * SPMV_WBS;
+            if (i < span) win[i] = t[q];
+        }
+    }
+    const int ra = r0 + tid;
+    const RowPre<VT> qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
+    __syncthreads();
+    if (cnt > 0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * SPMV_WBS;
+            prod[i] = i < cnt ? v[k] * win[c[k] - cmin] : (VT)0;
+        }
     }
     __syncthreads();
-    if (ra < r1) row_out(qa, prod, ra, out, alpha, beta, gamma, delta);
+    if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
     for (int r = ra + SPMV_WBS; r < r1; r += SPMV_WBS) {
-        const RowPre<VT> q = row_pre<VT>(rowptr, r, p0, x, z, z2);
-        row_out(q, prod, r, out, alpha, beta, gamma, delta);
+        const RowPre<VT> q = row_pre<VT>(rowptr, r, x, z, z2);
+        row_out(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
 }
 
