@@ -68,6 +68,7 @@ struct Matrix {
     float* v32_owned = nullptr;
     int32_t* blk = nullptr;          // device, nblocks + 1 row starts
     int64_t nblocks = 0;
+    int align = 1;                   // block ranges start at multiples of this (1 or 4)
     double norm_inf = 0.0;
     int device = 0;
     Window win64, win32;

@@ -114,53 +114,144 @@ __device__ __forceinline__ void long_row(const int32_t* __restrict__ rowptr,
     }
 }
 
-template <typename VT, typename IT, typename OT>
+// G consecutive elements from a (G * sizeof(T))-aligned address, or, for a
+// group that runs past the end of the array (`full` false), element by
+// element with the index clamped to `lastidx` (masked by the caller).
+template <int G, typename T>
+struct Grp {
+    T v[G];
+};
+template <int G, typename T>
+__device__ __forceinline__ Grp<G, T> load_grp(const T* __restrict__ p, int idx, bool full,
+                                              int lastidx) {
+    Grp<G, T> r;
+    if constexpr (G == 1) {
+        r.v[0] = __builtin_nontemporal_load(p + min(idx, lastidx));
+    } else {
+        typedef T vec_t __attribute__((ext_vector_type(G)));
+        if (full) {
+            const vec_t a = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(p + idx));
+#pragma unroll
+            for (int j = 0; j < G; ++j) r.v[j] = a[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < G; ++j) r.v[j] = p[min(idx + j, lastidx)];
+        }
+    }
+    return r;
+}
+// FP64 values of a group of four: two 16-byte loads.
+template <>
+__device__ __forceinline__ Grp<4, double> load_grp<4, double>(const double* __restrict__ p, int idx,
+                                                              bool full, int lastidx) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    Grp<4, double> r;
+    if (full) {
+        const d2 a = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p + idx));
+        const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p + idx) + 1);
+        r.v[0] = a.x;
+        r.v[1] = a.y;
+        r.v[2] = b.x;
+        r.v[3] = b.y;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.v[j] = p[min(idx + j, lastidx)];
+    }
+    return r;
+}
+
+// Main fused kernel.  Each thread reads column indices and values as groups
+// of G consecutive nonzeros (16-byte loads for G = 4 and 4-byte indices);
+// groups start at the block's first nonzero rounded down to a multiple of G
+// (the partition guarantees that this aligned range holds at most
+// SPMV_CHUNK entries).  Positions outside the block are masked to zero, the
+// products land in LDS at their aligned position and each thread sums whole
+// rows from an offset view.  Every load of the block is issued before the
+// first gathered value is used.
+template <typename VT, typename IT, typename OT, int G>
 __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const VT* __restrict__ val, const int32_t* __restrict__ blk, int nblk,
+    const VT* __restrict__ val, const int32_t* __restrict__ blk, int nblk, int nnz,
     const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
     const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
-    __shared__ VT prod[SPMV_CHUNK];
+    constexpr int PER = SPMV_CHUNK / SPMV_BS;
+    static_assert(PER % G == 0, "groups must tile the per-thread share");
+    constexpr int NG = PER / G;
+    __shared__ __align__(16) VT prod_ext[SPMV_CHUNK];
     __shared__ VT red[SPMV_BS / 64];
     const int b = xcd_remap(blockIdx.x, nblk);
     const int r0 = blk[b], r1 = blk[b + 1];
     const int p0 = rowptr[r0], p1 = rowptr[r1];
-    const int cnt = p1 - p0;
     const int tid = threadIdx.x;
-    if (cnt > SPMV_CHUNK) {
+    const int base = p0 & ~(G - 1);
+    if (p1 - base > SPMV_CHUNK) {
+        // only a block of one row can exceed the budget (partition invariant)
         long_row<VT, IT, OT, SPMV_BS>(rowptr, colind, val, r0, p0, p1, x, u, z, z2, out, alpha,
                                       beta, gamma, delta, red);
         return;
     }
-    constexpr int PER = SPMV_CHUNK / SPMV_BS;
-    // Branch-free issue: positions past the block's range re-read its last
-    // nonzero (in range, already in cache) and are masked to zero below.
-    const int last = p0 + (cnt > 0 ? cnt - 1 : 0);
-    int32_t c[PER];
-    VT v[PER];
-    if (cnt > 0) {
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int j = min(p0 + tid + k * SPMV_BS, last);
-            c[k] = __builtin_nontemporal_load(colind + j);
-            v[k] = __builtin_nontemporal_load(val + j);
-        }
-    }
-    // the thread's first two rows (clamped into the block; masked at use)
     const int ra = r0 + tid, rb = r0 + tid + SPMV_BS;
-    const RowPre<VT> qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
-    const RowPre<VT> qb = row_pre<VT>(rowptr, min(rb, r1 - 1), x, z, z2);
-    if (cnt > 0) {
-        VT g[PER];
+    RowPre<VT> qa, qb;
+    if constexpr (G == 1) {
+        // positions past the block re-read its last nonzero (masked below)
+        const int cnt = p1 - p0, last = p1 - 1;
+        int32_t c[PER];
+        VT v[PER];
+        if (cnt > 0) {
 #pragma unroll
-        for (int k = 0; k < PER; ++k) g[k] = (VT)u[c[k]];
+            for (int k = 0; k < PER; ++k) {
+                const int j = min(p0 + tid + k * SPMV_BS, last);
+                c[k] = __builtin_nontemporal_load(colind + j);
+                v[k] = __builtin_nontemporal_load(val + j);
+            }
+        }
+        // the thread's first two rows (clamped into the block; masked at use)
+        qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
+        qb = row_pre<VT>(rowptr, min(rb, r1 - 1), x, z, z2);
+        if (cnt > 0) {
+            VT g[PER];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = tid + k * SPMV_BS;
-            prod[i] = i < cnt ? v[k] * g[k] : (VT)0;
+            for (int k = 0; k < PER; ++k) g[k] = (VT)u[c[k]];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int i = tid + k * SPMV_BS;
+                prod_ext[i] = i < cnt ? v[k] * g[k] : (VT)0;
+            }
+        }
+    } else {
+        const int gmax = (p1 - base - 1) / G;   // last group holding a nonzero of the block
+        Grp<G, int32_t> c[NG];
+        Grp<G, VT> v[NG];
+        if (p1 > p0) {
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                const int idx = base + G * min(tid + k * SPMV_BS, gmax);
+                const bool full = idx + G <= nnz;
+                c[k] = load_grp<G>(colind, idx, full, nnz - 1);
+                v[k] = load_grp<G>(val, idx, full, nnz - 1);
+            }
+        }
+        qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
+        qb = row_pre<VT>(rowptr, min(rb, r1 - 1), x, z, z2);
+        if (p1 > p0) {
+            VT g[NG][G];
+#pragma unroll
+            for (int k = 0; k < NG; ++k)
+#pragma unroll
+                for (int j = 0; j < G; ++j) g[k][j] = (VT)u[c[k].v[j]];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                const int pos = G * (tid + k * SPMV_BS);
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int e = base + pos + j;
+                    prod_ext[pos + j] = (e >= p0 && e < p1) ? v[k].v[j] * g[k][j] : (VT)0;
+                }
+            }
         }
     }
     __syncthreads();
+    const VT* prod = prod_ext + (p0 - base);
     if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
     if (rb < r1) row_out(qb, prod, p0, rb, out, alpha, beta, gamma, delta);
     for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
@@ -242,10 +333,24 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
                            (int)W.nblocks, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2,
                            (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
     } else {
-        hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT>), dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0,
-                           s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks, (const IT*)x,
-                           (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta,
-                           (VT)gamma, (VT)delta);
+#ifndef PPA_SPMV_G64
+#define PPA_SPMV_G64 1
+#endif
+#ifndef PPA_SPMV_G32
+#define PPA_SPMV_G32 4
+#endif
+        constexpr int G = sizeof(VT) == 8 ? PPA_SPMV_G64 : PPA_SPMV_G32;
+        const bool grp = G > 1 && A.align % G == 0 && reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
+        if (grp)
+            hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT, G>), dim3((unsigned)A.nblocks),
+                               dim3(SPMV_BS), 0, s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks,
+                               (int)A.nnz, (const IT*)x, (const IT*)u, (const IT*)z,
+                               (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+        else
+            hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT, 1>), dim3((unsigned)A.nblocks),
+                               dim3(SPMV_BS), 0, s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks,
+                               (int)A.nnz, (const IT*)x, (const IT*)u, (const IT*)z,
+                               (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
     }
     PPA_HIP(hipGetLastError());
 }
@@ -399,18 +504,19 @@ void launch_cast_f32_f64(const float* in, double* out, int64_t n, hipStream_t s)
     PPA_HIP(hipGetLastError());
 }
 
-// Greedy row-block partition: at most `chunk` nonzeros and `maxrows` rows per
-// block; a row longer than `chunk` forms a block of its own (returned via
-// *has_long).
+// Greedy row-block partition: each block's nonzero range, with its start
+// rounded down to a multiple of `align`, holds at most `chunk` entries, and a
+// block has at most `maxrows` rows; a row that does not fit alone forms a
+// block of its own (reported via *has_long).
 static std::vector<int32_t> partition(const std::vector<int32_t>& rp, int64_t n, int chunk,
-                                      int maxrows, bool* has_long) {
+                                      int maxrows, int align, bool* has_long) {
     std::vector<int32_t> blk;
     blk.reserve(n / 64 + 2);
     blk.push_back(0);
     int64_t r = 0;
     bool lg = false;
     while (r < n) {
-        const int64_t start = r, base = rp[r];
+        const int64_t start = r, base = rp[r] & ~(int64_t)(align - 1);
         if (rp[r + 1] - base > chunk) {
             ++r;
             lg = true;
@@ -449,7 +555,7 @@ static bool allow_lds(size_t bytes) {
 // the LDS size, but stays off until matrix_tune selects it.
 static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStream_t s) {
     bool lg = false;
-    std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, &lg);
+    std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, 1, &lg);
     if (lg) return;
     int maxlds = 0;
     PPA_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, A.device));
@@ -520,7 +626,10 @@ void matrix_setup(Matrix& A, hipStream_t s) {
                 "indices or non-finite values",
                 (long long)nbad);
     A.norm_inf = nrm;
-    std::vector<int32_t> blk = partition(rp, n, SPMV_CHUNK, SPMV_MAXROWS, nullptr);
+    // grouped loads: the partition aligns block ranges to the widest group
+    // the index array's alignment allows (values are checked at launch)
+    A.align = reinterpret_cast<uintptr_t>(A.colind) % 16 == 0 ? 4 : 1;
+    std::vector<int32_t> blk = partition(rp, n, SPMV_CHUNK, SPMV_MAXROWS, A.align, nullptr);
     A.nblocks = (int64_t)blk.size() - 1;
     PPA_HIP(hipMalloc(&A.blk, blk.size() * sizeof(int32_t)));
     PPA_HIP(hipMemcpyAsync(A.blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
