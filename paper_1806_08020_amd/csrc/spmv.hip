@@ -32,6 +32,15 @@
 #include <algorithm>
 #include <cmath>
 
+// Nonzeros per lane in one load of the main kernel: FP64 values one at a
+// time, FP32 values (and their indices) as 16-byte groups of four.
+#ifndef PPA_SPMV_G64
+#define PPA_SPMV_G64 1
+#endif
+#ifndef PPA_SPMV_G32
+#define PPA_SPMV_G32 4
+#endif
+
 namespace ppa {
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -57,8 +66,10 @@ struct RowPre {
     VT x, z, z2;
 };
 
-// Loads for row r (must be a valid row; callers clamp and mask).
-template <typename VT, typename IT>
+// Loads for row r (must be a valid row; callers clamp and mask).  EPI false:
+// the caller guarantees z and z2 are null, so their terms are constant zeros
+// and hold no registers.
+template <typename VT, bool EPI = true, typename IT>
 __device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr, int r,
                                               const IT* __restrict__ x, const IT* __restrict__ z,
                                               const IT* __restrict__ z2) {
@@ -66,8 +77,13 @@ __device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr
     q.a = rowptr[r];
     q.e = rowptr[r + 1];
     q.x = x ? (VT)x[r] : (VT)0;
-    q.z = z ? (VT)z[r] : (VT)0;
-    q.z2 = z2 ? (VT)z2[r] : (VT)0;
+    if constexpr (EPI) {
+        q.z = z ? (VT)z[r] : (VT)0;
+        q.z2 = z2 ? (VT)z2[r] : (VT)0;
+    } else {
+        q.z = (VT)0;
+        q.z2 = (VT)0;
+    }
     return q;
 }
 
@@ -168,17 +184,17 @@ __device__ __forceinline__ Grp<4, double> load_grp<4, double>(const double* __re
 // products land in LDS at their aligned position and each thread sums whole
 // rows from an offset view.  Every load of the block is issued before the
 // first gathered value is used.
-template <typename VT, typename IT, typename OT, int G>
+template <typename VT, typename IT, typename OT, int G, bool EPI>
 __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const VT* __restrict__ val, const int32_t* __restrict__ blk, int nblk, int nnz,
     const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
     const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
     constexpr int PER = SPMV_CHUNK / SPMV_BS;
-    static_assert(PER % G == 0, "groups must tile the per-thread share");
-    constexpr int NG = PER / G;
-    __shared__ __align__(16) VT prod_ext[SPMV_CHUNK];
-    __shared__ VT red[SPMV_BS / 64];
+    static_assert(PER * SPMV_BS == SPMV_CHUNK, "chunk must be a multiple of the block size");
+    constexpr int NG = (PER + G - 1) / G;      // groups per thread (the last may be idle)
+    // products at their aligned positions; the long-row path reuses it for its partials
+    __shared__ __align__(16) VT prod_ext[NG * G * SPMV_BS];
     const int b = xcd_remap(blockIdx.x, nblk);
     const int r0 = blk[b], r1 = blk[b + 1];
     const int p0 = rowptr[r0], p1 = rowptr[r1];
@@ -187,7 +203,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     if (p1 - base > SPMV_CHUNK) {
         // only a block of one row can exceed the budget (partition invariant)
         long_row<VT, IT, OT, SPMV_BS>(rowptr, colind, val, r0, p0, p1, x, u, z, z2, out, alpha,
-                                      beta, gamma, delta, red);
+                                      beta, gamma, delta, prod_ext);
         return;
     }
     const int ra = r0 + tid, rb = r0 + tid + SPMV_BS;
@@ -206,8 +222,8 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
             }
         }
         // the thread's first two rows (clamped into the block; masked at use)
-        qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
-        qb = row_pre<VT>(rowptr, min(rb, r1 - 1), x, z, z2);
+        qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
+        qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), x, z, z2);
         if (cnt > 0) {
             VT g[PER];
 #pragma unroll
@@ -231,8 +247,8 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
                 v[k] = load_grp<G>(val, idx, full, nnz - 1);
             }
         }
-        qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
-        qb = row_pre<VT>(rowptr, min(rb, r1 - 1), x, z, z2);
+        qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
+        qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), x, z, z2);
         if (p1 > p0) {
             VT g[NG][G];
 #pragma unroll
@@ -255,7 +271,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
     if (rb < r1) row_out(qb, prod, p0, rb, out, alpha, beta, gamma, delta);
     for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
-        const RowPre<VT> q = row_pre<VT>(rowptr, r, x, z, z2);
+        const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
         row_out(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
 }
@@ -333,24 +349,19 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
                            (int)W.nblocks, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2,
                            (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
     } else {
-#ifndef PPA_SPMV_G64
-#define PPA_SPMV_G64 1
-#endif
-#ifndef PPA_SPMV_G32
-#define PPA_SPMV_G32 4
-#endif
         constexpr int G = sizeof(VT) == 8 ? PPA_SPMV_G64 : PPA_SPMV_G32;
         const bool grp = G > 1 && A.align % G == 0 && reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
+        const bool epi = z != nullptr || z2 != nullptr;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0, s, A.rowptr,
+                               A.colind, val, A.blk, (int)A.nblocks, (int)A.nnz, (const IT*)x,
+                               (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha,
+                               (VT)beta, (VT)gamma, (VT)delta);
+        };
         if (grp)
-            hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT, G>), dim3((unsigned)A.nblocks),
-                               dim3(SPMV_BS), 0, s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks,
-                               (int)A.nnz, (const IT*)x, (const IT*)u, (const IT*)z,
-                               (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+            epi ? go(k_fused_spmv<VT, IT, OT, G, true>) : go(k_fused_spmv<VT, IT, OT, G, false>);
         else
-            hipLaunchKernelGGL((k_fused_spmv<VT, IT, OT, 1>), dim3((unsigned)A.nblocks),
-                               dim3(SPMV_BS), 0, s, A.rowptr, A.colind, val, A.blk, (int)A.nblocks,
-                               (int)A.nnz, (const IT*)x, (const IT*)u, (const IT*)z,
-                               (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+            epi ? go(k_fused_spmv<VT, IT, OT, 1, true>) : go(k_fused_spmv<VT, IT, OT, 1, false>);
     }
     PPA_HIP(hipGetLastError());
 }
