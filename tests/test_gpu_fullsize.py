@@ -1,0 +1,163 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (matrix handles created with the default kernel choice,
+which times the windowed variant against the plain one for large matrices).
+
+* pi(A)v: whole output vectors against the FP64 oracle element by element
+  (a CSR mat-vec at these sizes costs the oracle tens of milliseconds), with
+  the same first-order rounding bound as the small-size tests;
+* polynomial roots: the GPU's harmonic Ritz values against the oracle's own
+  GMRES(d) run on the same seed vector;
+* eigensolves: properties that hold at any size -- every returned pair's
+  residual recomputed independently on the host from the returned vector,
+  unit-norm vectors, reported residuals equal to the recomputed ones.
+
+Workloads: 2-D convection-diffusion 1000x1000 (beta*h = 0.5, d = 50), 3-D
+convection-diffusion 160^3 (beta*h = 0.3, double polynomial 10 x 20, FP32
+pi(A)v), random banded n = 2e6 with 27 nonzeros per row within +-5000
+(d = 100, FP32 pi(A)v).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1806_08020_amd import workloads as W
+
+from .test_gpu_parity import EPS32, EPS64, chain_tol, dev, host, oracle_chain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cd2():
+    return W.convdiff_2d(1000, 0.5)
+
+
+@pytest.fixture(scope="module")
+def cd3():
+    return W.convdiff_3d(160, 0.3)
+
+
+@pytest.fixture(scope="module")
+def band():
+    return W.random_banded(2_000_000, 27, 5000, seed=4)
+
+
+def match_roots(got, ref, rtol):
+    """Every root of `got` has a partner in `ref` within rtol (relative), and
+    the multisets have the same size and the same number of complex roots."""
+    assert got.size == ref.size
+    assert np.sum(got.imag != 0) == np.sum(ref.imag != 0)
+    for z in got:
+        assert np.min(np.abs(ref - z)) <= rtol * abs(z), z
+
+
+def host_residuals(csr, mu, X):
+    """||A x - mu x|| for each returned pair, from the host copy of x."""
+    S = csr.to_scipy()
+    out = []
+    for t in range(mu.size):
+        x = X[t]
+        out.append(np.linalg.norm(S @ x.real + 1j * (S @ x.imag) - mu[t] * x))
+    return np.array(out)
+
+
+def test_cd2_full_roots_and_apply(lib, cd2):
+    """n = 1e6, d = 50, FP64: roots against the oracle's GMRES(50) on the same
+    b; pi(A)v on the GPU's roots against the oracle factor by factor."""
+    b, v0 = W.start_vectors(cd2.n, 2)
+    mv = O.csr_matvec(cd2)
+    A = lib.Matrix(cd2)
+    P = lib.Poly.build(A, 50, dev(b))
+    roots = P.roots()
+    oroots, _ = O.gmres_poly(mv, b, 50)
+    match_roots(roots, oroots, 1e-9)
+    y = host(lib.apply(A, P, dev(v0)))
+    ref, g = oracle_chain(mv, roots, v0)
+    err = np.max(np.abs(y - ref))
+    assert err <= chain_tol(cd2, roots, g, EPS64), err
+
+
+def test_cd3_full_double_poly_apply_fp32(lib, cd3):
+    """n = 4.1e6, double polynomial 10 x 20 built on the GPU: pi_2(tau(A)) v
+    in FP32 (values and vectors) and in FP64 against the FP64 oracle."""
+    b, v0 = W.start_vectors(cd3.n, 3)
+    mv = O.csr_matvec(cd3)
+    A = lib.Matrix(cd3, want_f32=True)
+    P = lib.Poly.build_double(A, 10, 20, dev(b))
+    assert P.is_double and P.d1 == 10 and P.degree == 20
+    r1, r2 = P.roots(1), P.roots(2)
+    tau = lambda x: O.tau_apply(mv, r1, x)
+    ref, g = oracle_chain(tau, r2, v0)
+    tol = chain_tol(cd3, r1, g, EPS64) * len(r2) * 4
+    y = host(lib.apply(A, P, dev(v0)))
+    assert np.max(np.abs(y - ref)) <= tol
+    y32 = host(lib.apply(A, P, dev(v0, torch.float32), precision="f32")).astype(float)
+    assert np.max(np.abs(y32 - ref)) <= tol * (EPS32 / EPS64) * 2
+
+
+def test_band_full_apply_fp32_and_fp64(lib, band):
+    """n = 2e6, 27 nonzeros per row, d = 100: pi(A)v in FP32 (the kernel the
+    matrix handle selected at creation) and FP64 against the oracle."""
+    b, v0 = W.start_vectors(band.n, 4)
+    mv = O.csr_matvec(band)
+    A = lib.Matrix(band, want_f32=True)
+    P = lib.Poly.build(A, 100, dev(b))
+    roots = P.roots()
+    ref, g = oracle_chain(mv, roots, v0)
+    tol = chain_tol(band, roots, g, EPS64)
+    y = host(lib.apply(A, P, dev(v0)))
+    assert np.max(np.abs(y - ref)) <= tol
+    y32 = host(lib.apply(A, P, dev(v0, torch.float32), precision="f32")).astype(float)
+    assert np.max(np.abs(y32 - ref)) <= tol * (EPS32 / EPS64) * 2
+
+
+def test_cd2_full_eigs_fp64_properties(lib, cd2):
+    """The benchmark's FP64 solve: d = 50, Arnoldi(50,25), nev = 20, rtol 1e-8."""
+    b, v0 = W.start_vectors(cd2.n, 2)
+    A = lib.Matrix(cd2)
+    P = lib.Poly.build(A, 50, dev(b))
+    r = lib.eigs(A, P, dev(v0), 50, 25, 20, rtol=1e-8, max_cycles=40, want_vectors=True)
+    assert r.nconv == 20 and r.converged
+    X = host(r.X)
+    assert np.all(np.abs(np.linalg.norm(X, axis=1) - 1) < 1e-12)
+    res = host_residuals(cd2, r.mu, X)
+    assert np.all(res <= 1e-8 * A.norm_inf * 1.001), res.max() / A.norm_inf
+    assert np.allclose(res, r.resid, rtol=1e-6, atol=1e-14 * A.norm_inf)
+    # complex values come in conjugate pairs; the cut at nev may leave the
+    # partner of the last (largest modulus) value outside the returned set
+    cpx = r.mu[r.mu.imag != 0]
+    for z in cpx:
+        assert np.min(np.abs(cpx - np.conj(z))) <= 1e-14 or abs(z) >= np.abs(r.mu).max() * (1 - 1e-12), z
+
+
+def test_cd3_full_eigs_mixed_properties(lib, cd3):
+    """The benchmark's mixed-precision solve: FP32 pi(A)v, FP64 everything else
+    and the closing FP64 pass; every returned pair meets rtol in FP64."""
+    b, v0 = W.start_vectors(cd3.n, 3)
+    A = lib.Matrix(cd3, want_f32=True)
+    P = lib.Poly.build_double(A, 10, 20, dev(b))
+    r = lib.eigs(A, P, dev(v0), 40, 20, 15, rtol=1e-8, max_cycles=20, precision="mixed",
+                 want_vectors=True)
+    assert r.nconv == 15 and r.converged
+    assert r.fp32_cycles >= 1
+    X = host(r.X)
+    res = host_residuals(cd3, r.mu, X)
+    assert np.all(res <= 1e-8 * A.norm_inf * 1.001), res.max() / A.norm_inf
+    assert np.allclose(res, r.resid, rtol=1e-6, atol=1e-14 * A.norm_inf)
+
+
+def test_band_full_eigs_reported_residuals(lib, band):
+    """One restart cycle of the benchmark's mixed solve on the banded matrix
+    (an interior problem that needs many cycles): the residuals it reports
+    for its current Ritz pairs equal the host-recomputed ones."""
+    b, v0 = W.start_vectors(band.n, 4)
+    A = lib.Matrix(band, want_f32=True)
+    P = lib.Poly.build(A, 100, dev(b))
+    r = lib.eigs(A, P, dev(v0), 60, 15, 10, rtol=1e-8, max_cycles=1, precision="mixed",
+                 want_vectors=True)
+    assert r.cycles == 1
+    X = host(r.X)
+    assert np.all(np.abs(np.linalg.norm(X, axis=1) - 1) < 1e-12)
+    res = host_residuals(band, r.mu, X)
+    assert np.allclose(res, r.resid, rtol=1e-6, atol=1e-14 * A.norm_inf)
