@@ -52,8 +52,7 @@ constexpr int SPMV_WCHUNK_F64 = 4096;      // nonzeros per windowed block, FP64 
 
 struct Window {
     bool on = false;                 // selected for this value type
-    int32_t* blk = nullptr;          // device, nblocks + 1 row starts
-    int32_t* meta = nullptr;         // device, per block: cmin, span
+    int4* bm = nullptr;              // device, per block {r0, r1, p0, p1}, {cmin, span, 0, 0}
     int64_t nblocks = 0;
     int span_max = 0;
     size_t lds_bytes = 0;
@@ -66,7 +65,7 @@ struct Matrix {
     const double* v64 = nullptr;
     const float* v32 = nullptr;
     float* v32_owned = nullptr;
-    int32_t* blk = nullptr;          // device, nblocks + 1 row starts
+    int4* bm = nullptr;              // device, per block {r0, r1, p0, p1}
     int64_t nblocks = 0;
     int align = 1;                   // block ranges start at multiples of this (1 or 4)
     double norm_inf = 0.0;

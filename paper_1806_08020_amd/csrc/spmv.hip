@@ -187,7 +187,7 @@ __device__ __forceinline__ Grp<4, double> load_grp<4, double>(const double* __re
 template <typename VT, typename IT, typename OT, int G, bool EPI>
 __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const VT* __restrict__ val, const int32_t* __restrict__ blk, int nblk, int nnz,
+    const VT* __restrict__ val, const int4* __restrict__ bm, int nblk, int nnz,
     const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
     const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
     constexpr int PER = SPMV_CHUNK / SPMV_BS;
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     // products at their aligned positions; the long-row path reuses it for its partials
     __shared__ __align__(16) VT prod_ext[NG * G * SPMV_BS];
     const int b = xcd_remap(blockIdx.x, nblk);
-    const int r0 = blk[b], r1 = blk[b + 1];
-    const int p0 = rowptr[r0], p1 = rowptr[r1];
+    const int4 m = bm[b];   // rows [r0, r1), nonzeros [p0, p1): one 16-byte load
+    const int r0 = m.x, r1 = m.y, p0 = m.z, p1 = m.w;
     const int tid = threadIdx.x;
     const int base = p0 & ~(G - 1);
     if (p1 - base > SPMV_CHUNK) {
@@ -276,24 +276,25 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     }
 }
 
-// Windowed variant: block b covers rows [blk[b], blk[b+1]) whose columns lie
-// in [meta[2b], meta[2b] + meta[2b+1]); dynamic LDS holds CH products and
+// Windowed variant: block b covers rows [r0, r1) (nonzeros [p0, p1)) whose
+// columns lie in [cmin, cmin + span), read as one 32-byte record
+// {r0, r1, p0, p1, cmin, span, -, -}; dynamic LDS holds CH products and
 // the window.  The partition guarantees at most CH nonzeros per block and at
 // least one nonzero (no long rows; empty blocks have span 0).
 template <typename VT, typename IT, typename OT, int CH>
 __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const VT* __restrict__ val, const int32_t* __restrict__ blk, const int32_t* __restrict__ meta,
-    int nblk, const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
+    const VT* __restrict__ val, const int4* __restrict__ wm, int nblk, const IT* __restrict__ x,
+    const IT* __restrict__ u, const IT* __restrict__ z,
     const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
     extern __shared__ __align__(16) unsigned char smem[];
     VT* prod = reinterpret_cast<VT*>(smem);
     VT* win = prod + CH;
     const int b = xcd_remap(blockIdx.x, nblk);
-    const int r0 = blk[b], r1 = blk[b + 1];
-    const int p0 = rowptr[r0], p1 = rowptr[r1];
+    const int4 m0 = wm[2 * b], m1 = wm[2 * b + 1];
+    const int r0 = m0.x, r1 = m0.y, p0 = m0.z, p1 = m0.w;
     const int cnt = p1 - p0;
-    const int cmin = meta[2 * b], span = meta[2 * b + 1];
+    const int cmin = m1.x, span = m1.y;
     const int tid = threadIdx.x;
     constexpr int PER = CH / SPMV_WBS;
     const int last = p0 + (cnt > 0 ? cnt - 1 : 0);
@@ -345,7 +346,7 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
     if (W.on) {
         constexpr int CH = sizeof(VT) == 4 ? SPMV_WCHUNK_F32 : SPMV_WCHUNK_F64;
         hipLaunchKernelGGL((k_fused_spmv_win<VT, IT, OT, CH>), dim3((unsigned)W.nblocks),
-                           dim3(SPMV_WBS), W.lds_bytes, s, A.rowptr, A.colind, val, W.blk, W.meta,
+                           dim3(SPMV_WBS), W.lds_bytes, s, A.rowptr, A.colind, val, W.bm,
                            (int)W.nblocks, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2,
                            (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
     } else {
@@ -354,7 +355,7 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
         const bool epi = z != nullptr || z2 != nullptr;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0, s, A.rowptr,
-                               A.colind, val, A.blk, (int)A.nblocks, (int)A.nnz, (const IT*)x,
+                               A.colind, val, A.bm, (int)A.nblocks, (int)A.nnz, (const IT*)x,
                                (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha,
                                (VT)beta, (VT)gamma, (VT)delta);
         };
@@ -587,13 +588,25 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
     bool ok = lds <= (size_t)maxlds && lds <= 96 * 1024;
     if (ok)
         ok = vbytes == 8 ? allow_lds<double, SPMV_WCHUNK_F64>(lds) : allow_lds<float, SPMV_WCHUNK_F32>(lds);
-    if (!ok) {
-        PPA_HIP(hipFree(dblk));
-        PPA_HIP(hipFree(dmeta));
-        return;
+    PPA_HIP(hipFree(dblk));
+    PPA_HIP(hipFree(dmeta));
+    if (!ok) return;
+    // per block {r0, r1, p0, p1, cmin, span, 0, 0}
+    std::vector<int32_t> rec(8 * nb, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        int32_t* q = &rec[8 * b];
+        q[0] = blk[b];
+        q[1] = blk[b + 1];
+        q[2] = A.rp_host[blk[b]];
+        q[3] = A.rp_host[blk[b + 1]];
+        q[4] = meta[2 * b];
+        q[5] = meta[2 * b + 1];
     }
-    W.blk = dblk;
-    W.meta = dmeta;
+    int4* dwm = nullptr;
+    PPA_HIP(hipMalloc(&dwm, rec.size() * sizeof(int32_t)));
+    PPA_HIP(hipMemcpyAsync(dwm, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    W.bm = dwm;
     W.nblocks = nb;
     W.span_max = smax;
     W.lds_bytes = lds;
@@ -642,8 +655,16 @@ void matrix_setup(Matrix& A, hipStream_t s) {
     A.align = reinterpret_cast<uintptr_t>(A.colind) % 16 == 0 ? 4 : 1;
     std::vector<int32_t> blk = partition(rp, n, SPMV_CHUNK, SPMV_MAXROWS, A.align, nullptr);
     A.nblocks = (int64_t)blk.size() - 1;
-    PPA_HIP(hipMalloc(&A.blk, blk.size() * sizeof(int32_t)));
-    PPA_HIP(hipMemcpyAsync(A.blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // per block {r0, r1, p0, p1}: the kernel's first load is this one record
+    std::vector<int32_t> rec(4 * std::max<int64_t>(A.nblocks, 1), 0);
+    for (int64_t b = 0; b < A.nblocks; ++b) {
+        rec[4 * b] = blk[b];
+        rec[4 * b + 1] = blk[b + 1];
+        rec[4 * b + 2] = rp[blk[b]];
+        rec[4 * b + 3] = rp[blk[b + 1]];
+    }
+    PPA_HIP(hipMalloc(&A.bm, rec.size() * sizeof(int32_t)));
+    PPA_HIP(hipMemcpyAsync(A.bm, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     PPA_HIP(hipStreamSynchronize(s));
 }
 
@@ -673,10 +694,10 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
     if (mode == 0 && (A.n < 200000 || A.nnz < 1000000)) return;
     build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
     if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
-    if (!A.win64.blk && !A.win32.blk) return;
+    if (!A.win64.bm && !A.win32.bm) return;
     if (mode == 1) {
-        A.win64.on = A.win64.blk != nullptr;
-        A.win32.on = A.win32.blk != nullptr;
+        A.win64.on = A.win64.bm != nullptr;
+        A.win32.on = A.win32.bm != nullptr;
         return;
     }
     double* u = nullptr;
@@ -690,7 +711,7 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
     for (int pass = 0; pass < 2; ++pass) {
         const bool f32 = pass == 1;
         Window& W = f32 ? A.win32 : A.win64;
-        if (!W.blk) continue;
+        if (!W.bm) continue;
         void* uu = u;
         if (f32) launch_cast_f64_f32(u, (float*)y, A.n, s), uu = y;   // FP32 copy of the ramp
         void* yy = f32 ? (void*)((float*)y + ((A.n + 63) & ~int64_t(63))) : (void*)y;
@@ -713,14 +734,13 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
 }
 
 void matrix_release(Matrix& A) {
-    if (A.blk) (void)hipFree(A.blk);
+    if (A.bm) (void)hipFree(A.bm);
     if (A.v32_owned) (void)hipFree(A.v32_owned);
     for (Window* W : {&A.win64, &A.win32}) {
-        if (W->blk) (void)hipFree(W->blk);
-        if (W->meta) (void)hipFree(W->meta);
-        W->blk = W->meta = nullptr;
+        if (W->bm) (void)hipFree(W->bm);
+        W->bm = nullptr;
     }
-    A.blk = nullptr;
+    A.bm = nullptr;
     A.v32_owned = nullptr;
 }
 
