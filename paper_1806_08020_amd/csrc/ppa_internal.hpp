@@ -53,6 +53,7 @@ constexpr int SPMV_WCHUNK_F64 = 4096;      // nonzeros per windowed block, FP64 
 struct Window {
     bool on = false;                 // selected for this value type
     int4* bm = nullptr;              // device, per block {r0, r1, p0, p1}, {cmin, span, 0, 0}
+    int align = 1;                   // block ranges start at multiples of this
     int64_t nblocks = 0;
     int span_max = 0;
     size_t lds_bytes = 0;

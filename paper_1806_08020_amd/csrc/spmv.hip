@@ -279,63 +279,105 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
 // Windowed variant: block b covers rows [r0, r1) (nonzeros [p0, p1)) whose
 // columns lie in [cmin, cmin + span), read as one 32-byte record
 // {r0, r1, p0, p1, cmin, span, -, -}; dynamic LDS holds CH products and
-// the window.  The partition guarantees at most CH nonzeros per block and at
-// least one nonzero (no long rows; empty blocks have span 0).
-template <typename VT, typename IT, typename OT, int CH>
+// the window.  The partition guarantees that the block's nonzero range,
+// its start rounded down to a multiple of G, holds at most CH entries (no
+// long rows; empty blocks have span 0).  Column indices and values are read
+// in groups of G as in the main kernel; the window u[cmin, cmin + span) is
+// copied with 16-byte loads from cmin rounded down to a 16-byte boundary (u
+// must be 16-byte aligned), so LDS holds span + 2 * (16 / sizeof(IT))
+// window entries at most.
+template <typename VT, typename IT, typename OT, int CH, int G, bool EPI>
 __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const VT* __restrict__ val, const int4* __restrict__ wm, int nblk, const IT* __restrict__ x,
-    const IT* __restrict__ u, const IT* __restrict__ z,
+    const VT* __restrict__ val, const int4* __restrict__ wm, int nblk, int nnz, int n,
+    const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
     const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
+    constexpr int PER = CH / SPMV_WBS;
+    static_assert(PER % G == 0, "groups must tile the per-thread share");
+    constexpr int NG = PER / G;
     extern __shared__ __align__(16) unsigned char smem[];
-    VT* prod = reinterpret_cast<VT*>(smem);
-    VT* win = prod + CH;
+    VT* prod_ext = reinterpret_cast<VT*>(smem);
+    VT* win = prod_ext + CH;
     const int b = xcd_remap(blockIdx.x, nblk);
     const int4 m0 = wm[2 * b], m1 = wm[2 * b + 1];
     const int r0 = m0.x, r1 = m0.y, p0 = m0.z, p1 = m0.w;
-    const int cnt = p1 - p0;
     const int cmin = m1.x, span = m1.y;
     const int tid = threadIdx.x;
-    constexpr int PER = CH / SPMV_WBS;
-    const int last = p0 + (cnt > 0 ? cnt - 1 : 0);
-    int32_t c[PER];
-    VT v[PER];
-    if (cnt > 0) {
+    const int base = p0 & ~(G - 1);
+    // column indices and values of the block, masked past its range
+    Grp<G, int32_t> c[NG];
+    Grp<G, VT> v[NG];
+    if (p1 > p0) {
+        const int gmax = (p1 - base - 1) / G;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int j = min(p0 + tid + k * SPMV_WBS, last);
-            c[k] = __builtin_nontemporal_load(colind + j);
-            v[k] = __builtin_nontemporal_load(val + j);
+        for (int k = 0; k < NG; ++k) {
+            const int idx = base + G * min(tid + k * SPMV_WBS, gmax);
+            const bool full = idx + G <= nnz;
+            c[k] = load_grp<G>(colind, idx, full, nnz - 1);
+            v[k] = load_grp<G>(val, idx, full, nnz - 1);
         }
     }
-    // window copy, 8 loads in flight per thread per step (clamped, masked)
-    constexpr int WU = 8;
-    for (int base = 0; base < span; base += WU * SPMV_WBS) {
-        VT t[WU];
+    // window copy: 16-byte vectors of u from wb = cmin rounded down
+    constexpr int VW = 16 / sizeof(IT);
+    typedef IT ivec __attribute__((ext_vector_type(VW)));
+    const int wb = cmin & ~(VW - 1);
+    const int nvec = span > 0 ? (cmin + span - wb + VW - 1) / VW : 0;
+    constexpr int WU = 4;
+    for (int q0 = 0; q0 < nvec; q0 += WU * SPMV_WBS) {
+        ivec t[WU];
 #pragma unroll
-        for (int q = 0; q < WU; ++q) t[q] = (VT)u[cmin + min(base + tid + q * SPMV_WBS, span - 1)];
+        for (int k = 0; k < WU; ++k) {
+            const int e = wb + VW * min(q0 + tid + k * SPMV_WBS, nvec - 1);
+            if (e + VW <= n) {
+                t[k] = *reinterpret_cast<const ivec*>(u + e);
+            } else {
 #pragma unroll
-        for (int q = 0; q < WU; ++q) {
-            const int i = base + tid + q * SPMV_WBS;
-            if (i < span) win[i] = t[q];
+                for (int j = 0; j < VW; ++j) t[k][j] = u[min(e + j, n - 1)];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WU; ++k) {
+            const int q = q0 + tid + k * SPMV_WBS;
+            if (q < nvec) {
+#pragma unroll
+                for (int j = 0; j < VW; ++j) win[VW * q + j] = (VT)t[k][j];
+            }
         }
     }
     const int ra = r0 + tid;
-    const RowPre<VT> qa = row_pre<VT>(rowptr, min(ra, r1 - 1), x, z, z2);
+    const RowPre<VT> qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
     __syncthreads();
-    if (cnt > 0) {
+    if (p1 > p0) {
+        // masked positions may hold columns of neighbouring blocks: their
+        // window index is clamped into the copied range
+        const int wlast = VW * nvec - 1;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = tid + k * SPMV_WBS;
-            prod[i] = i < cnt ? v[k] * win[c[k] - cmin] : (VT)0;
+        for (int k = 0; k < NG; ++k) {
+            const int pos = G * (tid + k * SPMV_WBS);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int e = base + pos + j;
+                const VT w = win[min(max(c[k].v[j] - wb, 0), wlast)];
+                prod_ext[pos + j] = (e >= p0 && e < p1) ? v[k].v[j] * w : (VT)0;
+            }
         }
     }
     __syncthreads();
+    const VT* prod = prod_ext + (p0 - base);
     if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
     for (int r = ra + SPMV_WBS; r < r1; r += SPMV_WBS) {
-        const RowPre<VT> q = row_pre<VT>(rowptr, r, x, z, z2);
+        const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
         row_out(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
+}
+
+template <typename VT>
+constexpr int win_chunk() {
+    return sizeof(VT) == 4 ? SPMV_WCHUNK_F32 : SPMV_WCHUNK_F64;
+}
+template <typename VT>
+constexpr int grp_width() {
+    return sizeof(VT) == 8 ? PPA_SPMV_G64 : PPA_SPMV_G32;
 }
 
 template <typename VT, typename IT, typename OT>
@@ -343,16 +385,26 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
                       double beta, const void* u, double gamma, const void* z, double delta,
                       const void* z2, void* o, hipStream_t s) {
     if (A.nblocks == 0) return;
-    if (W.on) {
-        constexpr int CH = sizeof(VT) == 4 ? SPMV_WCHUNK_F32 : SPMV_WCHUNK_F64;
-        hipLaunchKernelGGL((k_fused_spmv_win<VT, IT, OT, CH>), dim3((unsigned)W.nblocks),
-                           dim3(SPMV_WBS), W.lds_bytes, s, A.rowptr, A.colind, val, W.bm,
-                           (int)W.nblocks, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2,
-                           (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+    constexpr int G = grp_width<VT>();
+    const bool epi = z != nullptr || z2 != nullptr;
+    const bool valg = reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
+    if (W.on && reinterpret_cast<uintptr_t>(u) % 16 == 0) {
+        constexpr int CH = win_chunk<VT>();
+        const bool grp = G > 1 && W.align % G == 0 && valg;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)W.nblocks), dim3(SPMV_WBS), W.lds_bytes, s,
+                               A.rowptr, A.colind, val, W.bm, (int)W.nblocks, (int)A.nnz, (int)A.n,
+                               (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o,
+                               (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+        };
+        if (grp)
+            epi ? go(k_fused_spmv_win<VT, IT, OT, CH, G, true>)
+                : go(k_fused_spmv_win<VT, IT, OT, CH, G, false>);
+        else
+            epi ? go(k_fused_spmv_win<VT, IT, OT, CH, 1, true>)
+                : go(k_fused_spmv_win<VT, IT, OT, CH, 1, false>);
     } else {
-        constexpr int G = sizeof(VT) == 8 ? PPA_SPMV_G64 : PPA_SPMV_G32;
-        const bool grp = G > 1 && A.align % G == 0 && reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
-        const bool epi = z != nullptr || z2 != nullptr;
+        const bool grp = G > 1 && A.align % G == 0 && valg;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0, s, A.rowptr,
                                A.colind, val, A.bm, (int)A.nblocks, (int)A.nnz, (const IT*)x,
@@ -541,23 +593,29 @@ static std::vector<int32_t> partition(const std::vector<int32_t>& rp, int64_t n,
     return blk;
 }
 
-// Allow the windowed kernels of one value type to use `bytes` of dynamic LDS.
-template <typename VT, int CH>
-static bool allow_lds(size_t bytes) {
+// Allow every windowed kernel instance of one value type to use `bytes` of
+// dynamic LDS.
+template <typename VT, typename IT, typename OT>
+static bool allow_lds_one(int b) {
+    constexpr int CH = win_chunk<VT>(), G = grp_width<VT>();
+    bool ok = true;
+    for (const void* f : {(const void*)k_fused_spmv_win<VT, IT, OT, CH, G, true>,
+                          (const void*)k_fused_spmv_win<VT, IT, OT, CH, G, false>,
+                          (const void*)k_fused_spmv_win<VT, IT, OT, CH, 1, true>,
+                          (const void*)k_fused_spmv_win<VT, IT, OT, CH, 1, false>})
+        ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+    return ok;
+}
+static bool allow_lds(size_t vbytes, size_t bytes) {
     const int b = (int)bytes;
     bool ok = true;
-    if (sizeof(VT) == 8) {
-        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<double, double, double, CH>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+    if (vbytes == 8) {
+        ok &= allow_lds_one<double, double, double>(b);
     } else {
-        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, float, float, CH>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
-        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, double, float, CH>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
-        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, float, double, CH>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
-        ok &= hipFuncSetAttribute((const void*)k_fused_spmv_win<float, double, double, CH>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+        ok &= allow_lds_one<float, float, float>(b);
+        ok &= allow_lds_one<float, double, float>(b);
+        ok &= allow_lds_one<float, float, double>(b);
+        ok &= allow_lds_one<float, double, double>(b);
     }
     (void)hipGetLastError();
     return ok;
@@ -567,7 +625,7 @@ static bool allow_lds(size_t bytes) {
 // the LDS size, but stays off until matrix_tune selects it.
 static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStream_t s) {
     bool lg = false;
-    std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, 1, &lg);
+    std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, A.align, &lg);
     if (lg) return;
     int maxlds = 0;
     PPA_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, A.device));
@@ -584,10 +642,10 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
     PPA_HIP(hipStreamSynchronize(s));
     int smax = 0;
     for (int64_t b = 0; b < nb; ++b) smax = std::max(smax, meta[2 * b + 1]);
-    const size_t lds = (size_t)chunk * vbytes + (size_t)smax * vbytes;
+    // products, then the window with room for the 16-byte aligned copy
+    const size_t lds = (size_t)chunk * vbytes + (size_t)(smax + 8) * vbytes;
     bool ok = lds <= (size_t)maxlds && lds <= 96 * 1024;
-    if (ok)
-        ok = vbytes == 8 ? allow_lds<double, SPMV_WCHUNK_F64>(lds) : allow_lds<float, SPMV_WCHUNK_F32>(lds);
+    if (ok) ok = allow_lds(vbytes, lds);
     PPA_HIP(hipFree(dblk));
     PPA_HIP(hipFree(dmeta));
     if (!ok) return;
@@ -607,6 +665,7 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
     PPA_HIP(hipMemcpyAsync(dwm, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     PPA_HIP(hipStreamSynchronize(s));
     W.bm = dwm;
+    W.align = A.align;
     W.nblocks = nb;
     W.span_max = smax;
     W.lds_bytes = lds;
