@@ -156,6 +156,63 @@ __global__ __launch_bounds__(BS) void k_update(const double* __restrict__ V, int
     }
 }
 
+// The reorthogonalisation's update and projection in one pass over V:
+//   t = w - V h          (h = the first projection, length j)
+//   partial[c * nb + b] = sum over the block's rows of V[c][r] t[r]  (c < j)
+// One row per thread; its JT >= j entries of V stay in registers between the
+// two steps.  The column sums of a wave are formed by a butterfly
+// reduce-scatter: at each step a lane keeps half of its columns and adds the
+// partner's copy of that half, so a wave needs about JT shuffles instead of
+// 6 per column; lane l then holds the wave's sum for one column.  The four
+// waves are combined through LDS in a fixed order.
+template <int JT>
+__global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V, int64_t ldv,
+                                                    int64_t n, int j, const double* __restrict__ h,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ t,
+                                                    double* __restrict__ partial, int nb) {
+    static_assert(JT >= 1 && JT <= 64 && (JT & (JT - 1)) == 0, "JT: power of two up to 64");
+    __shared__ double hs[JT];
+    __shared__ double red[NW][JT];
+    for (int c = threadIdx.x; c < JT; c += BS) hs[c] = c < j ? h[c] : 0.0;
+    const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const int64_t rr = r < n ? r : n - 1;
+    double v[JT];
+#pragma unroll
+    for (int c = 0; c < JT; ++c) v[c] = V[(int64_t)min(c, j - 1) * ldv + rr];
+    double tv = w[rr];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < JT; ++c) tv -= v[c] * hs[c];
+    if (r < n) t[r] = tv;
+    const double wt = r < n ? tv : 0.0;
+#pragma unroll
+    for (int c = 0; c < JT; ++c) v[c] = c < j ? v[c] * wt : 0.0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int col = 0;
+    int o = 32;
+#pragma unroll
+    for (int K = JT; K > 1; K >>= 1, o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            const double send = up ? v[i] : v[K / 2 + i];
+            const double keep = up ? v[K / 2 + i] : v[i];
+            v[i] = keep + __shfl_xor(send, o, 64);
+        }
+        if (up) col += K / 2;
+    }
+    // lanes that share a column now hold partial sums over disjoint lanes
+    for (; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
+    if ((lane & (64 / JT - 1)) == 0) red[wave][col] = v[0];
+    __syncthreads();
+    for (int c = threadIdx.x; c < j; c += BS) {
+        double s = 0.0;
+        for (int q = 0; q < NW; ++q) s += red[q][c];
+        partial[(int64_t)c * nb + blockIdx.x] = s;
+    }
+}
+
 // out[c] = sum_b partial[c * nb + b], one block per column, fixed tree.
 __global__ __launch_bounds__(BS) void k_reduce_cols(const double* __restrict__ partial, int nb,
                                                     double* __restrict__ out) {
@@ -206,9 +263,18 @@ int cgs_blocks(int64_t n) {
     return (int)std::max<int64_t>(1, nb);
 }
 
+// blocks of the fused update-projection kernel (one row per thread)
+static int cgs_blocks_fused(int64_t n) {
+    const int64_t nb = (n + BS - 1) / BS;
+    PPA_REQUIRE(nb <= (int64_t(1) << 27), "vector too long for the Gram-Schmidt kernels");
+    return (int)std::max<int64_t>(1, nb);
+}
+
 void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws) {
     ws.nb = cgs_blocks(n);
-    ws.partial = c.take<double>((size_t)(CGS_JMAX_ALL + 2) * ws.nb);
+    ws.nbf = cgs_blocks_fused(n);
+    ws.partial = c.take<double>(std::max<size_t>((size_t)(CGS_JMAX_ALL + 2) * ws.nb,
+                                                 (size_t)CGS_JFUSED * ws.nbf));
     ws.h1 = c.take<double>(CGS_JMAX_ALL);
     ws.h2 = c.take<double>(CGS_JMAX_ALL);
     ws.scal = c.take<double>(4);
@@ -244,10 +310,27 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
     // pass 1: h1 = V^T w and ||w_in||^2
     proj(n, j, V, ldv, w, ws.partial, nb, 1, s);
     reduce_cols(ws.partial, nb, j + 1, ws.h1, s);   // h1[0..j-1], h1[j] = ||w_in||^2
-    // reorthogonalisation: t = w - V h1, h2 = V^T t
-    update(n, j, V, ldv, ws.h1, w, ws.t, nullptr, nb, s);
-    proj(n, j, V, ldv, ws.t, ws.partial, nb, 0, s);
-    reduce_cols(ws.partial, nb, j, ws.h2, s);
+    // reorthogonalisation: t = w - V h1, h2 = V^T t (one pass over V when
+    // the basis fits the fused kernel's registers)
+    if (j <= CGS_JFUSED) {
+        const int nbf = ws.nbf;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nbf), dim3(BS), 0, s, V, ldv, n, j, ws.h1, w, ws.t,
+                               ws.partial, nbf);
+        };
+        if (j <= 16)
+            go(k_update_proj<16>);
+        else if (j <= 32)
+            go(k_update_proj<32>);
+        else
+            go(k_update_proj<64>);
+        PPA_HIP(hipGetLastError());
+        reduce_cols(ws.partial, nbf, j, ws.h2, s);
+    } else {
+        update(n, j, V, ldv, ws.h1, w, ws.t, nullptr, nb, s);
+        proj(n, j, V, ldv, ws.t, ws.partial, nb, 0, s);
+        reduce_cols(ws.partial, nb, j, ws.h2, s);
+    }
     // w_out = t - V h2 and ||w_out||^2
     update(n, j, V, ldv, ws.h2, ws.t, w_out, ws.partial, nb, s);
     reduce_cols(ws.partial, nb, 1, ws.scal + 1, s);

@@ -139,9 +139,11 @@ struct Cgs2Ws {
     double* h2 = nullptr;        // JMAX_ALL
     double* scal = nullptr;      // [0] = ||w_in||^2, [1] = ||w_out||^2, [2] = 1/beta
     double* t = nullptr;         // n
-    int nb = 0;
+    int nb = 0;                  // blocks of the streaming kernels
+    int nbf = 0;                 // blocks of the fused update-projection kernel
 };
 constexpr int CGS_JMAX_ALL = 256;
+constexpr int CGS_JFUSED = 64;   // widest basis of the fused update-projection
 int cgs_blocks(int64_t n);
 void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws);
 // Orthogonalise w against V[:, 0:j] (CGS2).  Writes the unnormalised result to

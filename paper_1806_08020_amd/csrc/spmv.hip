@@ -774,18 +774,28 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
         void* uu = u;
         if (f32) launch_cast_f64_f32(u, (float*)y, A.n, s), uu = y;   // FP32 copy of the ramp
         void* yy = f32 ? (void*)((float*)y + ((A.n + 63) & ~int64_t(63))) : (void*)y;
-        W.on = false;
-        const float t_plain = time_passes(A, f32, uu, yy, 4, s);
-        W.on = true;
-        float t_win = 0.f;
-        try {
-            t_win = time_passes(A, f32, uu, yy, 4, s);
-        } catch (const Error&) {
-            (void)hipGetLastError();
+        // alternate the two kernels over three trials after a warm-up of
+        // each, and compare the best trials: a single short timing favours
+        // whichever variant runs second on warm caches
+        float t_plain = 1e30f, t_win = 1e30f;
+        bool win_ok = true;
+        for (int trial = 0; trial < 4 && win_ok; ++trial) {
             W.on = false;
-            continue;
+            const float tp = time_passes(A, f32, uu, yy, 8, s);
+            W.on = true;
+            float tw = 0.f;
+            try {
+                tw = time_passes(A, f32, uu, yy, 8, s);
+            } catch (const Error&) {
+                (void)hipGetLastError();
+                win_ok = false;
+                break;
+            }
+            if (trial == 0) continue;   // warm-up
+            t_plain = std::min(t_plain, tp);
+            t_win = std::min(t_win, tw);
         }
-        W.on = t_win < 0.95f * t_plain;
+        W.on = win_ok && t_win < 0.95f * t_plain;
     }
     PPA_HIP(hipStreamSynchronize(s));
     PPA_HIP(hipFree(u));

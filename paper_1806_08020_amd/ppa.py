@@ -171,7 +171,7 @@ class Matrix:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _lib is not None:   # the module may already be torn down at exit
             _lib.ppa_matrix_destroy(h)
             self.h = None
 
@@ -236,7 +236,7 @@ class Poly:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _lib is not None:
             _lib.ppa_poly_destroy(h)
             self.h = None
 
@@ -427,7 +427,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _lib is not None:
             _lib.ppa_batch_destroy(h)
             self.h = None
 
