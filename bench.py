@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # by the hash of the kernel source the counters were taken on: any change of
 # the kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
-    ("c2", "45c99c7879fab0d1"): {"fetch_kib": 37049.65, "write_kib": 7812.64, "fetch_factor": 2.0,
-                   "write_factor": 1.0},
+    ("c2", "923cb5853e06ca3e"): {"fetch_kib": 36911.28, "write_kib": 7812.85, "fetch_factor": 2.0,
+                                 "write_factor": 1.0},
 }
 
 CONFIGS = {
