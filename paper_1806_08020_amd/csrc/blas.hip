@@ -174,13 +174,16 @@ __global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V
     static_assert(JT >= 1 && JT <= 64 && (JT & (JT - 1)) == 0, "JT: power of two up to 64");
     __shared__ double hs[JT];
     __shared__ double red[NW][JT];
-    for (int c = threadIdx.x; c < JT; c += BS) hs[c] = c < j ? h[c] : 0.0;
     const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
     const int64_t rr = r < n ? r : n - 1;
+    // columns past j re-read column j - 1 (weight 0): unconditional loads
+    // keep the register count lowest; the instance is chosen with JT < 2j
     double v[JT];
 #pragma unroll
     for (int c = 0; c < JT; ++c) v[c] = V[(int64_t)min(c, j - 1) * ldv + rr];
     double tv = w[rr];
+    // h is staged in LDS after the row's loads are in flight
+    for (int c = threadIdx.x; c < JT; c += BS) hs[c] = c < j ? h[c] : 0.0;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < JT; ++c) tv -= v[c] * hs[c];
@@ -318,7 +321,11 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
             hipLaunchKernelGGL(kern, dim3(nbf), dim3(BS), 0, s, V, ldv, n, j, ws.h1, w, ws.t,
                                ws.partial, nbf);
         };
-        if (j <= 16)
+        if (j <= 4)
+            go(k_update_proj<4>);
+        else if (j <= 8)
+            go(k_update_proj<8>);
+        else if (j <= 16)
             go(k_update_proj<16>);
         else if (j <= 32)
             go(k_update_proj<32>);
