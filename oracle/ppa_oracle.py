@@ -39,6 +39,7 @@ __all__ = [
     "leja_order", "gmres_poly", "apply_poly", "tau_apply", "double_poly",
     "apply_double", "ArnoldiResult", "thick_restart_arnoldi", "pp_eigs",
     "sort_ritz", "keep_count", "thick_restart", "BREAKDOWN_TOL",
+    "pof", "log10_pof", "extra_root_counts", "add_stability_roots",
 ]
 
 # Breakdown rule (reading): an Arnoldi/GMRES step breaks down when the norm
@@ -209,6 +210,73 @@ def gmres_poly(matvec, b: np.ndarray, d: int, cnt: Counters | None = None):
 # --------------------------------------------------------------------------
 # eq. (2.1): pi(A) v in factored form
 # --------------------------------------------------------------------------
+# ---------------------------------------------------------------- stability (section 7)
+def pof(theta: np.ndarray) -> np.ndarray:
+    """Section 7: pof(j) = prod_{i != j} |1 - theta_j / theta_i|, the product
+    of the other factors of pi evaluated at theta_j (so |pi'(theta_j)| =
+    pof(j) / |theta_j|).  Written as the definition: a product, which may
+    overflow to inf for high degrees (log10_pof is the same quantity as a sum
+    of logarithms)."""
+    theta = np.asarray(theta, dtype=complex)
+    out = np.empty(theta.size)
+    for j in range(theta.size):
+        others = np.delete(theta, j)
+        out[j] = float(np.prod(np.abs(1.0 - theta[j] / others)))
+    return out
+
+
+def log10_pof(theta: np.ndarray) -> np.ndarray:
+    """log10 pof(j) = sum_{i != j} log10 |1 - theta_j / theta_i| (no overflow;
+    -inf when theta_j repeats)."""
+    theta = np.asarray(theta, dtype=complex)
+    out = np.empty(theta.size)
+    with np.errstate(divide="ignore"):
+        for j in range(theta.size):
+            others = np.delete(theta, j)
+            out[j] = float(np.sum(np.log10(np.abs(1.0 - theta[j] / others))))
+    return out
+
+
+def extra_root_counts(theta: np.ndarray) -> np.ndarray:
+    """Section 7, 'Adding roots for stability', step 2-3 count: one more copy
+    of theta_j for every factor 1e14 by which pof(j) exceeds 1e4, i.e.
+    ceil((log10 pof(j) - 4) / 14), never negative (reading: a copy is added
+    only when pof(j) exceeds 1e4, a second when it exceeds 1e18, ...)."""
+    x = (log10_pof(theta) - 4.0) / 14.0
+    return np.maximum(0, np.ceil(x)).astype(int)
+
+
+def add_stability_roots(theta: np.ndarray):
+    """Section 7, 'Adding roots for stability', on a root list in modified
+    Leja order.  For each root in list order (a conjugate pair as one unit,
+    at its Im > 0 member) with c = extra_root_counts > 0: the first copy goes
+    to the end of the current list; the other c - 1 are inserted at the
+    positions p + round(k (L - p) / c), k = 1..c-1, spaced evenly between the
+    root's position p and the end of the current list (length L before
+    this root's copies), never between the two members of a pair.  pof is
+    evaluated once, on the original list.  Returns (new list, counts)."""
+    theta = np.asarray(theta, dtype=complex)
+    counts = extra_root_counts(theta)
+    out = list(theta)
+    for j, z in enumerate(theta):
+        c = int(counts[j])
+        if c == 0 or z.imag < 0.0:
+            continue
+        unit = [z, np.conj(z)] if z.imag > 0.0 else [z]
+        p = next(i for i, w in enumerate(out) if w == z)
+        L = len(out)
+        spots = []
+        for kk in range(1, c):
+            q = p + int(np.floor(kk * (L - p) / c + 0.5))
+            if 0 < q < len(out) and out[q - 1].imag > 0.0 and out[q] == np.conj(out[q - 1]):
+                q += 1   # not between a pair's members
+            spots.append(q)
+        out = out + unit
+        for q in sorted(spots, reverse=True):
+            out[q:q] = unit
+    return np.array(out, dtype=complex), counts
+
+
 def apply_poly(matvec, roots: np.ndarray, v: np.ndarray, cnt: Counters | None = None,
                op_mvps: int = 1):
     """pi(A) v = prod_i (I - A/theta_i) v, factors in the given (Leja) order.
