@@ -119,6 +119,22 @@ int ppa_poly_degree(const ppa_poly* p, int* deg, int* d1);
  * into host arrays of capacity `cap`; returns the count in *count. */
 int ppa_poly_roots(const ppa_poly* p, int level, double* re, double* im, int cap, int* count);
 
+/* Stability control (section 7, "Adding roots for stability").
+ * ppa_poly_log10_pof: log10 pof(j) for every root theta_j of `level` (2: pi,
+ * or pi_2 of a double polynomial; 1: pi_1), in application order, where
+ * pof(j) = prod_{i != j} |1 - theta_j / theta_i| (so |pi'(theta_j)| =
+ * pof(j) / |theta_j|; -inf for a repeated root).  `out` holds `cap` doubles;
+ * *count receives the root count.  Host only.
+ * ppa_poly_stabilize: a new polynomial equal to p except that every root of
+ * `level` with pof(j) > 1e4 gets ceil((log10 pof(j) - 4) / 14) extra copies
+ * (a double root above 1e4, triple above 1e18, ...).  The first copy goes to
+ * the end of the root list, the others are spaced evenly between the root
+ * and the end; a conjugate pair is copied as a pair and never split
+ * (section 8, Example 9 applies the same test to pi_2).  *added receives the
+ * number of roots added; the caller destroys *out.  Host only. */
+int ppa_poly_log10_pof(const ppa_poly* p, int level, double* out, int cap, int* count);
+int ppa_poly_stabilize(const ppa_poly* p, int level, ppa_poly** out, int* added);
+
 /* Workspace bytes for ppa_poly_build / ppa_poly_build_double with degree d
  * (for a double polynomial pass d = max(d1, d2) and double_poly = 1). */
 int ppa_poly_build_workspace_bytes(const ppa_matrix* A, int d, int double_poly, size_t* bytes);

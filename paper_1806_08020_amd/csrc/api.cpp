@@ -190,6 +190,39 @@ int ppa_poly_roots(const ppa_poly* h, int level, double* re, double* im, int cap
     });
 }
 
+int ppa_poly_log10_pof(const ppa_poly* h, int level, double* out, int cap, int* count) {
+    return guarded([&] {
+        PPA_REQUIRE(h != nullptr && out != nullptr, "poly and out are required");
+        PPA_REQUIRE(level == 1 || level == 2, "level must be 1 or 2");
+        const Poly* p = reinterpret_cast<const Poly*>(h);
+        const std::vector<cplx>& r = level == 2 ? p->roots : p->roots1;
+        PPA_REQUIRE((int)r.size() <= cap, "capacity %d below the root count %zu", cap, r.size());
+        const std::vector<double> lp = log10_pof(r);
+        for (size_t i = 0; i < lp.size(); ++i) out[i] = lp[i];
+        if (count) *count = (int)lp.size();
+        return PPA_OK;
+    });
+}
+
+int ppa_poly_stabilize(const ppa_poly* h, int level, ppa_poly** out, int* added) {
+    return guarded([&] {
+        PPA_REQUIRE(h != nullptr && out != nullptr, "poly and out are required");
+        PPA_REQUIRE(level == 1 || level == 2, "level must be 1 or 2");
+        *out = nullptr;
+        const Poly* p = reinterpret_cast<const Poly*>(h);
+        PPA_REQUIRE(level == 2 || p->is_double(), "level 1 needs a double polynomial");
+        Poly* q = new Poly(*p);
+        int n_added = 0;
+        if (level == 2)
+            q->roots = add_stability_roots(p->roots, &n_added);
+        else
+            q->roots1 = add_stability_roots(p->roots1, &n_added);
+        if (added) *added = n_added;
+        *out = reinterpret_cast<ppa_poly*>(q);
+        return PPA_OK;
+    });
+}
+
 int ppa_poly_build_workspace_bytes(const ppa_matrix* h, int d, int double_poly, size_t* bytes) {
     return guarded([&] {
         PPA_REQUIRE(h && bytes, "matrix and bytes are required");

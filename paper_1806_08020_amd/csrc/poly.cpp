@@ -271,4 +271,72 @@ size_t apply_poly_bytes(const Matrix& A, const Poly& p, VecT chain) {
     return ch.bytes;
 }
 
+// ---------------------------------------------------------------- stability
+// Section 7.  pof(j) = prod_{i != j} |1 - theta_j / theta_i| is the product of
+// the other factors of pi at theta_j (|pi'(theta_j)| = pof(j) / |theta_j|); a
+// large value means the factored product amplifies the component along an
+// eigenvector near theta_j and cancels it again in one factor.  It is formed
+// as a sum of base-10 logarithms so that high degrees do not overflow.
+std::vector<double> log10_pof(const std::vector<cplx>& th) {
+    const size_t d = th.size();
+    std::vector<double> out(d, 0.0);
+    for (size_t j = 0; j < d; ++j) {
+        double acc = 0.0;
+        for (size_t i = 0; i < d; ++i) {
+            if (i == j) continue;
+            acc += std::log10(std::abs(1.0 - th[j] / th[i]));   // -inf for a repeated root
+        }
+        out[j] = acc;
+    }
+    return out;
+}
+
+// One extra copy of theta_j for every factor 1e14 by which pof(j) exceeds
+// 1e4: ceil((log10 pof(j) - 4) / 14), never negative.
+std::vector<int> extra_root_counts(const std::vector<cplx>& th) {
+    const std::vector<double> lp = log10_pof(th);
+    std::vector<int> c(th.size(), 0);
+    for (size_t j = 0; j < th.size(); ++j) {
+        const double x = std::ceil((lp[j] - 4.0) / 14.0);
+        c[j] = (std::isfinite(x) && x > 0.0) ? (int)x : 0;
+    }
+    return c;
+}
+
+// The extra copies placed as section 7 describes, in list order (a
+// conjugate pair is one unit, handled at its Im > 0 member): the first copy
+// is appended to the current list; the remaining c - 1 go to positions
+// p + round(k (L - p) / c), k = 1..c-1, between the root's position p and
+// the end of the list as it stood before this root's copies (length L),
+// moved past the second member when a position falls inside a pair.
+std::vector<cplx> add_stability_roots(const std::vector<cplx>& th, int* added) {
+    const std::vector<int> cnt = extra_root_counts(th);
+    std::vector<cplx> out = th;
+    int total = 0;
+    for (size_t j = 0; j < th.size(); ++j) {
+        const int c = cnt[j];
+        const cplx z = th[j];
+        if (c == 0 || z.imag() < 0.0) continue;
+        std::vector<cplx> unit{z};
+        if (z.imag() > 0.0) unit.push_back(std::conj(z));
+        size_t p = 0;
+        while (out[p] != z) ++p;
+        const size_t L = out.size();
+        std::vector<size_t> spots;
+        for (int k = 1; k < c; ++k) {
+            size_t q = p + (size_t)std::floor((double)k * (double)(L - p) / (double)c + 0.5);
+            if (q > 0 && q < out.size() && out[q - 1].imag() > 0.0 && out[q] == std::conj(out[q - 1]))
+                ++q;
+            spots.push_back(q);
+        }
+        out.insert(out.end(), unit.begin(), unit.end());
+        std::sort(spots.begin(), spots.end());
+        for (auto it = spots.rbegin(); it != spots.rend(); ++it)
+            out.insert(out.begin() + (std::ptrdiff_t)*it, unit.begin(), unit.end());
+        total += c * (int)unit.size();
+    }
+    if (added) *added = total;
+    return out;
+}
+
 }  // namespace ppa

@@ -203,6 +203,12 @@ int apply_buffers(const Poly& p);
 void carve_apply(Carver& c, int64_t n, const Poly& p, VecT t, ApplyWs& ws);
 // in/out types: vin/vout select the element type of v and y; the chain runs in
 // `chain` precision (F32 chain = FP32 matrix values).
+// Stability control of section 7 (host): log10 pof per root, the number of
+// extra copies per root, and the root list with the copies placed.
+std::vector<double> log10_pof(const std::vector<cplx>& th);
+std::vector<int> extra_root_counts(const std::vector<cplx>& th);
+std::vector<cplx> add_stability_roots(const std::vector<cplx>& th, int* added);
+
 // Algorithmic bytes of the fused SpMV passes of one apply_poly with chain
 // element type `chain` (nothing is launched).
 size_t apply_poly_bytes(const Matrix& A, const Poly& p, VecT chain);

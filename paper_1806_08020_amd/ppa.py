@@ -69,6 +69,8 @@ def _load():
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
         "ppa_poly_roots": (i, [vp, i, P(d), P(d), i, P(i)]),
+        "ppa_poly_log10_pof": (i, [vp, i, P(d), i, P(i)]),
+        "ppa_poly_stabilize": (i, [vp, i, P(vp), P(i)]),
         "ppa_poly_build_workspace_bytes": (i, [vp, i, i, P(sz)]),
         "ppa_poly_build": (i, [vp, i, vp, vp, sz, vp, P(vp)]),
         "ppa_poly_build_double": (i, [vp, i, i, vp, vp, sz, vp, P(vp)]),
@@ -220,6 +222,22 @@ class Poly:
         st = _check(_lib.ppa_poly_build_double(A.h, d1, d2, _ptr(b), _ptr(ws), ws.numel(), _stream(),
                                                C.byref(h)))
         return cls(h, st)
+
+    def log10_pof(self, level: int = 2) -> np.ndarray:
+        """log10 pof(j) of the roots of ``level`` in application order."""
+        cnt = self.degree if level == 2 else self.d1
+        out = np.zeros(max(cnt, 1))
+        c = C.c_int()
+        _check(_lib.ppa_poly_log10_pof(self.h, level, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                       out.size, C.byref(c)))
+        return out[: c.value]
+
+    def stabilized(self, level: int = 2):
+        """(new Poly with the section-7 extra roots at ``level``, roots added)."""
+        h = vp()
+        added = C.c_int()
+        _check(_lib.ppa_poly_stabilize(self.h, level, C.byref(h), C.byref(added)))
+        return Poly(h), added.value
 
     def roots(self, level: int = 2) -> np.ndarray:
         cnt = self.degree if level == 2 else self.d1

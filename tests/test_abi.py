@@ -109,3 +109,50 @@ def test_host_eigvecs_accurate_on_restarted_arnoldi(cdll):
         w, V = ppa.dense_eig(Hm)
         R = Hm @ V - V * w
         assert np.linalg.norm(R, axis=0).max() <= 1e-13 * np.linalg.norm(Hm)
+
+
+def _ex7():
+    from paper_1806_08020_amd import workloads as W
+    lam = np.concatenate([np.arange(1, 100) / 10.0, np.arange(10, 9910), [20000.0]])
+    return W.diag_csr(lam)
+
+
+def test_host_stability_roots_match_oracle(cdll):
+    """Section 7 on the host side of the library: log10 pof and the list with
+    the extra copies placed equal the oracle's, element by element and in
+    order, for Example 7's polynomials (d = 8, 25, 40), Example 9's outer
+    polynomial, and hand-built lists with a conjugate pair and repeated roots."""
+    import oracle as O
+    from paper_1806_08020_amd import ppa
+    A = _ex7()
+    mv = O.csr_matvec(A)
+    b = np.random.default_rng([7, 1]).standard_normal(A.n)
+    cases = [O.gmres_poly(mv, b, d)[0] for d in (8, 25, 40)]
+    b9 = np.random.default_rng(1).standard_normal(A.n)
+    cases.append(O.double_poly(mv, b9, 5, 20)[1])
+    z = 1e12 + 1e11j
+    cases.append(np.array([z, np.conj(z), 2.0, 3.0, 4.0, 5.0], dtype=complex))
+    cases.append(np.array([10.0, 2e10, 3.0, 4.0, 5.0], dtype=complex))
+    cases.append(np.array([1.0, 1.0, 2.0], dtype=complex))     # repeated root: pof 0
+    for roots in cases:
+        P = ppa.Poly.from_roots(roots)
+        lp = P.log10_pof()
+        olp = O.log10_pof(roots)
+        fin = np.isfinite(olp)
+        assert np.array_equal(fin, np.isfinite(lp))
+        assert np.allclose(lp[fin], olp[fin], rtol=0, atol=1e-11)
+        S, added = P.stabilized()
+        want, counts = O.add_stability_roots(roots)
+        assert added == want.size - roots.size == int(np.sum(counts[roots.imag >= 0] *
+                                                             np.where(roots[roots.imag >= 0].imag > 0, 2, 1)))
+        assert S.degree == want.size
+        assert np.array_equal(S.roots(), want)
+    # a double polynomial keeps its other level untouched
+    r1 = np.array([3.0, 7.0], dtype=complex)
+    r2 = cases[3]
+    D = ppa.Poly.from_roots(r2, roots1=r1)
+    S2, added2 = D.stabilized(level=2)
+    assert np.array_equal(S2.roots(1), r1) and added2 > 0
+    assert np.array_equal(S2.roots(2), O.add_stability_roots(r2)[0])
+    S1, added1 = D.stabilized(level=1)
+    assert added1 == 0 and np.array_equal(S1.roots(2), r2)
