@@ -40,6 +40,8 @@ __all__ = [
     "apply_double", "ArnoldiResult", "thick_restart_arnoldi", "pp_eigs",
     "sort_ritz", "keep_count", "thick_restart", "BREAKDOWN_TOL",
     "pof", "log10_pof", "extra_root_counts", "add_stability_roots",
+    "damped_start", "gmres_poly_two", "ideal_order_condition", "order_test_quotients",
+    "damping_heuristic",
 ]
 
 # Breakdown rule (reading): an Arnoldi/GMRES step breaks down when the norm
@@ -210,6 +212,71 @@ def gmres_poly(matvec, b: np.ndarray, d: int, cnt: Counters | None = None):
 # --------------------------------------------------------------------------
 # eq. (2.1): pi(A) v in factored form
 # --------------------------------------------------------------------------
+# ---------------------------------------------------------------- start vectors (sections 5, 6)
+def damped_start(matvec, b: np.ndarray, power: int = 1, alpha: float = 0.0) -> np.ndarray:
+    """Section 6, damped polynomials: the GMRES start vector A^power b, plus
+    alpha * b when alpha != 0 (the A b + alpha b family).  Premultiplying by
+    A damps b's components along eigenvectors of small eigenvalues, so the
+    GMRES polynomial tries less hard to be small there."""
+    x = np.array(b, dtype=float)
+    for _ in range(power):
+        x = matvec(x)
+    return x + alpha * np.asarray(b, dtype=float) if alpha != 0.0 else x
+
+
+def gmres_poly_two(matvec, b1: np.ndarray, b2: np.ndarray, d: int, cnt: Counters | None = None):
+    """Section 5, 'Polynomial determined by two starting vectors': b1, b2
+    scaled to norm 1/sqrt(2) each, one GMRES(d) cycle on the block-diagonal
+    system diag(A, A) of dimension 2n from [b1; b2]; its polynomial is
+    applied to A.  Returns (roots in Leja order, effective degree)."""
+    n = b1.size
+    bh = np.concatenate([b1 / (np.sqrt(2.0) * np.linalg.norm(b1)),
+                         b2 / (np.sqrt(2.0) * np.linalg.norm(b2))])
+
+    def mv2(x):
+        return np.concatenate([matvec(x[:n]), matvec(x[n:])])
+    return gmres_poly(mv2, bh, d, cnt)
+
+
+def ideal_order_condition(mu: np.ndarray, nev: int, k: int) -> bool:
+    """Section 6, step 4: |mu_1| <= ... <= |mu_nev| < min_{nev < j <= k} |mu_j|,
+    for Rayleigh quotients listed in the order of |1 - nu_j|."""
+    a = np.abs(np.asarray(mu)[:k])
+    mono = all(a[i] <= a[i + 1] for i in range(nev - 1))
+    return bool(mono and (nev == k or a[nev - 1] < a[nev:k].min()))
+
+
+def order_test_quotients(csr, roots, b: np.ndarray, m: int, k: int) -> np.ndarray:
+    """Section 6, steps 1-3: one Arnoldi(m,k) cycle on pi(A) from b, Ritz
+    values nu_j ordered by |1 - nu_j|, and mu_j = y_j^* A y_j for the first k
+    (unit Ritz vectors), returned in that order."""
+    amv = csr_matvec(csr)
+    op = (lambda x: apply_poly(amv, roots, x))
+    res = thick_restart_arnoldi(op, amv, b, m, k, k, 0.0, 1)
+    o = sort_ritz(res.nu)
+    return res.mu[o]
+
+
+def damping_heuristic(csr, b: np.ndarray, d: int, m: int, k: int, nev: int):
+    """Section 6, 'Heuristic for damping b and adjusting d'.  Build pi from b
+    and test the Ideal Order Condition on one Arnoldi(m,k) cycle; if it
+    fails, rebuild pi from A b and test again; while it still fails, halve d
+    (keeping the damped start vector) and test again, down to d = 1.
+    Returns (roots, info) with info = dict(d, damped, attempts, held)."""
+    amv = csr_matvec(csr)
+    start, damped, attempts = np.array(b, dtype=float), False, 0
+    while True:
+        roots, _ = gmres_poly(amv, start, d)
+        attempts += 1
+        held = ideal_order_condition(order_test_quotients(csr, roots, b, m, k), nev, k)
+        if held or d == 1:
+            return roots, dict(d=d, damped=damped, attempts=attempts, held=held)
+        if not damped:
+            start, damped = damped_start(amv, b, 1), True
+        else:
+            d = d // 2
+
+
 # ---------------------------------------------------------------- stability (section 7)
 def pof(theta: np.ndarray) -> np.ndarray:
     """Section 7: pof(j) = prod_{i != j} |1 - theta_j / theta_i|, the product
