@@ -138,6 +138,53 @@ def stability_report(P, dbl):
     return out
 
 
+def safeguards_report():
+    """Sections 5-6 on the device: Example 6 (A = diag(1..10000), d = 50,
+    Arnoldi(50,20), nev = 15) with the Ideal-Order-Condition heuristic
+    against the plain polynomial, and Example 4 (A = diag(1..1000), d = 10, the
+    start vector's last 100 components scaled by 0.01) with one and with two
+    start vectors.  'correct' counts returned eigenvalues equal to the 15
+    smallest."""
+    import torch
+    from paper_1806_08020_amd import ppa
+    from paper_1806_08020_amd import workloads as W
+
+    def solve(A, P, v0, cycles):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ppa.eigs(A, P, v0, 50, 20, 15, rtol=1e-8, max_cycles=cycles)
+        torch.cuda.synchronize()
+        mus = np.sort(r.mu.real)
+        correct = int(sum(np.min(np.abs(mus - w)) < 1e-6 for w in range(1, 16)))
+        return {"converged": bool(r.converged), "cycles": int(r.cycles), "correct": correct,
+                "ms": round((time.perf_counter() - t0) * 1e3, 2)}
+
+    out = {}
+    csr = W.diag_csr(np.arange(1, 10001, dtype=float))
+    rng = np.random.default_rng([6, 1])
+    b = torch.as_tensor(rng.standard_normal(csr.n), device="cuda")
+    v0 = torch.as_tensor(rng.standard_normal(csr.n), device="cuda")
+    A = ppa.Matrix(csr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P, info = ppa.Poly.build_ex(A, 50, b, test=(50, 20, 15))
+    torch.cuda.synchronize()
+    t_build = (time.perf_counter() - t0) * 1e3
+    P0 = ppa.Poly.build(A, 50, b)
+    out["example6_d50"] = {"heuristic": dict(info, build_ms=round(t_build, 2)),
+                           "plain": solve(A, P0, v0, 30), "with_heuristic": solve(A, P, v0, 30)}
+    csr = W.diag_csr(np.arange(1, 1001, dtype=float))
+    rng = np.random.default_rng([4, 0])
+    b, v0, b2 = (rng.standard_normal(csr.n) for _ in range(3))
+    b[-100:] *= 0.01
+    A = ppa.Matrix(csr)
+    bt, v0t, b2t = (torch.as_tensor(x, device="cuda") for x in (b, v0, b2))
+    P1, _ = ppa.Poly.build_ex(A, 10, bt)
+    P2, _ = ppa.Poly.build_ex(A, 10, bt, b2=b2t)
+    out["example4_skewed_d10"] = {"one_start": solve(A, P1, v0t, 40), "two_starts": solve(A, P2, v0t, 40)}
+    return out
+
+
 def served_mix_report(count):
     """Served mix (2-D convection-diffusion solves of random size, degree and
     nev, seeded): capacity from a closed-loop run (all requests at t = 0),
@@ -313,6 +360,7 @@ def main():
                     "non-normal operator the two runs may certify different pseudo-eigenvalues",
         }
     line["stability"] = stability_report(P, dbl)
+    line["safeguards"] = safeguards_report()
     if not args.no_serve:
         line["served"] = served_mix_report(args.serve_requests)
     if not args.no_cpu_baseline:

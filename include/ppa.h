@@ -154,6 +154,52 @@ int ppa_poly_build(const ppa_matrix* A, int d, const double* b_d,
 int ppa_poly_build_double(const ppa_matrix* A, int d1, int d2, const double* b_d,
                           void* ws_d, size_t ws_bytes, void* stream, ppa_poly** out);
 
+/* Polynomial-quality safeguards (sections 5 and 6).
+ *   d        requested degree.
+ *   damp     GMRES start vector A^damp b (0, 1 or 2): premultiplying by A damps
+ *            b's components along eigenvectors of small eigenvalues (section 6).
+ *   alpha    when nonzero and damp >= 1, alpha * b is added on the last
+ *            product (the A b + alpha b family of section 6).
+ *   test_m, test_k, test_nev
+ *            0: no test.  Otherwise the Ideal-Order-Condition heuristic of
+ *            section 6: one Arnoldi(test_m, test_k) cycle on pi(A) from b,
+ *            Ritz values ordered by |1 - nu|, Rayleigh quotients mu_j = y_j^* A y_j
+ *            of the first test_k, and the condition |mu_1| <= ... <= |mu_nev| <
+ *            min_{nev < j <= k} |mu_j|.  If it fails the start vector is damped
+ *            once more (A b in place of b, up to damp = 2); while it still fails
+ *            the degree is halved, down to 1.  Needs 1 <= test_nev <= test_k <
+ *            test_m <= 64, test_k <= 32, n > test_m. */
+typedef struct {
+    int d;
+    int damp;
+    double alpha;
+    int test_m, test_k, test_nev;
+} ppa_poly_build_opts;
+
+typedef struct {
+    int degree;     /* degree of the returned polynomial                       */
+    int damp;       /* damping power of its start vector                       */
+    int attempts;   /* polynomials built                                        */
+    int held;       /* 1/0: the Ideal Order Condition held / failed for it;
+                       -1: not tested                                          */
+} ppa_poly_build_info;
+
+/* Workspace bytes of ppa_poly_build_ex (two_start: b2_d will be given). */
+int ppa_poly_build_ex_workspace_bytes(const ppa_matrix* A, const ppa_poly_build_opts* o,
+                                      int two_start, size_t* bytes);
+
+/* GMRES polynomial with the safeguards above.  b_d: double[n] start vector.
+ * b2_d: NULL, or a second start vector (section 5, "polynomial determined by
+ * two starting vectors"): GMRES(d) then runs on the block-diagonal system
+ * diag(A, A) of dimension 2n from [b; b2] with each half scaled to norm
+ * 1/sqrt(2), and its polynomial is returned (damping applies to both
+ * vectors; the order test cycle starts from b_d).  *info receives what was
+ * done.  Synchronises `stream`.  Returns PPA_WARN_DEGREE_REDUCED as
+ * ppa_poly_build does. */
+int ppa_poly_build_ex(const ppa_matrix* A, const ppa_poly_build_opts* o, const double* b_d,
+                      const double* b2_d, void* ws_d, size_t ws_bytes, void* stream,
+                      ppa_poly** out, ppa_poly_build_info* info);
+
 /* Workspace bytes for ppa_poly_apply. */
 int ppa_poly_apply_workspace_bytes(const ppa_matrix* A, const ppa_poly* p, int precision,
                                    size_t* bytes);

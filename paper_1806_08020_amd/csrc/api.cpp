@@ -271,6 +271,39 @@ int ppa_poly_build_double(const ppa_matrix* h, int d1, int d2, const double* b_d
     });
 }
 
+int ppa_poly_build_ex_workspace_bytes(const ppa_matrix* h, const ppa_poly_build_opts* o,
+                                      int two_start, size_t* bytes) {
+    return guarded([&] {
+        PPA_REQUIRE(h && o && bytes, "matrix, options and bytes are required");
+        PPA_REQUIRE(o->d >= 1, "degree must be >= 1");
+        *bytes = poly_build_ex_ws(*reinterpret_cast<const Matrix*>(h), *o, two_start != 0);
+        return PPA_OK;
+    });
+}
+
+int ppa_poly_build_ex(const ppa_matrix* h, const ppa_poly_build_opts* o, const double* b_d,
+                      const double* b2_d, void* ws_d, size_t ws_bytes, void* stream,
+                      ppa_poly** out, ppa_poly_build_info* info) {
+    return guarded([&] {
+        PPA_REQUIRE(h && o && b_d && out, "matrix, options, b and out are required");
+        *out = nullptr;
+        PPA_REQUIRE(ws_d != nullptr, "workspace is required");
+        Poly* p = new Poly();
+        ppa_poly_build_info inf{};
+        int st = PPA_OK;
+        try {
+            st = poly_build_ex(*reinterpret_cast<const Matrix*>(h), *o, b_d, b2_d, ws_d, ws_bytes,
+                               (hipStream_t)stream, *p, inf);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        if (info) *info = inf;
+        *out = reinterpret_cast<ppa_poly*>(p);
+        return st;
+    });
+}
+
 int ppa_poly_apply_workspace_bytes(const ppa_matrix* h, const ppa_poly* ph, int precision,
                                    size_t* bytes) {
     return guarded([&] {

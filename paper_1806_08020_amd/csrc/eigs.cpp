@@ -97,21 +97,47 @@ void apply_tau(const Matrix& A, const std::vector<cplx>& roots1, const double* x
 }
 
 // One cycle of GMRES(d) from b with operator A (roots1 empty) or tau(A).
+// With b2 (section 5, two start vectors; roots1 empty) the cycle runs on the
+// block-diagonal system diag(A, A) of dimension 2n from [b; b2], each half
+// scaled to norm 1/sqrt(2): the Krylov vectors have length 2n and each
+// operator application is one fused pass per half.  The workspace must be
+// carved for the vector length used.
 // Returns the effective degree; Hbar receives (d_eff+1) x d_eff.
 int gmres_cycle(const Matrix& A, const std::vector<cplx>& roots1, int d, const double* b,
-                GmresWs& g, hipStream_t s, std::vector<double>& Hbar) {
+                const double* b2, GmresWs& g, hipStream_t s, std::vector<double>& Hbar) {
     const int64_t n = A.n;
+    const int64_t N = b2 ? 2 * n : n;
     launch_zero(g.H, (int64_t)(d + 1) * d, s);
-    set_unit(n, b, g.V, g.dpart, g.cw.nb, g.dout, s);
+    if (b2) {
+        const int nbh = cgs_blocks(n);
+        const double n1 = std::sqrt(norm2_host(n, b, g.dpart, nbh, g.dout, s));
+        const double n2 = std::sqrt(norm2_host(n, b2, g.dpart, nbh, g.dout, s));
+        if (!(n1 > 0.0) || !(n2 > 0.0) || !std::isfinite(n1) || !std::isfinite(n2))
+            fail(PPA_ERR_NONFINITE, "start vector has zero or non-finite norm");
+        hipLaunchKernelGGL(k_copy, dim3(sgrid(n)), dim3(256), 0, s, b, g.V, n);
+        hipLaunchKernelGGL(k_copy, dim3(sgrid(n)), dim3(256), 0, s, b2, g.V + n, n);
+        hipLaunchKernelGGL(k_scale_host, dim3(sgrid(n)), dim3(256), 0, s, g.V, n, 1.0 / (std::sqrt(2.0) * n1));
+        hipLaunchKernelGGL(k_scale_host, dim3(sgrid(n)), dim3(256), 0, s, g.V + n, n,
+                           1.0 / (std::sqrt(2.0) * n2));
+        PPA_HIP(hipGetLastError());
+    } else {
+        set_unit(n, b, g.V, g.dpart, g.cw.nb, g.dout, s);
+    }
     for (int j = 0; j < d; ++j) {
         const double* vj = g.V + (size_t)j * g.ld;
-        if (roots1.empty())
+        if (b2) {
             launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj, 0.0, nullptr, 0.0,
                               nullptr, g.w, s);
-        else
+            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj + n, 0.0, nullptr, 0.0,
+                              nullptr, g.w + n, s);
+        } else if (roots1.empty()) {
+            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj, 0.0, nullptr, 0.0,
+                              nullptr, g.w, s);
+        } else {
             apply_tau(A, roots1, vj, g.w, g.aw, s);
+        }
         double* vn = g.V + (size_t)(j + 1) * g.ld;
-        launch_cgs2(n, j + 1, g.V, g.ld, g.w, vn, g.H + (size_t)j * (d + 1), vn, kBreakdownTol,
+        launch_cgs2(N, j + 1, g.V, g.ld, g.w, vn, g.H + (size_t)j * (d + 1), vn, kBreakdownTol,
                     g.cw, s);
     }
     std::vector<double> H((size_t)(d + 1) * d);
@@ -158,7 +184,7 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
     c.check();
     int status = PPA_OK;
     std::vector<double> Hb;
-    int de = gmres_cycle(A, {}, d1, b, g, s, Hb);
+    int de = gmres_cycle(A, {}, d1, b, nullptr, g, s, Hb);
     if (de < d1) status = PPA_WARN_DEGREE_REDUCED;
     std::vector<cplx> r1 = leja_order(harmonic_ritz(de, Hb));
     if (!dbl) {
@@ -166,7 +192,7 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
         out.roots1.clear();
         return status;
     }
-    de = gmres_cycle(A, r1, d2, b, g, s, Hb);
+    de = gmres_cycle(A, r1, d2, b, nullptr, g, s, Hb);
     if (de < d2) status = PPA_WARN_DEGREE_REDUCED;
     out.roots1 = r1;
     out.roots = leja_order(harmonic_ritz(de, Hb));
@@ -497,6 +523,150 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     if (converged) return PPA_OK;
     if (broke) return PPA_WARN_BREAKDOWN;
     return PPA_WARN_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------- safeguards
+// Sections 5-6: a GMRES polynomial from a damped start vector A^p b (+ alpha
+// b), optionally from two start vectors, optionally checked by the
+// Ideal-Order-Condition heuristic: one Arnoldi(m,k) cycle on pi(A) from b,
+// Ritz values ordered by |1 - nu|, Rayleigh quotients mu_j = y_j^* A y_j for
+// j <= k, and the test |mu_1| <= ... <= |mu_nev| < min_{nev < j <= k} |mu_j|.
+// On failure the start vector is damped once more (A b in place of b), and
+// while the test still fails the degree is halved (keeping the damped start
+// vector), down to d = 1.
+namespace {
+
+struct BuildExWs {
+    double* s1 = nullptr;
+    double* s2 = nullptr;
+    double* tmp = nullptr;
+    GmresWs g;
+    void* ews = nullptr;
+    size_t ews_bytes = 0;
+};
+
+ppa_eigs_opts test_opts(const ppa_poly_build_opts& o) {
+    ppa_eigs_opts t{};
+    t.m = o.test_m;
+    t.k = o.test_k;
+    t.nev = o.test_k;
+    t.max_cycles = 1;
+    t.rtol = 0.0;
+    t.anorm = 0.0;
+    t.precision = PPA_F64;
+    t.flags = 0;
+    return t;
+}
+
+void carve_build_ex(Carver& c, const Matrix& A, const ppa_poly_build_opts& o, bool two,
+                    BuildExWs& w) {
+    const int64_t n = A.n;
+    w.s1 = c.take<double>((size_t)n);
+    if (two) w.s2 = c.take<double>((size_t)n);
+    w.tmp = c.take<double>((size_t)n);
+    carve_gmres(c, two ? 2 * n : n, o.d, false, w.g);
+    if (o.test_m > 0) {
+        Poly single;
+        single.roots.assign(1, cplx(1.0, 0.0));
+        w.ews_bytes = eigs_ws(A, &single, test_opts(o));
+        w.ews = c.take<char>(w.ews_bytes);
+    }
+}
+
+// dst = A^power b (+ alpha b on the last pass), power 0..2
+void damp_start(const Matrix& A, const double* b, int power, double alpha, double* dst, double* tmp,
+                hipStream_t s) {
+    if (power == 0) {
+        hipLaunchKernelGGL(k_copy, dim3(sgrid(A.n)), dim3(256), 0, s, b, dst, A.n);
+        PPA_HIP(hipGetLastError());
+        return;
+    }
+    const double* cur = b;
+    for (int p = 0; p < power; ++p) {
+        const bool last = p == power - 1;
+        double* out = last ? dst : tmp;
+        launch_fused_spmv(A, VecT::F64, VecT::F64, last ? alpha : 0.0,
+                          (last && alpha != 0.0) ? b : nullptr, 1.0, cur, 0.0, nullptr, 0.0,
+                          nullptr, out, s);
+        cur = out;
+    }
+}
+
+}  // namespace
+
+size_t poly_build_ex_ws(const Matrix& A, const ppa_poly_build_opts& o, bool two) {
+    Carver c(nullptr, 0);
+    BuildExWs w;
+    carve_build_ex(c, A, o, two, w);
+    return c.bytes();
+}
+
+int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b, const double* b2,
+                  void* ws, size_t ws_bytes, hipStream_t s, Poly& out, ppa_poly_build_info& info) {
+    PPA_REQUIRE(o.d >= 1 && o.d <= CGS_JMAX_ALL - 2, "polynomial degree out of range");
+    PPA_REQUIRE(o.damp >= 0 && o.damp <= 2, "damping power must be 0, 1 or 2");
+    const bool test = o.test_m > 0;
+    if (test) {
+        PPA_REQUIRE(o.test_m >= 2 && o.test_m <= 64 && o.test_nev >= 1 && o.test_nev <= o.test_k &&
+                        o.test_k < o.test_m && o.test_k <= 32,
+                    "order test: need 1 <= nev <= k < m <= 64, k <= 32");
+        PPA_REQUIRE(A.n >= o.test_m + 1, "order test: n must exceed m");
+    }
+    Carver c(ws, ws_bytes);
+    BuildExWs w;
+    carve_build_ex(c, A, o, b2 != nullptr, w);
+    c.check();
+    int d = o.d, power = o.damp, attempts = 0, status = PPA_OK;
+    int held = -1;
+    for (;;) {
+        damp_start(A, b, power, o.alpha, w.s1, w.tmp, s);
+        if (b2) damp_start(A, b2, power, o.alpha, w.s2, w.tmp, s);
+        std::vector<double> Hb;
+        const int de = gmres_cycle(A, {}, d, w.s1, b2 ? w.s2 : nullptr, w.g, s, Hb);
+        status = de < d ? PPA_WARN_DEGREE_REDUCED : PPA_OK;
+        Poly p;
+        p.roots = leja_order(harmonic_ritz(de, Hb));
+        ++attempts;
+        if (test) {
+            const ppa_eigs_opts t = test_opts(o);
+            std::vector<double> lre(t.nev), lim(t.nev), res(t.nev), nre(t.nev), nim(t.nev);
+            ppa_eigs_result r{};
+            r.lam_re = lre.data();
+            r.lam_im = lim.data();
+            r.resid = res.data();
+            r.ritz_re = nre.data();
+            r.ritz_im = nim.data();
+            (void)eigs(A, &p, t, b, w.ews, w.ews_bytes, s, r);
+            // the returned pairs back in the order of |1 - nu|
+            std::vector<cplx> nu, mu;
+            for (int i = 0; i < t.nev; ++i)
+                if (std::isfinite(lre[i])) {
+                    nu.emplace_back(nre[i], nim[i]);
+                    mu.emplace_back(lre[i], lim[i]);
+                }
+            const std::vector<int> ord = sort_ritz(nu, 1.0);
+            const int kk = (int)ord.size(), nev = std::min(o.test_nev, kk);
+            bool ok = nev >= 1;
+            for (int i = 0; ok && i + 1 < nev; ++i)
+                ok = std::abs(mu[ord[i]]) <= std::abs(mu[ord[i + 1]]);
+            for (int i = nev; ok && i < kk; ++i) ok = std::abs(mu[ord[nev - 1]]) < std::abs(mu[ord[i]]);
+            held = ok ? 1 : 0;
+        }
+        if (!test || held == 1 || d == 1) {
+            out.roots = std::move(p.roots);
+            out.roots1.clear();
+            break;
+        }
+        if (power == o.damp && power < 2)
+            ++power;          // damp: A b in place of b
+        else
+            d = std::max(1, d / 2);
+    }
+    info.degree = (int)out.roots.size();
+    info.damp = power;
+    info.attempts = attempts;
+    info.held = held;
+    return status;
 }
 
 }  // namespace ppa

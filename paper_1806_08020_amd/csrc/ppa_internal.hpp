@@ -266,6 +266,9 @@ size_t poly_build_ws(int64_t n, int d, bool dbl);
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
                hipStream_t s, Poly& out);
 size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o);
+size_t poly_build_ex_ws(const Matrix& A, const ppa_poly_build_opts& o, bool two);
+int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b, const double* b2,
+                  void* ws, size_t ws_bytes, hipStream_t s, Poly& out, ppa_poly_build_info& info);
 int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v0, void* ws,
          size_t ws_bytes, hipStream_t s, ppa_eigs_result& r);
 

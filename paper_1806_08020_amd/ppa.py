@@ -45,6 +45,15 @@ class EigsResult(C.Structure):
                 ("t_apply_ms", C.c_double), ("t_cgs_ms", C.c_double)]
 
 
+class PolyBuildOpts(C.Structure):
+    _fields_ = [("d", C.c_int), ("damp", C.c_int), ("alpha", C.c_double), ("test_m", C.c_int),
+                ("test_k", C.c_int), ("test_nev", C.c_int)]
+
+
+class PolyBuildInfo(C.Structure):
+    _fields_ = [("degree", C.c_int), ("damp", C.c_int), ("attempts", C.c_int), ("held", C.c_int)]
+
+
 class BatchRequest(C.Structure):
     _fields_ = [("n", C.c_int64), ("rowptr_d", vp), ("colind_d", vp), ("val_d", vp),
                 ("anorm", C.c_double), ("d", C.c_int), ("m", C.c_int), ("k", C.c_int),
@@ -69,6 +78,8 @@ def _load():
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
         "ppa_poly_roots": (i, [vp, i, P(d), P(d), i, P(i)]),
+        "ppa_poly_build_ex_workspace_bytes": (i, [vp, P(PolyBuildOpts), i, P(sz)]),
+        "ppa_poly_build_ex": (i, [vp, P(PolyBuildOpts), vp, vp, vp, sz, vp, P(vp), P(PolyBuildInfo)]),
         "ppa_poly_log10_pof": (i, [vp, i, P(d), i, P(i)]),
         "ppa_poly_stabilize": (i, [vp, i, P(vp), P(i)]),
         "ppa_poly_build_workspace_bytes": (i, [vp, i, i, P(sz)]),
@@ -222,6 +233,24 @@ class Poly:
         st = _check(_lib.ppa_poly_build_double(A.h, d1, d2, _ptr(b), _ptr(ws), ws.numel(), _stream(),
                                                C.byref(h)))
         return cls(h, st)
+
+    @classmethod
+    def build_ex(cls, A: Matrix, d: int, b: torch.Tensor, b2: torch.Tensor | None = None,
+                 damp: int = 0, alpha: float = 0.0, test=None):
+        """GMRES polynomial with the safeguards of sections 5-6: damped start
+        vector A^damp b (+ alpha b), optional second start vector b2, optional
+        Ideal-Order-Condition test ``test = (m, k, nev)``.  Returns (Poly, info)."""
+        tm, tk, tn = test if test is not None else (0, 0, 0)
+        o = PolyBuildOpts(d, damp, alpha, tm, tk, tn)
+        nb = C.c_size_t()
+        _check(_lib.ppa_poly_build_ex_workspace_bytes(A.h, C.byref(o), int(b2 is not None), C.byref(nb)))
+        ws = _workspace(nb.value)
+        h = vp()
+        info = PolyBuildInfo()
+        st = _check(_lib.ppa_poly_build_ex(A.h, C.byref(o), _ptr(b), _ptr(b2), _ptr(ws), ws.numel(),
+                                           _stream(), C.byref(h), C.byref(info)))
+        return cls(h, st), dict(degree=info.degree, damp=info.damp, attempts=info.attempts,
+                                held=info.held)
 
     def log10_pof(self, level: int = 2) -> np.ndarray:
         """log10 pof(j) of the roots of ``level`` in application order."""
