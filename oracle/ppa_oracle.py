@@ -497,7 +497,7 @@ def _ritz_test(Vm, g_cols, amatvec, cnt):
 def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
                           rtol_abs: float, max_cycles: int,
                           cnt: Counters | None = None, hook=None,
-                          target: float = 1.0) -> ArnoldiResult:
+                          target: float = 1.0, shift: float = 0.0) -> ArnoldiResult:
     """Thick-restarted Arnoldi(m,k) with exact shifts on the operator ``op``
     (pi(A) or pi_2(tau(A))), convergence tested on A (section 4).
 
@@ -556,22 +556,29 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
         if hook is not None:
             hook("restart", V.copy(), H.copy(), kk)
     mu, rr, Y, nus = res
-    o = np.lexsort((mu.imag, mu.real, np.abs(mu)))
+    # returned by distance to the target point of A (the shift; R9)
+    o = np.lexsort((mu.imag, mu.real, np.abs(mu - shift)))
     return ArnoldiResult(mu=mu[o], resid=rr[o], Y=Y[:, o], converged=conv, cycles=cycle,
                          counters=cnt, nu=nus[o], history=history, breakdown=broke)
 
 
 def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
             d: int | None = None, d1: int | None = None, d2: int | None = None,
-            rtol: float = 1e-8, max_cycles: int = 100, roots=None, hook=None):
+            rtol: float = 1e-8, max_cycles: int = 100, roots=None, hook=None,
+            shift: float = 0.0):
     """Polynomial preconditioned Arnoldi end to end (section 2 listing;
     section 8 for ``d1, d2``).  rtol is relative: the absolute bound is
     rtol * ||A||_inf.  ``d=0`` runs standard Arnoldi on A.  ``roots`` may
     give a ready root list (single polynomial) or a pair (roots1, roots2).
+    ``shift`` = mu (section 2 footnote: for eigenvalues near mu use A - mu I):
+    the polynomial is built for and applied to A - mu I, the Rayleigh
+    quotients and residuals are those of A (the residual is the same for
+    both), and the eigenvalues are returned by their distance to mu.
 
     Returns (ArnoldiResult, roots) where roots is a list or a (r1, r2) pair."""
-    amv = csr_matvec(csr)
+    amv0 = csr_matvec(csr)
     cnt = Counters()
+    amv = (lambda x: amv0(x) - shift * x) if shift != 0.0 else amv0
 
     if roots is not None:
         rts = roots
@@ -592,6 +599,6 @@ def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
     else:
         def op(x):
             return apply_poly(amv, rts, x, cnt)
-    res = thick_restart_arnoldi(op, amv, v0, m, k, nev, rtol * infnorm(csr), max_cycles, cnt, hook,
-                                target=0.0 if rts is None else 1.0)
+    res = thick_restart_arnoldi(op, amv0, v0, m, k, nev, rtol * infnorm(csr), max_cycles, cnt, hook,
+                                target=0.0 if rts is None else 1.0, shift=shift)
     return res, rts
