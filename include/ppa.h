@@ -174,6 +174,9 @@ typedef struct {
     int damp;
     double alpha;
     int test_m, test_k, test_nev;
+    double shift;   /* target mu (section 2 footnote): the polynomial is built for
+                       and applied to A - mu I; the order test and ppa_eigs then
+                       rank eigenvalues by their distance to mu (0: the origin) */
 } ppa_poly_build_opts;
 
 typedef struct {
@@ -183,6 +186,15 @@ typedef struct {
     int held;       /* 1/0: the Ideal Order Condition held / failed for it;
                        -1: not tested                                          */
 } ppa_poly_build_info;
+
+/* The target mu of a polynomial: it acts on A - mu I (set by
+ * ppa_poly_build_ex; 0 for the other builders).  ppa_poly_set_shift sets it
+ * on a polynomial whose roots were computed for A - mu I (ppa_poly_from_roots).
+ * ppa_eigs with such a polynomial iterates on pi(A - mu I), tests and
+ * returns Rayleigh quotients of A itself (the residual A y - lam y is the
+ * same for both) ordered by distance to mu.  Real mu only. */
+int ppa_poly_shift(const ppa_poly* p, double* shift);
+int ppa_poly_set_shift(ppa_poly* p, double shift);
 
 /* Workspace bytes of ppa_poly_build_ex (two_start: b2_d will be given). */
 int ppa_poly_build_ex_workspace_bytes(const ppa_matrix* A, const ppa_poly_build_opts* o,

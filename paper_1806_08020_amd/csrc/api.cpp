@@ -6,6 +6,8 @@
 
 #include "ppa_internal.hpp"
 
+#include <cmath>
+
 namespace ppa {
 
 static thread_local std::string g_err;
@@ -268,6 +270,23 @@ int ppa_poly_build_double(const ppa_matrix* h, int d1, int d2, const double* b_d
         }
         *out = reinterpret_cast<ppa_poly*>(p);
         return st;
+    });
+}
+
+int ppa_poly_shift(const ppa_poly* h, double* shift) {
+    return guarded([&] {
+        PPA_REQUIRE(h && shift, "poly and shift are required");
+        *shift = reinterpret_cast<const Poly*>(h)->shift;
+        return PPA_OK;
+    });
+}
+
+int ppa_poly_set_shift(ppa_poly* h, double shift) {
+    return guarded([&] {
+        PPA_REQUIRE(h != nullptr, "poly is NULL");
+        PPA_REQUIRE(std::isfinite(shift), "shift must be finite");
+        reinterpret_cast<Poly*>(h)->shift = shift;
+        return PPA_OK;
     });
 }
 

@@ -92,8 +92,8 @@ void carve_gmres(Carver& c, int64_t n, int d, bool tau, GmresWs& g) {
 // tau(A) x = x - pi_1(A) x  (F64): the last pass of the pi_1 chain is scaled
 // by -1 and adds x in its epilogue.
 void apply_tau(const Matrix& A, const std::vector<cplx>& roots1, const double* x, double* out,
-               ApplyWs& aw, hipStream_t s) {
-    apply_single_epilogue(A, roots1, x, out, -1.0, 1.0, x, aw, s);
+               ApplyWs& aw, hipStream_t s, double sigma) {
+    apply_single_epilogue(A, roots1, x, out, -1.0, 1.0, x, aw, s, sigma);
 }
 
 // One cycle of GMRES(d) from b with operator A (roots1 empty) or tau(A).
@@ -104,7 +104,8 @@ void apply_tau(const Matrix& A, const std::vector<cplx>& roots1, const double* x
 // carved for the vector length used.
 // Returns the effective degree; Hbar receives (d_eff+1) x d_eff.
 int gmres_cycle(const Matrix& A, const std::vector<cplx>& roots1, int d, const double* b,
-                const double* b2, GmresWs& g, hipStream_t s, std::vector<double>& Hbar) {
+                const double* b2, double sigma, GmresWs& g, hipStream_t s,
+                std::vector<double>& Hbar) {
     const int64_t n = A.n;
     const int64_t N = b2 ? 2 * n : n;
     launch_zero(g.H, (int64_t)(d + 1) * d, s);
@@ -125,16 +126,19 @@ int gmres_cycle(const Matrix& A, const std::vector<cplx>& roots1, int d, const d
     }
     for (int j = 0; j < d; ++j) {
         const double* vj = g.V + (size_t)j * g.ld;
+        // (A - sigma I) v: the shift is the coefficient of the gathered vector
+        // itself in the fused epilogue
+        const bool sh = sigma != 0.0;
         if (b2) {
-            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj, 0.0, nullptr, 0.0,
-                              nullptr, g.w, s);
-            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj + n, 0.0, nullptr, 0.0,
-                              nullptr, g.w + n, s);
+            launch_fused_spmv(A, VecT::F64, VecT::F64, -sigma, sh ? vj : nullptr, 1.0, vj, 0.0,
+                              nullptr, 0.0, nullptr, g.w, s);
+            launch_fused_spmv(A, VecT::F64, VecT::F64, -sigma, sh ? vj + n : nullptr, 1.0, vj + n,
+                              0.0, nullptr, 0.0, nullptr, g.w + n, s);
         } else if (roots1.empty()) {
-            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, vj, 0.0, nullptr, 0.0,
-                              nullptr, g.w, s);
+            launch_fused_spmv(A, VecT::F64, VecT::F64, -sigma, sh ? vj : nullptr, 1.0, vj, 0.0,
+                              nullptr, 0.0, nullptr, g.w, s);
         } else {
-            apply_tau(A, roots1, vj, g.w, g.aw, s);
+            apply_tau(A, roots1, vj, g.w, g.aw, s, sigma);
         }
         double* vn = g.V + (size_t)(j + 1) * g.ld;
         launch_cgs2(N, j + 1, g.V, g.ld, g.w, vn, g.H + (size_t)j * (d + 1), vn, kBreakdownTol,
@@ -174,7 +178,7 @@ size_t poly_build_ws(int64_t n, int d, bool dbl) {
 }
 
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
-               hipStream_t s, Poly& out) {
+               hipStream_t s, Poly& out, double sigma) {
     const bool dbl = d2 > 0;
     const int dmax = std::max(d1, d2);
     PPA_REQUIRE(d1 >= 1 && dmax <= CGS_JMAX_ALL - 2, "polynomial degree out of range");
@@ -184,7 +188,8 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
     c.check();
     int status = PPA_OK;
     std::vector<double> Hb;
-    int de = gmres_cycle(A, {}, d1, b, nullptr, g, s, Hb);
+    out.shift = sigma;
+    int de = gmres_cycle(A, {}, d1, b, nullptr, sigma, g, s, Hb);
     if (de < d1) status = PPA_WARN_DEGREE_REDUCED;
     std::vector<cplx> r1 = leja_order(harmonic_ritz(de, Hb));
     if (!dbl) {
@@ -192,7 +197,7 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
         out.roots1.clear();
         return status;
     }
-    de = gmres_cycle(A, r1, d2, b, nullptr, g, s, Hb);
+    de = gmres_cycle(A, r1, d2, b, nullptr, sigma, g, s, Hb);
     if (de < d2) status = PPA_WARN_DEGREE_REDUCED;
     out.roots1 = r1;
     out.roots = leja_order(harmonic_ritz(de, Hb));
@@ -463,8 +468,10 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     const int nw = (int)last.mu.size();
     std::vector<int> ord(nw);
     std::iota(ord.begin(), ord.end(), 0);
+    // returned by distance to the target (the polynomial's shift; 0: the origin)
+    const double tgt = p ? p->shift : 0.0;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-        const double ma = std::abs(last.mu[a]), mb = std::abs(last.mu[b]);
+        const double ma = std::abs(last.mu[a] - tgt), mb = std::abs(last.mu[b] - tgt);
         if (ma != mb) return ma < mb;
         if (last.mu[a].real() != last.mu[b].real()) return last.mu[a].real() < last.mu[b].real();
         return last.mu[a].imag() < last.mu[b].imag();
@@ -622,10 +629,11 @@ int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b
         damp_start(A, b, power, o.alpha, w.s1, w.tmp, s);
         if (b2) damp_start(A, b2, power, o.alpha, w.s2, w.tmp, s);
         std::vector<double> Hb;
-        const int de = gmres_cycle(A, {}, d, w.s1, b2 ? w.s2 : nullptr, w.g, s, Hb);
+        const int de = gmres_cycle(A, {}, d, w.s1, b2 ? w.s2 : nullptr, o.shift, w.g, s, Hb);
         status = de < d ? PPA_WARN_DEGREE_REDUCED : PPA_OK;
         Poly p;
         p.roots = leja_order(harmonic_ritz(de, Hb));
+        p.shift = o.shift;
         ++attempts;
         if (test) {
             const ppa_eigs_opts t = test_opts(o);
@@ -647,14 +655,16 @@ int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b
             const std::vector<int> ord = sort_ritz(nu, 1.0);
             const int kk = (int)ord.size(), nev = std::min(o.test_nev, kk);
             bool ok = nev >= 1;
-            for (int i = 0; ok && i + 1 < nev; ++i)
-                ok = std::abs(mu[ord[i]]) <= std::abs(mu[ord[i + 1]]);
-            for (int i = nev; ok && i < kk; ++i) ok = std::abs(mu[ord[nev - 1]]) < std::abs(mu[ord[i]]);
+            // distances to the target mu = shift (0: the origin)
+            auto dist = [&](int i) { return std::abs(mu[ord[i]] - o.shift); };
+            for (int i = 0; ok && i + 1 < nev; ++i) ok = dist(i) <= dist(i + 1);
+            for (int i = nev; ok && i < kk; ++i) ok = dist(nev - 1) < dist(i);
             held = ok ? 1 : 0;
         }
         if (!test || held == 1 || d == 1) {
             out.roots = std::move(p.roots);
             out.roots1.clear();
+            out.shift = p.shift;
             break;
         }
         if (power == o.damp && power < 2)

@@ -98,7 +98,9 @@ std::vector<cplx> leja_order(const std::vector<cplx>& theta) {
 }
 
 // ---------------------------------------------------------------- apply
-int apply_buffers(const Poly& p) { return p.is_double() ? 6 : 4; }
+// A shifted double polynomial may need one more buffer (the two-step last
+// pass below).
+int apply_buffers(const Poly& p) { return p.is_double() ? (p.shift != 0.0 ? 7 : 6) : 4; }
 
 void carve_apply(Carver& c, int64_t n, const Poly& p, VecT t, ApplyWs& ws) {
     const size_t es = t == VecT::F64 ? sizeof(double) : sizeof(float);
@@ -114,12 +116,19 @@ struct Chain {
     std::vector<void*> pool;
     size_t bytes = 0;
     bool dry = false;   // count bytes only
+    double sigma = 0.0; // the operator is A - sigma I
     void pass(double alpha, const void* x, double beta, const void* u, double gamma, const void* z,
               double delta, const void* z2, void* out, VecT out_t) {
         if (dry)
             bytes += fused_spmv_bytes(A, ct, out_t, x, u, z, z2);
         else
             bytes += launch_fused_spmv(A, ct, out_t, alpha, x, beta, u, gamma, z, delta, z2, out, s);
+    }
+    void axpy3(double a, const void* x, double b, const void* y, double c, const void* z, void* out,
+               VecT out_t) {
+        const size_t sin = ct == VecT::F64 ? 8 : 4, sout = out_t == VecT::F64 ? 8 : 4;
+        bytes += (size_t)A.n * (sin * (1 + (y != nullptr) + (z != nullptr)) + sout);
+        if (!dry) launch_axpy3(A.n, ct, out_t, a, x, b, y, c, z, out, s);
     }
 };
 
@@ -139,6 +148,11 @@ void pi_chain(Chain& ch, const std::vector<cplx>& roots, const void* u0, double 
         }
         fail(PPA_ERR_INVALID, "internal: apply buffer pool exhausted");
     };
+    // With a shift sigma the factors act on A - sigma I; sigma folds into the
+    // coefficients of the vector that is also the gathered one:
+    //   real:  w - (A - sigma) w / theta = (1 + sigma/theta) w - A w / theta
+    //   pair:  s = (2a + sigma) w - A w,  w - (A - sigma) s / q = w - A s / q + (sigma/q) s
+    const double sg = ch.sigma;
     size_t i = 0;
     while (i < nr) {
         const cplx t = roots[i];
@@ -146,25 +160,55 @@ void pi_chain(Chain& ch, const std::vector<cplx>& roots, const void* u0, double 
         const bool last = (i + (pair ? 2 : 1)) >= nr;
         if (!pair) {
             const double ib = -1.0 / t.real();
+            const double sx = 1.0 - sg * ib;
             if (last) {
-                ch.pass(c, cur, c * ib, cur, gamma, z, delta, z2, out, out_t);
+                ch.pass(c * sx, cur, c * ib, cur, gamma, z, delta, z2, out, out_t);
             } else {
                 void* nx = pick(cur, nullptr);
-                ch.pass(1.0, cur, ib, cur, 0.0, nullptr, 0.0, nullptr, nx, ch.ct);
+                ch.pass(sx, cur, ib, cur, 0.0, nullptr, 0.0, nullptr, nx, ch.ct);
                 cur = nx;
             }
             i += 1;
         } else {
             const double a = t.real();
             const double q = t.real() * t.real() + t.imag() * t.imag();
+            const double ss = sg / q;
             void* sb = pick(cur, nullptr);
-            ch.pass(2.0 * a, cur, -1.0, cur, 0.0, nullptr, 0.0, nullptr, sb, ch.ct);
-            if (last) {
+            ch.pass(2.0 * a + sg, cur, -1.0, cur, 0.0, nullptr, 0.0, nullptr, sb, ch.ct);
+            if (!last) {
+                void* nx = pick(cur, sb);
+                ch.pass(1.0, cur, -1.0 / q, sb, ss, ss != 0.0 ? sb : nullptr, 0.0, nullptr, nx, ch.ct);
+                cur = nx;
+            } else if (ss == 0.0) {
                 ch.pass(c, cur, -c / q, sb, gamma, z, delta, z2, out, out_t);
             } else {
-                void* nx = pick(cur, sb);
-                ch.pass(1.0, cur, -1.0 / q, sb, 0.0, nullptr, 0.0, nullptr, nx, ch.ct);
-                cur = nx;
+                // c w - (c/q) A s + (c sigma/q) s + gamma z + delta z2: merge terms on
+                // the same vector, then put the s term in a free slot
+                double al = c, g1 = gamma, g2 = delta;
+                const void* z1p = z;
+                const void* z2p = z2;
+                if (z1p == cur) { al += g1; z1p = nullptr; g1 = 0.0; }
+                if (z2p == cur) { al += g2; z2p = nullptr; g2 = 0.0; }
+                const double es = c * ss;
+                if (z1p == sb) {
+                    g1 += es;
+                } else if (z2p == sb) {
+                    g2 += es;
+                } else if (z1p == nullptr) {
+                    z1p = sb;
+                    g1 = es;
+                } else if (z2p == nullptr) {
+                    z2p = sb;
+                    g2 = es;
+                } else {
+                    // five distinct vectors: the factor first, then the epilogue
+                    void* tmp = pick(cur, sb);
+                    ch.pass(1.0, cur, -1.0 / q, sb, ss, sb, 0.0, nullptr, tmp, ch.ct);
+                    ch.axpy3(al, tmp, g1, z1p, g2, z2p, out, out_t);
+                    i += 2;
+                    continue;
+                }
+                ch.pass(al, cur, -c / q, sb, g1, z1p, g2, z2p, out, out_t);
             }
             i += 2;
         }
@@ -175,9 +219,10 @@ void pi_chain(Chain& ch, const std::vector<cplx>& roots, const void* u0, double 
 
 size_t apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
                              double* y, double c, double gamma, const double* z, ApplyWs& ws,
-                             hipStream_t s) {
+                             hipStream_t s, double sigma) {
     PPA_REQUIRE(!roots.empty(), "apply: empty polynomial");
     Chain ch{A, VecT::F64, s, {}};
+    ch.sigma = sigma;
     for (int i = 0; i < 4; ++i) ch.pool.push_back(ws.buf[i]);
     pi_chain(ch, roots, v, c, gamma, z, 0.0, nullptr, y, VecT::F64, {v, z});
     return ch.bytes;
@@ -242,6 +287,7 @@ size_t apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT 
                   VecT chain, ApplyWs& ws, hipStream_t s) {
     PPA_REQUIRE(p.degree() >= 1, "apply: empty polynomial");
     Chain ch{A, chain, s, {}};
+    ch.sigma = p.shift;
     const int nb = apply_buffers(p);
     for (int i = 0; i < nb; ++i) ch.pool.push_back(ws.buf[i]);
     const void* v0 = v;
@@ -263,11 +309,12 @@ size_t apply_poly_bytes(const Matrix& A, const Poly& p, VecT chain) {
     PPA_REQUIRE(p.degree() >= 1, "apply: empty polynomial");
     Chain ch{A, chain, nullptr, {}};
     ch.dry = true;
+    ch.sigma = p.shift;
     // stand-in addresses: only their identity matters for the count
-    static char tags[8];
+    static char tags[10];
     const int nb = apply_buffers(p);
     for (int i = 0; i < nb; ++i) ch.pool.push_back(&tags[i]);
-    run_apply(ch, p, &tags[6], chain, &tags[7]);
+    run_apply(ch, p, &tags[8], chain, &tags[9]);
     return ch.bytes;
 }
 

@@ -78,6 +78,7 @@ struct Matrix {
 struct Poly {
     std::vector<cplx> roots;    // pi (single) or pi_2 (double), application order
     std::vector<cplx> roots1;   // pi_1 (double polynomial), empty otherwise
+    double shift = 0.0;         // the polynomial acts on A - shift I
     bool is_double() const { return !roots1.empty(); }
     int degree() const { return (int)roots.size(); }
     int total_degree() const {
@@ -129,6 +130,9 @@ void matrix_setup(Matrix& A, hipStream_t s);   // validate, norm, partition
 // forces the windowed kernel whenever it fits, mode -1 keeps the plain one.
 void matrix_tune(Matrix& A, int mode, hipStream_t s);
 void matrix_release(Matrix& A);
+// out = a x + b y + c z (y, z may be null), element types as given
+void launch_axpy3(int64_t n, VecT in, VecT out_t, double a, const void* x, double b, const void* y,
+                  double c, const void* z, void* out, hipStream_t s);
 void launch_cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s);
 void launch_cast_f32_f64(const float* in, double* out, int64_t n, hipStream_t s);
 
@@ -197,7 +201,7 @@ std::vector<cplx> harmonic_ritz(int d, const std::vector<double>& Hbar /*(d+1) x
 std::vector<cplx> leja_order(const std::vector<cplx>& theta);
 // Apply pi(A) (or pi_2(tau(A))) to v: FP64 or FP32 chain.
 struct ApplyWs {
-    void* buf[6] = {};   // n-vectors of the chain's element type
+    void* buf[8] = {};   // n-vectors of the chain's element type (apply_buffers of them)
 };
 int apply_buffers(const Poly& p);
 void carve_apply(Carver& c, int64_t n, const Poly& p, VecT t, ApplyWs& ws);
@@ -219,7 +223,7 @@ size_t apply_poly(const Matrix& A, const Poly& p, VecT vin, const void* v, VecT 
 // tau(A) = I - pi_1(A) of section 8 is c = -1, gamma = 1, z = v).
 size_t apply_single_epilogue(const Matrix& A, const std::vector<cplx>& roots, const double* v,
                              double* y, double c, double gamma, const double* z, ApplyWs& ws,
-                             hipStream_t s);
+                             hipStream_t s, double sigma = 0.0);
 // ---------------------------------------------------------------- projected problem (ritz.cpp)
 // Ordering of Ritz values (section 4): increasing |target - nu|, ties larger
 // Im first, then smaller Re.  target = 1 for pi(A), 0 for A itself.
@@ -264,7 +268,7 @@ RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, doubl
 // polynomial construction and Arnoldi drivers (eigs.cpp)
 size_t poly_build_ws(int64_t n, int d, bool dbl);
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
-               hipStream_t s, Poly& out);
+               hipStream_t s, Poly& out, double sigma = 0.0);
 size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o);
 size_t poly_build_ex_ws(const Matrix& A, const ppa_poly_build_opts& o, bool two);
 int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b, const double* b2,

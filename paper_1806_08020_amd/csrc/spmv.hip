@@ -557,6 +557,38 @@ static unsigned stream_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
 }
 
+template <typename IT, typename OT>
+__global__ void k_axpy3(int64_t n, double a, const IT* __restrict__ x, double b,
+                        const IT* __restrict__ y, double c, const IT* __restrict__ z,
+                        OT* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v = a * (double)x[i];
+        if (y) v += b * (double)y[i];
+        if (z) v += c * (double)z[i];
+        out[i] = (OT)v;
+    }
+}
+
+void launch_axpy3(int64_t n, VecT in, VecT out_t, double a, const void* x, double b, const void* y,
+                  double c, const void* z, void* out, hipStream_t s) {
+    if (n <= 0) return;
+    const dim3 g(stream_grid(n)), bl(256);
+    if (in == VecT::F64 && out_t == VecT::F64)
+        hipLaunchKernelGGL((k_axpy3<double, double>), g, bl, 0, s, n, a, (const double*)x, b,
+                           (const double*)y, c, (const double*)z, (double*)out);
+    else if (in == VecT::F64)
+        hipLaunchKernelGGL((k_axpy3<double, float>), g, bl, 0, s, n, a, (const double*)x, b,
+                           (const double*)y, c, (const double*)z, (float*)out);
+    else if (out_t == VecT::F64)
+        hipLaunchKernelGGL((k_axpy3<float, double>), g, bl, 0, s, n, a, (const float*)x, b,
+                           (const float*)y, c, (const float*)z, (double*)out);
+    else
+        hipLaunchKernelGGL((k_axpy3<float, float>), g, bl, 0, s, n, a, (const float*)x, b,
+                           (const float*)y, c, (const float*)z, (float*)out);
+    PPA_HIP(hipGetLastError());
+}
+
 void launch_cast_f64_f32(const double* in, float* out, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_cast_f64_f32, dim3(stream_grid(n)), dim3(256), 0, s, in, out, n);

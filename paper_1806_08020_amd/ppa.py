@@ -47,7 +47,7 @@ class EigsResult(C.Structure):
 
 class PolyBuildOpts(C.Structure):
     _fields_ = [("d", C.c_int), ("damp", C.c_int), ("alpha", C.c_double), ("test_m", C.c_int),
-                ("test_k", C.c_int), ("test_nev", C.c_int)]
+                ("test_k", C.c_int), ("test_nev", C.c_int), ("shift", C.c_double)]
 
 
 class PolyBuildInfo(C.Structure):
@@ -78,6 +78,8 @@ def _load():
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
         "ppa_poly_roots": (i, [vp, i, P(d), P(d), i, P(i)]),
+        "ppa_poly_shift": (i, [vp, P(d)]),
+        "ppa_poly_set_shift": (i, [vp, d]),
         "ppa_poly_build_ex_workspace_bytes": (i, [vp, P(PolyBuildOpts), i, P(sz)]),
         "ppa_poly_build_ex": (i, [vp, P(PolyBuildOpts), vp, vp, vp, sz, vp, P(vp), P(PolyBuildInfo)]),
         "ppa_poly_log10_pof": (i, [vp, i, P(d), i, P(i)]),
@@ -236,12 +238,13 @@ class Poly:
 
     @classmethod
     def build_ex(cls, A: Matrix, d: int, b: torch.Tensor, b2: torch.Tensor | None = None,
-                 damp: int = 0, alpha: float = 0.0, test=None):
+                 damp: int = 0, alpha: float = 0.0, test=None, shift: float = 0.0):
         """GMRES polynomial with the safeguards of sections 5-6: damped start
         vector A^damp b (+ alpha b), optional second start vector b2, optional
-        Ideal-Order-Condition test ``test = (m, k, nev)``.  Returns (Poly, info)."""
+        Ideal-Order-Condition test ``test = (m, k, nev)``, target ``shift``
+        (the polynomial acts on A - shift I).  Returns (Poly, info)."""
         tm, tk, tn = test if test is not None else (0, 0, 0)
-        o = PolyBuildOpts(d, damp, alpha, tm, tk, tn)
+        o = PolyBuildOpts(d, damp, alpha, tm, tk, tn, shift)
         nb = C.c_size_t()
         _check(_lib.ppa_poly_build_ex_workspace_bytes(A.h, C.byref(o), int(b2 is not None), C.byref(nb)))
         ws = _workspace(nb.value)
@@ -251,6 +254,16 @@ class Poly:
                                            _stream(), C.byref(h), C.byref(info)))
         return cls(h, st), dict(degree=info.degree, damp=info.damp, attempts=info.attempts,
                                 held=info.held)
+
+    @property
+    def shift(self) -> float:
+        x = C.c_double()
+        _check(_lib.ppa_poly_shift(self.h, C.byref(x)))
+        return x.value
+
+    @shift.setter
+    def shift(self, mu: float):
+        _check(_lib.ppa_poly_set_shift(self.h, float(mu)))
 
     def log10_pof(self, level: int = 2) -> np.ndarray:
         """log10 pof(j) of the roots of ``level`` in application order."""
