@@ -41,7 +41,7 @@ __all__ = [
     "sort_ritz", "keep_count", "thick_restart", "BREAKDOWN_TOL",
     "pof", "log10_pof", "extra_root_counts", "add_stability_roots",
     "damped_start", "gmres_poly_two", "ideal_order_condition", "order_test_quotients",
-    "damping_heuristic",
+    "damping_heuristic", "harmonic_projection", "harmonic_restart",
 ]
 
 # Breakdown rule (reading): an Arnoldi/GMRES step breaks down when the norm
@@ -459,6 +459,54 @@ def thick_restart(V: np.ndarray, H: np.ndarray, G: np.ndarray, nu: np.ndarray, k
     return kk
 
 
+def harmonic_projection(Hm: np.ndarray, hm: float, target: float):
+    """Harmonic Ritz pairs of the projected operator with respect to the
+    target tau (the harmonic Arnoldi method the paper uses in section 4,
+    Example 2): f = (H_m - tau I)^{-T} e_m and the eigenpairs (theta, g) of
+    H_m + h_{m+1,m}^2 f e_m^T.  Returns (theta, G, f)."""
+    m = Hm.shape[0]
+    e = np.zeros(m)
+    e[-1] = 1.0
+    f = np.linalg.solve((Hm - target * np.eye(m)).T, e)
+    theta, G = np.linalg.eig(Hm + hm * hm * np.outer(f, e))
+    return theta, G, f
+
+
+def harmonic_restart(V: np.ndarray, H: np.ndarray, G: np.ndarray, theta: np.ndarray,
+                     f: np.ndarray, k: int, m: int) -> int:
+    """Thick restart keeping harmonic Ritz vectors, in place.  Every harmonic
+    Ritz pair (theta, y = V_m g) has residual op(y) - theta y parallel to
+    w = v_{m+1} - h_{m+1,m} V_m f, so span{y_1..y_kk, w} carries a
+    Krylov-like relation: with Q a real orthonormal basis of the kept g's
+    (k-1 when a pair would be split) and w_hat = [-h f; 1] orthonormalised
+    against [Q; 0], the new basis is V_{m+1} [[Q, *], [0, *]] (w_hat last)
+    and the new projected block is [Q; 0 | w_hat]^T H_bar_m Q, a full
+    (kk+1) x kk matrix.  Returns the number of kept vectors."""
+    kk = keep_count(theta, k)
+    cols = []
+    for i in range(kk):
+        if theta[i].imag == 0.0:
+            cols.append(G[:, i].real)
+        elif theta[i].imag > 0.0:
+            cols.append(G[:, i].real)
+            cols.append(G[:, i].imag)
+    Q, _ = np.linalg.qr(np.array(cols).T)
+    hm = H[m, m - 1]
+    Qh = np.vstack([Q, np.zeros((1, kk))])
+    w = np.concatenate([-hm * f.real, [1.0]])
+    for _ in range(2):
+        w = w - Qh @ (Qh.T @ w)
+    w = w / np.linalg.norm(w)
+    Qp = np.hstack([Qh, w[:, None]])
+    Hn = Qp.T @ H[: m + 1, :m] @ Q
+    Vn = V[:, : m + 1] @ Qp
+    V[:] = 0.0
+    H[:] = 0.0
+    V[:, : kk + 1] = Vn
+    H[: kk + 1, :kk] = Hn
+    return kk
+
+
 @dataclass
 class ArnoldiResult:
     mu: np.ndarray            # eigenvalue estimates of A (Rayleigh quotients), sorted by |mu|
@@ -497,7 +545,8 @@ def _ritz_test(Vm, g_cols, amatvec, cnt):
 def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
                           rtol_abs: float, max_cycles: int,
                           cnt: Counters | None = None, hook=None,
-                          target: float = 1.0, shift: float = 0.0) -> ArnoldiResult:
+                          target: float = 1.0, shift: float = 0.0,
+                          harmonic: bool = False) -> ArnoldiResult:
     """Thick-restarted Arnoldi(m,k) with exact shifts on the operator ``op``
     (pi(A) or pi_2(tau(A))), convergence tested on A (section 4).
 
@@ -508,6 +557,9 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
     conjugate pair would be split) as a real orthonormal basis Q of their
     Ritz vectors, V_k <- V_m Q, v_{k+1} <- v_{m+1},
     H_k <- Q^T H_m Q with row k+1 equal to h_{m+1,m} e_m^T Q, and continue.
+    ``harmonic``: the pairs are harmonic Ritz pairs with respect to the
+    target (harmonic_projection) and the restart keeps harmonic Ritz vectors
+    (harmonic_restart); the test is unchanged.
 
     ``hook(event, V, H, j)``, if given, sees copies of the basis and the
     projected matrix at the end of each cycle (event "cycle", j = basis
@@ -540,7 +592,10 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
         if hook is not None:
             hook("cycle", V.copy(), H.copy(), mcyc)
         Hm = H[:mcyc, :mcyc]
-        nu, G = np.linalg.eig(Hm)
+        if harmonic:
+            nu, G, fh = harmonic_projection(Hm, H[mcyc, mcyc - 1], target)
+        else:
+            nu, G = np.linalg.eig(Hm)
         order = sort_ritz(nu, target)
         nu, G = nu[order], G[:, order]
         nw = min(nev, mcyc)
@@ -551,7 +606,7 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
         if done or broke or cycle == max_cycles:
             conv = done
             break
-        kk = thick_restart(V, H, G, nu, k, m)
+        kk = harmonic_restart(V, H, G, nu, fh, k, m) if harmonic else thick_restart(V, H, G, nu, k, m)
         j0 = kk
         if hook is not None:
             hook("restart", V.copy(), H.copy(), kk)
@@ -565,7 +620,7 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
 def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
             d: int | None = None, d1: int | None = None, d2: int | None = None,
             rtol: float = 1e-8, max_cycles: int = 100, roots=None, hook=None,
-            shift: float = 0.0):
+            shift: float = 0.0, harmonic: bool = False):
     """Polynomial preconditioned Arnoldi end to end (section 2 listing;
     section 8 for ``d1, d2``).  rtol is relative: the absolute bound is
     rtol * ||A||_inf.  ``d=0`` runs standard Arnoldi on A.  ``roots`` may
@@ -574,6 +629,7 @@ def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
     the polynomial is built for and applied to A - mu I, the Rayleigh
     quotients and residuals are those of A (the residual is the same for
     both), and the eigenvalues are returned by their distance to mu.
+    ``harmonic`` restarts with harmonic Ritz vectors (thick_restart_arnoldi).
 
     Returns (ArnoldiResult, roots) where roots is a list or a (r1, r2) pair."""
     amv0 = csr_matvec(csr)
@@ -600,5 +656,5 @@ def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
         def op(x):
             return apply_poly(amv, rts, x, cnt)
     res = thick_restart_arnoldi(op, amv0, v0, m, k, nev, rtol * infnorm(csr), max_cycles, cnt, hook,
-                                target=0.0 if rts is None else 1.0, shift=shift)
+                                target=0.0 if rts is None else 1.0, shift=shift, harmonic=harmonic)
     return res, rts
