@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # by the hash of the kernel source the counters were taken on: any change of
 # the kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
-    ("c2", "923cb5853e06ca3e"): {"fetch_kib": 36911.28, "write_kib": 7812.85, "fetch_factor": 2.0,
+    ("c2", "161e43af15ba6d9c"): {"fetch_kib": 36918.59, "write_kib": 7812.87, "fetch_factor": 2.0,
                                  "write_factor": 1.0},
 }
 
@@ -185,6 +185,39 @@ def safeguards_report():
     return out
 
 
+def harmonic_report():
+    """Section 4, Example 2: Arnoldi(50,20) for the 15 smallest-magnitude
+    eigenvalues, rtol 1e-8, restarted with Ritz vectors and with harmonic
+    Ritz vectors, at several degrees.  Operators: a synthetic stand-in for
+    Example 2's matrix (n = 23560, about 20 nonzeros per row, complex
+    spectrum with outlying conjugate pairs on which the degree-5 minimum
+    residual polynomial exceeds 1 in modulus) and Example 1's two-region
+    convection-diffusion operator at n = 1e4."""
+    import torch
+    from paper_1806_08020_amd import ppa
+    from paper_1806_08020_amd import workloads as W
+
+    out = {}
+    for name, csr, degs in (("example2_standin_n23560", W.band_with_rotations(23560), (0, 5, 40)),
+                            ("example1_n10000", W.two_region_convdiff(100), (0, 10))):
+        A = ppa.Matrix(csr)
+        b, v0 = (torch.as_tensor(x, device="cuda") for x in W.start_vectors(csr.n, 10))
+        rows = {}
+        for d in degs:
+            P = ppa.Poly.build(A, d, b) if d else None
+            for harm in (False, True):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = ppa.eigs(A, P, v0, 50, 20, 15, rtol=1e-8, max_cycles=3000 if d == 0 else 600,
+                             harmonic=harm)
+                torch.cuda.synchronize()
+                rows[f"d{d}_{'harmonic' if harm else 'ritz'}"] = {
+                    "converged": bool(r.converged), "cycles": int(r.cycles), "mvps": int(r.mvps),
+                    "vops": int(r.vops), "ms": round((time.perf_counter() - t0) * 1e3, 2)}
+        out[name] = rows
+    return out
+
+
 def served_mix_report(count):
     """Served mix (2-D convection-diffusion solves of random size, degree and
     nev, seeded): capacity from a closed-loop run (all requests at t = 0),
@@ -237,6 +270,9 @@ def main():
                     help="skip the solve in the other precision (mixed vs FP64)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served mix")
     ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed solve: no comparison, served mix, stability, "
+                         "safeguard or harmonic blocks (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -330,7 +366,7 @@ def main():
                      "launches": passes},
     }
     line["eigenpairs_per_s_by_precision"] = {prec: round(nconv / wall, 4)}
-    if not args.no_compare:
+    if not (args.no_compare or args.headline_only):
         alt = "mixed" if prec == "f64" else "f64"
         if alt == "mixed" and not A.has_f32:
             A = ppa.Matrix(csr, want_f32=True)
@@ -359,9 +395,11 @@ def main():
             "note": "every returned pair of both runs meets rtol on A in FP64; on a strongly "
                     "non-normal operator the two runs may certify different pseudo-eigenvalues",
         }
-    line["stability"] = stability_report(P, dbl)
-    line["safeguards"] = safeguards_report()
-    if not args.no_serve:
+    if not args.headline_only:
+        line["stability"] = stability_report(P, dbl)
+        line["safeguards"] = safeguards_report()
+        line["harmonic"] = harmonic_report()
+    if not (args.no_serve or args.headline_only):
         line["served"] = served_mix_report(args.serve_requests)
     if not args.no_cpu_baseline:
         roots = (P.roots(1), P.roots(2)) if dbl else P.roots()

@@ -283,6 +283,13 @@ typedef struct ppa_eigs_opts {
 /* opts.flags: time the polynomial applications and the orthogonalisation with
  * HIP events recorded on `stream` (results in t_apply_ms / t_cgs_ms). */
 #define PPA_FLAG_TIMING 1
+/* Harmonic restart (the harmonic Arnoldi variant of section 4, Example 2):
+ * each cycle takes harmonic Ritz pairs of the operator with respect to its
+ * target (1 for pi(A), 0 without a polynomial), eig(H_m + h^2 f e_m^T) with
+ * (H_m - target I)^T f = e_m, tests them as usual, and restarts with the
+ * kept harmonic Ritz vectors plus v_{m+1} - h V_m f, whose direction all
+ * their residuals share. */
+#define PPA_FLAG_HARMONIC 2
 
 typedef struct ppa_eigs_result {
     /* host arrays of capacity nev, filled with the returned pairs sorted by

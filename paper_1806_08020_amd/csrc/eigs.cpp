@@ -293,6 +293,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     double spmv_bytes = 0.0;
     bool fp32 = o.precision == PPA_MIXED;
     const bool timing = (o.flags & PPA_FLAG_TIMING) != 0;
+    const bool harmonic = (o.flags & PPA_FLAG_HARMONIC) != 0;
     struct Events {
         std::vector<hipEvent_t> ev;
         ~Events() {
@@ -376,7 +377,8 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         std::vector<double> Hm((size_t)mc * mc);
         for (int jj = 0; jj < mc; ++jj)
             for (int i = 0; i < mc; ++i) Hm[i + (size_t)jj * mc] = H[i + (size_t)jj * (m + 1)];
-        RitzPlan R = plan_ritz(Hm, mc, nev, target);
+        RitzPlan R = plan_ritz(Hm, mc, nev, target, harmonic && mc == m,
+                               mc == m ? H[m + (size_t)(m - 1) * (m + 1)] : 0.0);
         const int nw = R.nw;
         PPA_HIP(hipMemcpyAsync(e.Qd, R.Gw.data(), R.Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
         launch_gemm_tall(n, mc, R.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);

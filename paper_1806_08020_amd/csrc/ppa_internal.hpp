@@ -236,8 +236,14 @@ struct RitzPlan {
     std::vector<int> dup;        // wanted i is the conjugate of wanted i-1 (same columns)
     int ycols = 0;
     std::vector<double> Gw;      // mc x ycols: Y = V_m Gw
+    bool harmonic = false;       // harmonic Ritz pairs (then fh, hm are set)
+    std::vector<double> fh;      // f = (H_m - target I)^{-T} e_m
+    double hm = 0.0;             // h_{m+1,m}
 };
-RitzPlan plan_ritz(const std::vector<double>& Hm, int mc, int nev, double target);
+// Ritz pairs of H_m, or with `harmonic` (and hm != 0) the harmonic Ritz pairs
+// with respect to `target`: eig(H_m + hm^2 f e_m^T), f = (H_m - target I)^{-T} e_m.
+RitzPlan plan_ritz(const std::vector<double>& Hm, int mc, int nev, double target,
+                   bool harmonic = false, double hm = 0.0);
 // Ritz-test dot products: kind 0 is y_a . (A y)_b, kind 1 is y_a . y_b.
 struct DotSpec {
     int a, b, kind;

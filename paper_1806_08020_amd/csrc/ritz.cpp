@@ -23,11 +23,29 @@ std::vector<int> sort_ritz(const std::vector<cplx>& nu, double target) {
     return idx;
 }
 
-RitzPlan plan_ritz(const std::vector<double>& Hm, int mc, int nev, double target) {
+RitzPlan plan_ritz(const std::vector<double>& Hm, int mc, int nev, double target, bool harmonic,
+                   double hm) {
     RitzPlan R;
     R.mc = mc;
     std::vector<cplx> nu0, G0;
-    dense_eig(mc, Hm.data(), nu0, &G0);
+    if (harmonic && hm != 0.0) {
+        // harmonic Ritz pairs: (H_m - tau I)^T f = e_m, eig(H_m + hm^2 f e_m^T)
+        std::vector<double> T((size_t)mc * mc);
+        for (int j = 0; j < mc; ++j)
+            for (int i = 0; i < mc; ++i)
+                T[i + (size_t)j * mc] = Hm[j + (size_t)i * mc] - (i == j ? target : 0.0);
+        std::vector<double> f(mc, 0.0);
+        f[mc - 1] = 1.0;
+        if (lu_solve(mc, T, f)) {
+            std::vector<double> M = Hm;
+            for (int i = 0; i < mc; ++i) M[i + (size_t)(mc - 1) * mc] += hm * hm * f[i];
+            dense_eig(mc, M.data(), nu0, &G0);
+            R.harmonic = true;
+            R.fh = f;
+            R.hm = hm;
+        }
+    }
+    if (!R.harmonic) dense_eig(mc, Hm.data(), nu0, &G0);
     const std::vector<int> ord = sort_ritz(nu0, target);
     R.nu.resize(mc);
     R.G.resize((size_t)mc * mc);
@@ -180,6 +198,36 @@ RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, doubl
             P.Hn[i + (size_t)jj * (m + 1)] = s;
         }
     for (int jj = 0; jj < kk; ++jj) P.Hn[kk + (size_t)jj * (m + 1)] = hm * P.Q[(mc - 1) + (size_t)jj * mc];
+    if (!R.harmonic || mc != m) return P;
+    // Harmonic restart: every kept harmonic Ritz pair's residual is parallel
+    // to v_{m+1} - hm V_m f, so the next basis vector is [-hm f; 1]
+    // orthonormalised against [Q; 0] (twice), and the new projected block is
+    // [Q; 0 | w]^T Hbar_m Q, a full (kk+1) x kk matrix.
+    std::vector<double> w(m + 1, 0.0);
+    for (int i = 0; i < m; ++i) w[i] = -hm * R.fh[i];
+    w[m] = 1.0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int jj = 0; jj < kk; ++jj) {
+            double c = 0.0;
+            for (int i = 0; i < m; ++i) c += P.Q[i + (size_t)jj * mc] * w[i];
+            for (int i = 0; i < m; ++i) w[i] -= c * P.Q[i + (size_t)jj * mc];
+        }
+    double nw = 0.0;
+    for (double x : w) nw += x * x;
+    nw = std::sqrt(nw);
+    for (int i = 0; i <= m; ++i) P.Qp[i + (size_t)kk * (m + 1)] = w[i] / nw;
+    // Hbar Q ((m+1) x kk) with Hbar = [H_m; hm e_m^T]
+    std::vector<double> HQ1((size_t)(m + 1) * kk, 0.0);
+    for (int jj = 0; jj < kk; ++jj) {
+        for (int i = 0; i < m; ++i) HQ1[i + (size_t)jj * (m + 1)] = HQ[i + (size_t)jj * mc];
+        HQ1[m + (size_t)jj * (m + 1)] = hm * P.Q[(m - 1) + (size_t)jj * mc];
+    }
+    for (int jj = 0; jj < kk; ++jj)
+        for (int i = 0; i <= kk; ++i) {
+            double acc = 0.0;
+            for (int r = 0; r <= m; ++r) acc += P.Qp[r + (size_t)i * (m + 1)] * HQ1[r + (size_t)jj * (m + 1)];
+            P.Hn[i + (size_t)jj * (m + 1)] = acc;
+        }
     return P;
 }
 

@@ -209,6 +209,31 @@ def random_banded(n: int, nnz_per_row: int = 27, band: int = 5000, seed: int = 4
     return CSR(n, rowptr.astype(np.int32), cols.reshape(-1).astype(np.int32), vals.reshape(-1))
 
 
+def band_with_rotations(n: int = 23560, nnz_per_row: int = 20, band: int = 200, seed: int = 2,
+                        shift: float = 0.5, pair_frac: float = 0.02, mag: float = 12.0) -> CSR:
+    """Nonsymmetric matrix with a complex spectrum and outlying conjugate
+    pairs: ``random_banded`` (diagonal uniform on [0, 10]) plus ``shift`` on
+    the diagonal, plus skew couplings +b, -b at (i, i+1), (i+1, i) for
+    ``pair_frac * n / 2`` disjoint even i, b uniform on [mag/2, mag].  Each
+    coupling moves a pair of eigenvalues far off the real axis, where a
+    low-degree minimum residual polynomial is not small."""
+    import scipy.sparse as sp
+    base = random_banded(n, nnz_per_row, band, seed)
+    S = base.to_scipy().tocoo()
+    rng = np.random.default_rng([seed, 2])
+    npairs = max(1, int(pair_frac * n / 2))
+    i = rng.choice(n // 2, npairs, replace=False) * 2
+    b = mag * rng.uniform(0.5, 1.0, npairs)
+    d = np.arange(n)
+    rows = np.concatenate([S.row, d, i, i + 1])
+    cols = np.concatenate([S.col, d, i + 1, i])
+    vals = np.concatenate([S.data, np.full(n, shift), b, -b])
+    M = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    return CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
 def diag_csr(d: np.ndarray) -> CSR:
     d = np.asarray(d, dtype=np.float64)
     n = d.size

@@ -53,3 +53,24 @@ def test_start_vectors_seeded():
     b, v0 = W.start_vectors(100, 3)
     b2, v02 = W.start_vectors(100, 3)
     assert np.array_equal(b, b2) and np.array_equal(v0, v02) and not np.array_equal(b, v0)
+
+
+def test_band_with_rotations_structure():
+    """Random band plus a diagonal shift plus skew couplings on disjoint
+    index pairs: A - base is shift*I + a block-diagonal skew part."""
+    n = 3000
+    A = W.band_with_rotations(n).to_scipy()
+    B = W.random_banded(n, 20, 200, seed=2).to_scipy()
+    D = (A - B).toarray()
+    assert np.allclose(np.diag(D), 0.5)
+    S = D - 0.5 * np.eye(n)
+    assert np.allclose(S, -S.T)
+    r, c = np.nonzero(np.abs(S) > 1e-9)
+    assert np.all(np.abs(r - c) == 1) and np.all(np.minimum(r, c) % 2 == 0)
+    assert r.size == 2 * int(0.02 * n / 2)
+    v = np.abs(S[r, c])
+    assert v.min() >= 6.0 and v.max() <= 12.0
+    C1, C2 = W.band_with_rotations(n), W.band_with_rotations(n)
+    assert np.array_equal(C1.colind, C2.colind) and np.array_equal(C1.vals, C2.vals)
+    for row in range(n):
+        assert np.all(np.diff(C1.colind[C1.rowptr[row]:C1.rowptr[row + 1]]) > 0)
