@@ -99,6 +99,26 @@ int ppa_matrix_info(const ppa_matrix* A, int64_t* n, int64_t* nnz, double* norm_
  * *windowed = 1 for the LDS-windowed kernel, 0 for the plain one. */
 int ppa_matrix_spmv_variant(const ppa_matrix* A, int precision, int* windowed);
 
+/* Cache policy of the plain (non-windowed) SpMV kernel, per value precision
+ * (PPA_F64 or PPA_F32).  It changes how the kernel's loads and stores treat
+ * the caches, never the arithmetic: every policy gives bitwise identical
+ * results.
+ *   PPA_CACHE_STREAM     non-temporal loads of column indices and values;
+ *   PPA_CACHE_KEEP       plain loads and stores, so that a matrix that fits in
+ *                        the 256 MB last-level cache stays there from one
+ *                        factor of pi to the next;
+ *   PPA_CACHE_KEEP_NTST  plain loads, non-temporal stores of the output.
+ * ppa_matrix_create picks KEEP when one pass moves at most 128 MB and STREAM
+ * otherwise, and on large matrices (n >= 200000, nnz >= 10^6) times the
+ * three and switches to another only when it is at least 3% faster.  The setter overrides that choice
+ * (PPA_ERR_INVALID for an unknown policy or precision, or PPA_F32 without
+ * FP32 values); it must not race with launches that use A. */
+#define PPA_CACHE_STREAM 0
+#define PPA_CACHE_KEEP 1
+#define PPA_CACHE_KEEP_NTST 2
+int ppa_matrix_cache_policy(const ppa_matrix* A, int precision, int* policy);
+int ppa_matrix_set_cache_policy(ppa_matrix* A, int precision, int policy);
+
 /* ------------------------------------------------------------------------
  * Polynomial pi in factored form, eq. (2.1): pi(z) = prod_i (1 - z/theta_i),
  * roots in modified Leja order with each complex root followed at once by its

@@ -123,6 +123,29 @@ int ppa_matrix_spmv_variant(const ppa_matrix* h, int precision, int* windowed) {
     });
 }
 
+int ppa_matrix_cache_policy(const ppa_matrix* h, int precision, int* policy) {
+    return guarded([&] {
+        PPA_REQUIRE(h && policy, "matrix and policy are required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        const Matrix* A = reinterpret_cast<const Matrix*>(h);
+        *policy = precision == PPA_F64 ? A->cp64 : A->cp32;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_set_cache_policy(ppa_matrix* h, int precision, int policy) {
+    return guarded([&] {
+        PPA_REQUIRE(h, "matrix is required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        PPA_REQUIRE(policy == PPA_CACHE_STREAM || policy == PPA_CACHE_KEEP || policy == PPA_CACHE_KEEP_NTST,
+                    "unknown cache policy %d", policy);
+        Matrix* A = reinterpret_cast<Matrix*>(h);
+        PPA_REQUIRE(precision == PPA_F64 || A->v32, "the matrix has no FP32 values");
+        (precision == PPA_F64 ? A->cp64 : A->cp32) = policy;
+        return PPA_OK;
+    });
+}
+
 static std::vector<cplx> read_roots(int deg, const double* re, const double* im) {
     PPA_REQUIRE(deg >= 1 && re, "polynomial needs deg >= 1 roots");
     std::vector<cplx> r(deg);

@@ -59,6 +59,9 @@ struct Window {
     size_t lds_bytes = 0;
 };
 
+// Cache policies of the plain SpMV kernel (values match ppa.h's PPA_CACHE_*).
+enum { CP_STREAM = 0, CP_KEEP = 1, CP_KEEP_NTST = 2 };
+
 struct Matrix {
     int64_t n = 0, nnz = 0;
     const int32_t* rowptr = nullptr;
@@ -69,6 +72,7 @@ struct Matrix {
     int4* bm = nullptr;              // device, per block {r0, r1, p0, p1}
     int64_t nblocks = 0;
     int align = 1;                   // block ranges start at multiples of this (1 or 4)
+    int cp64 = CP_KEEP, cp32 = CP_KEEP;   // cache policy of the plain SpMV kernel per value type
     double norm_inf = 0.0;
     int device = 0;
     Window win64, win32;

@@ -9,7 +9,9 @@
 // Layout and mapping (gfx950):
 //  * rows are cut into row blocks of at most SPMV_CHUNK nonzeros; a block of
 //    SPMV_BS threads first loads its contiguous nonzero range (colind, values)
-//    with unit-stride, non-temporal loads, multiplies by the gathered u and
+//    with unit-stride loads (non-temporal for matrices far larger than the
+//    last-level cache, cached otherwise: a per-matrix policy that the setup
+//    times on large matrices), multiplies by the gathered u and
 //    stages the products in LDS, then each thread sums whole rows from LDS and
 //    applies the axpy epilogue -- every global access but the gather of u is
 //    coalesced.  The row pointers and streamed vectors of a thread's first
@@ -30,6 +32,7 @@
 #include "ppa_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 // Nonzeros per lane in one load of the main kernel: FP64 values one at a
@@ -42,6 +45,27 @@
 #endif
 
 namespace ppa {
+
+// Cache policy of the main kernel (chosen per matrix and value precision):
+//   CP_STREAM     non-temporal loads of the matrix stream, plain stores: for
+//                 matrices much larger than the last-level cache;
+//   CP_KEEP       plain loads and stores: the matrix and vectors stay in the
+//                 256 MB last-level cache from one factor to the next;
+//   CP_KEEP_NTST  plain loads, non-temporal stores of the output.
+template <int CP, typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+    if constexpr (CP == CP_STREAM)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <int CP, typename T>
+__device__ __forceinline__ void out_store(T* p, T v) {
+    if constexpr (CP == CP_KEEP_NTST)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb / NUM_XCD, r = nb % NUM_XCD;
@@ -87,12 +111,12 @@ __device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr
     return q;
 }
 
-template <typename VT, typename OT>
+template <int CP, typename VT, typename OT>
 __device__ __forceinline__ void row_out(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
                                         VT alpha, VT beta, VT gamma, VT delta) {
     VT s = 0;
     for (int k = q.a - p0; k < q.e - p0; ++k) s += prod[k];
-    out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
+    out_store<CP>(out + r, (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2));
 }
 
 // One row longer than the block's nonzero budget: r1 == r0 + 1, reduced
@@ -137,41 +161,36 @@ template <int G, typename T>
 struct Grp {
     T v[G];
 };
-template <int G, typename T>
+template <int G, int CP, typename T>
 __device__ __forceinline__ Grp<G, T> load_grp(const T* __restrict__ p, int idx, bool full,
                                               int lastidx) {
     Grp<G, T> r;
     if constexpr (G == 1) {
-        r.v[0] = __builtin_nontemporal_load(p + min(idx, lastidx));
+        r.v[0] = stream_load<CP>(p + min(idx, lastidx));
+    } else if constexpr (G == 4 && sizeof(T) == 8) {
+        // FP64 values of a group of four: two 16-byte loads
+        typedef T d2 __attribute__((ext_vector_type(2)));
+        if (full) {
+            const d2 a = stream_load<CP>(reinterpret_cast<const d2*>(p + idx));
+            const d2 b = stream_load<CP>(reinterpret_cast<const d2*>(p + idx) + 1);
+            r.v[0] = a.x;
+            r.v[1] = a.y;
+            r.v[2] = b.x;
+            r.v[3] = b.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r.v[j] = p[min(idx + j, lastidx)];
+        }
     } else {
         typedef T vec_t __attribute__((ext_vector_type(G)));
         if (full) {
-            const vec_t a = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(p + idx));
+            const vec_t a = stream_load<CP>(reinterpret_cast<const vec_t*>(p + idx));
 #pragma unroll
             for (int j = 0; j < G; ++j) r.v[j] = a[j];
         } else {
 #pragma unroll
             for (int j = 0; j < G; ++j) r.v[j] = p[min(idx + j, lastidx)];
         }
-    }
-    return r;
-}
-// FP64 values of a group of four: two 16-byte loads.
-template <>
-__device__ __forceinline__ Grp<4, double> load_grp<4, double>(const double* __restrict__ p, int idx,
-                                                              bool full, int lastidx) {
-    typedef double d2 __attribute__((ext_vector_type(2)));
-    Grp<4, double> r;
-    if (full) {
-        const d2 a = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p + idx));
-        const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p + idx) + 1);
-        r.v[0] = a.x;
-        r.v[1] = a.y;
-        r.v[2] = b.x;
-        r.v[3] = b.y;
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) r.v[j] = p[min(idx + j, lastidx)];
     }
     return r;
 }
@@ -184,7 +203,7 @@ __device__ __forceinline__ Grp<4, double> load_grp<4, double>(const double* __re
 // products land in LDS at their aligned position and each thread sums whole
 // rows from an offset view.  Every load of the block is issued before the
 // first gathered value is used.
-template <typename VT, typename IT, typename OT, int G, bool EPI>
+template <typename VT, typename IT, typename OT, int G, bool EPI, int CP>
 __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const VT* __restrict__ val, const int4* __restrict__ bm, int nblk, int nnz,
@@ -217,8 +236,8 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int j = min(p0 + tid + k * SPMV_BS, last);
-                c[k] = __builtin_nontemporal_load(colind + j);
-                v[k] = __builtin_nontemporal_load(val + j);
+                c[k] = stream_load<CP>(colind + j);
+                v[k] = stream_load<CP>(val + j);
             }
         }
         // the thread's first two rows (clamped into the block; masked at use)
@@ -243,8 +262,8 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
             for (int k = 0; k < NG; ++k) {
                 const int idx = base + G * min(tid + k * SPMV_BS, gmax);
                 const bool full = idx + G <= nnz;
-                c[k] = load_grp<G>(colind, idx, full, nnz - 1);
-                v[k] = load_grp<G>(val, idx, full, nnz - 1);
+                c[k] = load_grp<G, CP>(colind, idx, full, nnz - 1);
+                v[k] = load_grp<G, CP>(val, idx, full, nnz - 1);
             }
         }
         qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
@@ -268,11 +287,11 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     }
     __syncthreads();
     const VT* prod = prod_ext + (p0 - base);
-    if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
-    if (rb < r1) row_out(qb, prod, p0, rb, out, alpha, beta, gamma, delta);
+    if (ra < r1) row_out<CP>(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
+    if (rb < r1) row_out<CP>(qb, prod, p0, rb, out, alpha, beta, gamma, delta);
     for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
         const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
-        row_out(q, prod, p0, r, out, alpha, beta, gamma, delta);
+        row_out<CP>(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
 }
 
@@ -313,8 +332,8 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
         for (int k = 0; k < NG; ++k) {
             const int idx = base + G * min(tid + k * SPMV_WBS, gmax);
             const bool full = idx + G <= nnz;
-            c[k] = load_grp<G>(colind, idx, full, nnz - 1);
-            v[k] = load_grp<G>(val, idx, full, nnz - 1);
+            c[k] = load_grp<G, CP_STREAM>(colind, idx, full, nnz - 1);
+            v[k] = load_grp<G, CP_STREAM>(val, idx, full, nnz - 1);
         }
     }
     // window copy: 16-byte vectors of u from wb = cmin rounded down
@@ -364,10 +383,10 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     }
     __syncthreads();
     const VT* prod = prod_ext + (p0 - base);
-    if (ra < r1) row_out(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
+    if (ra < r1) row_out<CP_STREAM>(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
     for (int r = ra + SPMV_WBS; r < r1; r += SPMV_WBS) {
         const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
-        row_out(q, prod, p0, r, out, alpha, beta, gamma, delta);
+        row_out<CP_STREAM>(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
 }
 
@@ -411,10 +430,22 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
                                (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha,
                                (VT)beta, (VT)gamma, (VT)delta);
         };
-        if (grp)
-            epi ? go(k_fused_spmv<VT, IT, OT, G, true>) : go(k_fused_spmv<VT, IT, OT, G, false>);
+        auto pick = [&](auto cp) {
+            constexpr int P = decltype(cp)::value;
+            if (grp)
+                epi ? go(k_fused_spmv<VT, IT, OT, G, true, P>)
+                    : go(k_fused_spmv<VT, IT, OT, G, false, P>);
+            else
+                epi ? go(k_fused_spmv<VT, IT, OT, 1, true, P>)
+                    : go(k_fused_spmv<VT, IT, OT, 1, false, P>);
+        };
+        const int cp = sizeof(VT) == 8 ? A.cp64 : A.cp32;
+        if (cp == CP_KEEP)
+            pick(std::integral_constant<int, CP_KEEP>());
+        else if (cp == CP_KEEP_NTST)
+            pick(std::integral_constant<int, CP_KEEP_NTST>());
         else
-            epi ? go(k_fused_spmv<VT, IT, OT, 1, true>) : go(k_fused_spmv<VT, IT, OT, 1, false>);
+            pick(std::integral_constant<int, CP_STREAM>());
     }
     PPA_HIP(hipGetLastError());
 }
@@ -757,6 +788,15 @@ void matrix_setup(Matrix& A, hipStream_t s) {
     PPA_HIP(hipMalloc(&A.bm, rec.size() * sizeof(int32_t)));
     PPA_HIP(hipMemcpyAsync(A.bm, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     PPA_HIP(hipStreamSynchronize(s));
+    // untimed default cache policy: cached loads when one pass (matrix,
+    // row pointers, two vectors in and one out) fits well inside the 256 MB
+    // last-level cache, streaming loads otherwise; matrix_tune times the
+    // policies on large matrices
+    const double keep = 128.0 * (1 << 20);
+    const double ws64 = 12.0 * A.nnz + 4.0 * (n + 1) + 24.0 * n;
+    const double ws32 = 8.0 * A.nnz + 4.0 * (n + 1) + 12.0 * n;
+    A.cp64 = ws64 <= keep ? CP_KEEP : CP_STREAM;
+    A.cp32 = ws32 <= keep ? CP_KEEP : CP_STREAM;
 }
 
 // Average time of `reps` passes u -> y with the current kernel choice.
@@ -779,17 +819,23 @@ static float time_passes(const Matrix& A, bool f32, void* u, void* y, int reps, 
 }
 
 void matrix_tune(Matrix& A, int mode, hipStream_t s) {
-    // Only large matrices are timed: the windowed kernel pays off when gathers
-    // miss the cache, and the timing costs a few passes.
-    if (mode < 0 || A.nnz == 0) return;
-    if (mode == 0 && (A.n < 200000 || A.nnz < 1000000)) return;
-    build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
-    if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
-    if (!A.win64.bm && !A.win32.bm) return;
-    if (mode == 1) {
-        A.win64.on = A.win64.bm != nullptr;
-        A.win32.on = A.win32.bm != nullptr;
+    // Only large matrices are timed (a few passes each): the cache policy of
+    // the plain kernel, then, where the column ranges allow it, the windowed
+    // kernel against the plain one.  Short timings alternate the candidates
+    // over three trials after a warm-up and compare the best trials: a single
+    // timing favours whichever variant runs second on warm caches.
+    if (A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
+        if (mode == 1 && A.nnz > 0) {
+            build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
+            if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
+            A.win64.on = A.win64.bm != nullptr;
+            A.win32.on = A.win32.bm != nullptr;
+        }
         return;
+    }
+    if (mode >= 0) {
+        build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
+        if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
     }
     double* u = nullptr;
     double* y = nullptr;
@@ -801,14 +847,27 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
     PPA_HIP(hipGetLastError());
     for (int pass = 0; pass < 2; ++pass) {
         const bool f32 = pass == 1;
+        if (f32 && !A.v32) continue;
         Window& W = f32 ? A.win32 : A.win64;
-        if (!W.bm) continue;
+        int& cp = f32 ? A.cp32 : A.cp64;
         void* uu = u;
         if (f32) launch_cast_f64_f32(u, (float*)y, A.n, s), uu = y;   // FP32 copy of the ramp
         void* yy = f32 ? (void*)((float*)y + ((A.n + 63) & ~int64_t(63))) : (void*)y;
-        // alternate the two kernels over three trials after a warm-up of
-        // each, and compare the best trials: a single short timing favours
-        // whichever variant runs second on warm caches
+        const bool won = W.on;
+        W.on = false;
+        const int cp0 = cp;
+        float tcp[3] = {1e30f, 1e30f, 1e30f};
+        for (int trial = 0; trial < 4; ++trial)
+            for (int c = 0; c < 3; ++c) {
+                cp = c;
+                const float t = time_passes(A, f32, uu, yy, 8, s);
+                if (trial > 0) tcp[c] = std::min(tcp[c], t);
+            }
+        // the size rule's choice stays unless another policy is clearly faster
+        const int c_best = (int)(std::min_element(tcp, tcp + 3) - tcp);
+        cp = tcp[c_best] < 0.97f * tcp[cp0] ? c_best : cp0;
+        W.on = won;
+        if (mode != 0 || !W.bm) continue;
         float t_plain = 1e30f, t_win = 1e30f;
         bool win_ok = true;
         for (int trial = 0; trial < 4 && win_ok; ++trial) {
@@ -828,6 +887,10 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
             t_win = std::min(t_win, tw);
         }
         W.on = win_ok && t_win < 0.95f * t_plain;
+    }
+    if (mode == 1) {
+        A.win64.on = A.win64.bm != nullptr;
+        A.win32.on = A.win32.bm != nullptr;
     }
     PPA_HIP(hipStreamSynchronize(s));
     PPA_HIP(hipFree(u));

@@ -74,6 +74,8 @@ def _load():
         "ppa_matrix_destroy": (i, [vp]),
         "ppa_matrix_info": (i, [vp, P(i64), P(i64), P(d), P(i64)]),
         "ppa_matrix_spmv_variant": (i, [vp, i, P(i)]),
+        "ppa_matrix_cache_policy": (i, [vp, i, P(i)]),
+        "ppa_matrix_set_cache_policy": (i, [vp, i, i]),
         "ppa_poly_from_roots": (i, [i, P(d), P(d), i, P(d), P(d), P(vp)]),
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
@@ -183,6 +185,18 @@ class Matrix:
         w = C.c_int()
         _check(_lib.ppa_matrix_spmv_variant(self.h, _PREC[precision], C.byref(w)))
         return bool(w.value)
+
+    CACHE_POLICIES = ("stream", "keep", "keep_ntst")
+
+    def cache_policy(self, precision: str = "f64") -> str:
+        """Cache policy of the plain SpMV kernel: "stream", "keep" or "keep_ntst"."""
+        c = C.c_int()
+        _check(_lib.ppa_matrix_cache_policy(self.h, _PREC[precision], C.byref(c)))
+        return self.CACHE_POLICIES[c.value]
+
+    def set_cache_policy(self, policy: str, precision: str = "f64") -> None:
+        _check(_lib.ppa_matrix_set_cache_policy(self.h, _PREC[precision],
+                                                self.CACHE_POLICIES.index(policy)))
 
     def __del__(self):
         h = getattr(self, "h", None)

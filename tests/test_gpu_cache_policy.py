@@ -1,0 +1,82 @@
+"""Cache policies of the plain fused SpMV kernel (non-temporal or cached
+matrix loads, plain or non-temporal output stores): they change how the
+kernel uses the caches, never its arithmetic, so every policy's output is
+bitwise the same, in FP64 and FP32, with and without the epilogue vectors,
+including the mixed FP32-values / FP64-vector forms."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_08020_amd import workloads as W
+
+from .test_gpu_parity import EPS64, dev, host
+
+pytestmark = pytest.mark.gpu
+
+POL = ("stream", "keep", "keep_ntst")
+
+
+@pytest.mark.parametrize("name", ["convdiff", "band", "long_rows"])
+def test_policies_bitwise_equal(lib, name):
+    if name == "convdiff":
+        csr = W.convdiff_2d(300, 0.5)
+    elif name == "band":
+        csr = W.random_banded(50_000, 27, 700, seed=4)
+    else:
+        rng = np.random.default_rng(0)
+        n = 6000
+        A = np.zeros((n, n))
+        A[np.arange(n), np.arange(n)] = 3.0
+        A[7, :] = rng.standard_normal(n)        # a row longer than one block
+        A[4000, ::2] = 1.0
+        csr = W.dense_csr(A)
+    A = lib.Matrix(csr, want_f32=True, window="off")
+    rng = np.random.default_rng(5)
+    u, x, z, z2 = (rng.standard_normal(csr.n) for _ in range(4))
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        outs = []
+        for p in POL:
+            A.set_cache_policy(p, prec)
+            assert A.cache_policy(prec) == p
+            outs.append((lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt)),
+                         lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt), 1.5, dev(z, dt), -0.25,
+                                        dev(z2, dt)),
+                         lib.fused_spmv(A, 1.0, dev(u, dt), -0.5, dev(u, dt),
+                                        out_dtype=torch.float64 if prec == "f32" else None)))
+        for o in outs[1:]:
+            for a, b in zip(outs[0], o):
+                assert torch.equal(a, b)
+    S = csr.to_scipy()
+    ref = 0.5 * x - 2.0 * (S @ u) + 1.5 * z - 0.25 * z2
+    nnzr = max(1, int(np.diff(csr.rowptr).max()))
+    scale = 0.5 * np.abs(x) + 2 * (abs(S) @ np.abs(u)) + 1.5 * np.abs(z) + 0.25 * np.abs(z2)
+    A.set_cache_policy("keep", "f64")
+    y = host(lib.fused_spmv(A, 0.5, dev(x), -2.0, dev(u), 1.5, dev(z), -0.25, dev(z2)))
+    assert np.all(np.abs(y - ref) <= (nnzr + 5) * EPS64 * scale)
+
+
+def test_default_policy_and_errors(lib):
+    """A matrix whose pass moves well under 128 MB keeps its stream cached by
+    default; unknown policies and FP32 without FP32 values are rejected."""
+    csr = W.laplacian_2d(50)
+    A = lib.Matrix(csr)
+    assert A.cache_policy("f64") == "keep"
+    with pytest.raises(RuntimeError):
+        A.set_cache_policy("keep", "f32")
+    with pytest.raises(ValueError):
+        A.set_cache_policy("bogus", "f64")
+
+
+def test_tuned_policy_full_size_bitwise(lib):
+    """Convection-diffusion 1000x1000 (the benchmark's matrix): the policy the
+    setup timing chose gives the same bits as the streaming policy."""
+    csr = W.convdiff_2d(1000, 0.5)
+    A = lib.Matrix(csr)
+    chosen = A.cache_policy("f64")
+    assert chosen in POL
+    rng = np.random.default_rng(8)
+    u, x = dev(rng.standard_normal(csr.n)), dev(rng.standard_normal(csr.n))
+    y1 = lib.fused_spmv(A, 1.0, x, -0.5, u)
+    A.set_cache_policy("stream", "f64")
+    y0 = lib.fused_spmv(A, 1.0, x, -0.5, u)
+    assert torch.equal(y0, y1)
