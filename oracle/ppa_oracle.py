@@ -41,7 +41,7 @@ __all__ = [
     "sort_ritz", "keep_count", "thick_restart", "BREAKDOWN_TOL",
     "pof", "log10_pof", "extra_root_counts", "add_stability_roots",
     "damped_start", "gmres_poly_two", "ideal_order_condition", "order_test_quotients",
-    "damping_heuristic", "harmonic_projection", "harmonic_restart",
+    "damping_heuristic", "harmonic_projection", "harmonic_restart", "arnoldi_extend_dcgs2",
 ]
 
 # Breakdown rule (reading): an Arnoldi/GMRES step breaks down when the norm
@@ -100,6 +100,75 @@ def cgs2(V: np.ndarray, w: np.ndarray, cnt: Counters | None = None):
         cnt.dots += 2 * j + 1
         cnt.vops += 4 * j + 2          # 2j dots, 2j axpys, 1 norm, 1 scaling
     return h + h2, w, beta
+
+
+def arnoldi_extend_dcgs2(op, V: np.ndarray, H: np.ndarray, j0: int, m: int,
+                         cnt: Counters | None = None):
+    """Arnoldi steps j0..m-1 with Gram-Schmidt and one reorthogonalisation
+    pass, the reorthogonalisation delayed by one step so that each step needs
+    one block of inner products (a low-synchronisation form of the paper's
+    Gram-Schmidt with reorthogonalisation; the paper names communication-
+    avoiding variants as future work in section 9).
+
+    V[:, :j0+1] must be orthonormal and H[:j0+1, :j0] hold the projected
+    matrix so far.  Step j0 is a plain first pass:
+        z = op(q_j0), h = Q^T z, u = z - Q h  (u: once-orthogonalised).
+    Step j (j0 < j <= m), with Q = V[:, :j] and u the candidate for q_j:
+        a = Q^T u                      (the delayed second pass of z_{j-1})
+        beta = sqrt(u^T u - a^T a),    q_j = (u - Q a) / beta
+        H[:j, j-1] += a,  H[j, j-1] = beta
+    and, while j < m, the next first pass without applying op to q_j:
+        w = op(u),  b = Q^T w
+        op(q_j) = (w - op(Q) a) / beta = (w - V[:, :j+1] c) / beta,  c = H[:j+1, :j] a
+        h = V[:, :j+1]^T op(q_j):  h[:j] = (b - c[:j]) / beta,
+                                   h[j]  = ((u^T w - a^T b) / beta - c[j]) / beta
+        u_next = op(q_j) - V[:, :j+1] h = w / beta - gamma u - Q g,
+            gamma = (c[j] / beta + h[j]) / beta,  g = c[:j] / beta + h[:j] - gamma a.
+    Breakdown at step j when beta <= BREAKDOWN_TOL * ||z_{j-1}|| with
+    ||z_{j-1}||^2 = ||h_{j-1}||^2 + u^T u (as in ``cgs2`` callers).
+
+    Returns (mc, broke): the basis size reached and whether it broke down."""
+    w = op(V[:, j0])
+    Q = V[:, : j0 + 1]
+    h = Q.T @ w
+    H[: j0 + 1, j0] = h
+    u = w - Q @ h
+    hsq = float(h @ h)
+    if cnt is not None:
+        cnt.dots += j0 + 1
+        cnt.vops += j0 + 1
+    for j in range(j0 + 1, m + 1):
+        Q = V[:, :j]
+        a = Q.T @ u
+        uu = float(u @ u)
+        beta = float(np.sqrt(max(uu - float(a @ a), 0.0)))
+        H[:j, j - 1] += a
+        if beta <= BREAKDOWN_TOL * np.sqrt(hsq + uu):
+            H[j, j - 1] = 0.0
+            return j, True
+        H[j, j - 1] = beta
+        V[:, j] = (u - Q @ a) / beta
+        if cnt is not None:
+            cnt.dots += j + 1
+            cnt.vops += j + 1
+        if j == m:
+            break
+        w = op(u)
+        b = Q.T @ w
+        uw = float(u @ w)
+        c = H[: j + 1, :j] @ a
+        htop = (b - c[:j]) / beta
+        hj = ((uw - float(a @ b)) / beta - c[j]) / beta
+        H[:j, j] = htop
+        H[j, j] = hj
+        gamma = (c[j] / beta + hj) / beta
+        g = c[:j] / beta + htop - gamma * a
+        u = w / beta - gamma * u - Q @ g
+        hsq = float(htop @ htop) + hj * hj
+        if cnt is not None:
+            cnt.dots += j + 1
+            cnt.vops += j + 2
+    return m, False
 
 
 # --------------------------------------------------------------------------
@@ -546,7 +615,7 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
                           rtol_abs: float, max_cycles: int,
                           cnt: Counters | None = None, hook=None,
                           target: float = 1.0, shift: float = 0.0,
-                          harmonic: bool = False) -> ArnoldiResult:
+                          harmonic: bool = False, ortho: str = "cgs2") -> ArnoldiResult:
     """Thick-restarted Arnoldi(m,k) with exact shifts on the operator ``op``
     (pi(A) or pi_2(tau(A))), convergence tested on A (section 4).
 
@@ -560,6 +629,9 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
     ``harmonic``: the pairs are harmonic Ritz pairs with respect to the
     target (harmonic_projection) and the restart keeps harmonic Ritz vectors
     (harmonic_restart); the test is unchanged.
+    ``ortho``: "cgs2" (Gram-Schmidt with one reorthogonalisation pass, as in
+    the paper) or "dcgs2" (the same with the reorthogonalisation delayed by
+    one step, ``arnoldi_extend_dcgs2``).
 
     ``hook(event, V, H, j)``, if given, sees copies of the basis and the
     projected matrix at the end of each cycle (event "cycle", j = basis
@@ -577,7 +649,9 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
     for cycle in range(1, max_cycles + 1):
         mcyc = m
         broke = False
-        for j in range(j0, m):
+        if ortho == "dcgs2":
+            mcyc, broke = arnoldi_extend_dcgs2(op, V, H, j0, m, cnt)
+        for j in range(j0, m if ortho != "dcgs2" else j0):
             w = op(V[:, j])
             w0 = float(np.linalg.norm(w))
             h, w, beta = cgs2(V[:, : j + 1], w, cnt)
@@ -620,7 +694,7 @@ def thick_restart_arnoldi(op, amatvec, v0: np.ndarray, m: int, k: int, nev: int,
 def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
             d: int | None = None, d1: int | None = None, d2: int | None = None,
             rtol: float = 1e-8, max_cycles: int = 100, roots=None, hook=None,
-            shift: float = 0.0, harmonic: bool = False):
+            shift: float = 0.0, harmonic: bool = False, ortho: str = "cgs2"):
     """Polynomial preconditioned Arnoldi end to end (section 2 listing;
     section 8 for ``d1, d2``).  rtol is relative: the absolute bound is
     rtol * ||A||_inf.  ``d=0`` runs standard Arnoldi on A.  ``roots`` may
@@ -629,7 +703,8 @@ def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
     the polynomial is built for and applied to A - mu I, the Rayleigh
     quotients and residuals are those of A (the residual is the same for
     both), and the eigenvalues are returned by their distance to mu.
-    ``harmonic`` restarts with harmonic Ritz vectors (thick_restart_arnoldi).
+    ``harmonic`` restarts with harmonic Ritz vectors and ``ortho`` selects the
+    Gram-Schmidt form (thick_restart_arnoldi).
 
     Returns (ArnoldiResult, roots) where roots is a list or a (r1, r2) pair."""
     amv0 = csr_matvec(csr)
@@ -656,5 +731,6 @@ def pp_eigs(csr, b: np.ndarray, v0: np.ndarray, m: int, k: int, nev: int,
         def op(x):
             return apply_poly(amv, rts, x, cnt)
     res = thick_restart_arnoldi(op, amv0, v0, m, k, nev, rtol * infnorm(csr), max_cycles, cnt, hook,
-                                target=0.0 if rts is None else 1.0, shift=shift, harmonic=harmonic)
+                                target=0.0 if rts is None else 1.0, shift=shift, harmonic=harmonic,
+                                ortho=ortho)
     return res, rts
