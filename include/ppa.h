@@ -197,6 +197,8 @@ typedef struct {
     double shift;   /* target mu (section 2 footnote): the polynomial is built for
                        and applied to A - mu I; the order test and ppa_eigs then
                        rank eigenvalues by their distance to mu (0: the origin) */
+    int flags;      /* PPA_FLAG_LOWSYNC: the delayed-reorthogonalisation Gram-
+                       Schmidt in the GMRES cycle and the order test; 0 otherwise */
 } ppa_poly_build_opts;
 
 typedef struct {
@@ -310,6 +312,15 @@ typedef struct ppa_eigs_opts {
  * kept harmonic Ritz vectors plus v_{m+1} - h V_m f, whose direction all
  * their residuals share. */
 #define PPA_FLAG_HARMONIC 2
+/* Low-synchronisation Gram-Schmidt: the reorthogonalisation pass of step j-1
+ * is delayed and merged with the projection of step j, so each Arnoldi step
+ * makes two passes over the basis (one block of inner products, one update)
+ * instead of three.  The operator acts on the once-orthogonalised candidate;
+ * op(q_j)'s projection follows from op(Q) a = V_{j+1} Hbar a.  Same Arnoldi
+ * decomposition as the default in exact arithmetic (a form of section 4's
+ * Gram-Schmidt with reorthogonalisation; section 9 names communication-
+ * avoiding variants as future work). */
+#define PPA_FLAG_LOWSYNC 4
 
 typedef struct ppa_eigs_result {
     /* host arrays of capacity nev, filled with the returned pairs sorted by

@@ -257,6 +257,240 @@ __global__ void k_scale(const double* __restrict__ in, double* __restrict__ out,
         out[i] = in[i] * s;
 }
 
+// ---------------------------------------------------------------- delayed form
+// partial columns (stride nb): [0, jq) Q^T u, [jq, 2 jq) Q^T w, then u.u,
+// u.w, w.w over the block's rows; a null u or w counts as zero.
+__global__ __launch_bounds__(BS) void k_dproj(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                              int jq, const double* __restrict__ u,
+                                              const double* __restrict__ w,
+                                              double* __restrict__ partial, int nb) {
+    constexpr int CH = CT / 2;   // columns per tile (two products each)
+    __shared__ double red[NW * CT];
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + threadIdx.x;
+    double ur[RPT], wr[RPT];
+    int64_t rr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t r = base + (int64_t)i * BS;
+        rr[i] = r < n ? r : n - 1;
+        ur[i] = (u && r < n) ? u[rr[i]] : 0.0;
+        wr[i] = (w && r < n) ? w[rr[i]] : 0.0;
+    }
+    {
+        double sc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            sc[0] += ur[i] * ur[i];
+            sc[1] += ur[i] * wr[i];
+            sc[2] += wr[i] * wr[i];
+        }
+        block_reduce_store<3>(sc, 3, red, partial + (int64_t)(2 * jq) * nb + blockIdx.x, nb);
+        __syncthreads();
+    }
+    for (int c0 = 0; c0 < jq; c0 += CH) {
+        double acc[2 * CH];
+#pragma unroll
+        for (int c = 0; c < 2 * CH; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, jq - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const double v = col[rr[i]];
+                acc[c] += v * ur[i];
+                acc[CH + c] += v * wr[i];
+            }
+        }
+        const int cnt = min(CH, jq - c0);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < 2 * CH; ++c) {
+            if ((c % CH) < cnt) {
+                const double v = wave_sum(acc[c]);
+                if (lane == 0) red[wv * CT + c] = v;
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < 2 * CH; c += BS) {
+            if ((c % CH) >= cnt) continue;
+            double t = 0.0;
+            for (int q = 0; q < NW; ++q) t += red[q * CT + c];
+            const int col = c < CH ? c0 + c : jq + c0 + (c - CH);
+            partial[(int64_t)col * nb + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Coefficients of one delayed step from the reduced inner products dred
+// (layout of k_dproj) and the device Hessenberg matrix; one block.
+// coef: a [0, JMAX), g [JMAX, 2 JMAX), then 1/beta, the scale of w, gamma.
+__global__ __launch_bounds__(BS) void k_dcoef(int kind, int jq, const double* __restrict__ dred,
+                                              double* __restrict__ Hd, int64_t ldh,
+                                              double* __restrict__ coef, double* __restrict__ scal,
+                                              double tol) {
+    __shared__ double sa[CGS_JMAX_ALL], sc[CGS_JMAX_ALL + 1];
+    __shared__ double rsum[NW * 2];
+    __shared__ double s_inv, s_beta;
+    double* g = coef + CGS_JMAX_ALL;
+    double* sv = coef + 2 * CGS_JMAX_ALL;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (kind == DCGS_FIRST) {
+        // h = Q^T z: provisional column jq - 1; u_out = z - Q h
+        double hs = 0.0;
+        for (int i = tid; i < jq; i += BS) {
+            const double h = dred[jq + i];
+            Hd[i + (int64_t)(jq - 1) * ldh] = h;
+            g[i] = h;
+            coef[i] = 0.0;
+            hs += h * h;
+        }
+        hs = wave_sum(hs);
+        if (lane == 0) rsum[wv] = hs;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int q = 0; q < NW; ++q) t += rsum[q];
+            scal[0] = t;
+            sv[0] = 0.0;
+            sv[1] = 1.0;
+            sv[2] = 0.0;
+        }
+        return;
+    }
+    // a = Q^T u finishes column jq - 1
+    double aa = 0.0, ab = 0.0;
+    for (int i = tid; i < jq; i += BS) {
+        const double a = dred[i];
+        sa[i] = a;
+        coef[i] = a;
+        aa += a * a;
+        ab += a * dred[jq + i];
+    }
+    aa = wave_sum(aa);
+    ab = wave_sum(ab);
+    if (lane == 0) {
+        rsum[wv] = aa;
+        rsum[NW + wv] = ab;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double ta = 0.0;
+        for (int q = 0; q < NW; ++q) ta += rsum[q];
+        const double uu = dred[2 * jq];
+        const double beta = sqrt(fmax(uu - ta, 0.0));
+        const double zn = sqrt(scal[0] + uu);
+        s_beta = beta;
+        s_inv = (beta > tol * zn && beta > 0.0) ? 1.0 / beta : 0.0;
+        Hd[jq + (int64_t)(jq - 1) * ldh] = beta;
+    }
+    for (int i = tid; i < jq; i += BS) Hd[i + (int64_t)(jq - 1) * ldh] += sa[i];
+    __syncthreads();
+    const double inv = s_inv;
+    if (kind == DCGS_LAST) {
+        if (tid == 0) {
+            sv[0] = inv;
+            sv[1] = 0.0;
+            sv[2] = 0.0;
+        }
+        return;
+    }
+    // c = Hbar_jq a ((jq + 1) entries, columns 0..jq-1 final)
+    for (int i = tid; i <= jq; i += BS) {
+        double t = 0.0;
+        for (int l = 0; l < jq; ++l) t += Hd[i + (int64_t)l * ldh] * sa[l];
+        sc[i] = t;
+    }
+    __syncthreads();
+    double tab = 0.0;
+    if (tid == 0) {
+        for (int q = 0; q < NW; ++q) tab += rsum[NW + q];
+    }
+    // h of op(q_jq): provisional column jq
+    double hs = 0.0;
+    for (int i = tid; i < jq; i += BS) {
+        const double h = (dred[jq + i] - sc[i]) * inv;
+        Hd[i + (int64_t)jq * ldh] = h;
+        g[i] = h;   // completed below
+        hs += h * h;
+    }
+    hs = wave_sum(hs);
+    __syncthreads();
+    if (lane == 0) rsum[wv] = hs;
+    __syncthreads();
+    if (tid == 0) {
+        const double uw = dred[2 * jq + 1];
+        const double hj = ((uw - tab) * inv - sc[jq]) * inv;
+        Hd[jq + (int64_t)jq * ldh] = hj;
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += rsum[q];
+        scal[0] = t + hj * hj;
+        const double gamma = (sc[jq] * inv + hj) * inv;
+        sv[0] = inv;
+        sv[1] = inv;
+        sv[2] = gamma;
+        s_beta = gamma;   // reused to broadcast gamma
+    }
+    __syncthreads();
+    const double gamma = s_beta;
+    for (int i = tid; i < jq; i += BS) g[i] = sc[i] * inv + g[i] - gamma * sa[i];
+}
+
+// q_out = (u - Q a) / beta  and  u_out = s_w w - gamma u - Q g  in one pass
+// over Q (either output may be null; a null u or w counts as zero).
+__global__ __launch_bounds__(BS) void k_dupdate(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                                int jq, const double* __restrict__ coef,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ w,
+                                                double* __restrict__ q_out,
+                                                double* __restrict__ u_out) {
+    __shared__ double as[CGS_JMAX_ALL + 8], gs[CGS_JMAX_ALL + 8];
+    for (int c = threadIdx.x; c < CGS_JMAX_ALL + 8; c += BS) {
+        as[c] = c < jq ? coef[c] : 0.0;
+        gs[c] = c < jq ? coef[CGS_JMAX_ALL + c] : 0.0;
+    }
+    const double inv = coef[2 * CGS_JMAX_ALL], sw = coef[2 * CGS_JMAX_ALL + 1],
+                 gamma = coef[2 * CGS_JMAX_ALL + 2];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + threadIdx.x;
+    double qa[RPT], ug[RPT], uv[RPT], wv[RPT];
+    int64_t rr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t r = base + (int64_t)i * BS;
+        rr[i] = r < n ? r : n - 1;
+        uv[i] = u ? u[rr[i]] : 0.0;
+        wv[i] = w ? w[rr[i]] : 0.0;
+        qa[i] = 0.0;
+        ug[i] = 0.0;
+    }
+    for (int c0 = 0; c0 < jq; c0 += 8) {
+        double v[8][RPT];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, jq - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) v[c][i] = col[rr[i]];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double ac = as[c0 + c], gc = gs[c0 + c];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                qa[i] += v[c][i] * ac;
+                ug[i] += v[c][i] * gc;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        if (base + (int64_t)i * BS < n) {
+            if (q_out) q_out[rr[i]] = (uv[i] - qa[i]) * inv;
+            if (u_out) u_out[rr[i]] = sw * wv[i] - gamma * uv[i] - ug[i];
+        }
+    }
+}
+
 }  // namespace
 
 int cgs_blocks(int64_t n) {
@@ -276,8 +510,10 @@ static int cgs_blocks_fused(int64_t n) {
 void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws) {
     ws.nb = cgs_blocks(n);
     ws.nbf = cgs_blocks_fused(n);
-    ws.partial = c.take<double>(std::max<size_t>((size_t)(CGS_JMAX_ALL + 2) * ws.nb,
+    ws.partial = c.take<double>(std::max<size_t>((size_t)(2 * CGS_JMAX_ALL + 4) * ws.nb,
                                                  (size_t)CGS_JFUSED * ws.nbf));
+    ws.dred = c.take<double>(2 * CGS_JMAX_ALL + 4);
+    ws.coef = c.take<double>(2 * CGS_JMAX_ALL + 8);
     ws.h1 = c.take<double>(CGS_JMAX_ALL);
     ws.h2 = c.take<double>(CGS_JMAX_ALL);
     ws.scal = c.take<double>(4);
@@ -348,6 +584,25 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
         hipLaunchKernelGGL(k_scale, dim3(sgrid(n)), dim3(256), 0, s, w_out, v_next, n, ws.scal + 2);
         PPA_HIP(hipGetLastError());
     }
+}
+
+void launch_dcgs_step(int kind, int64_t n, int jq, const double* V, int64_t ldv, const double* u,
+                      const double* w, double* Hd, int64_t ldh, double* q_out, double* u_out,
+                      double breakdown_tol, Cgs2Ws& ws, hipStream_t s) {
+    PPA_REQUIRE(jq >= 1 && jq <= CGS_JMAX_ALL - 1, "delayed Gram-Schmidt: basis size %d out of range", jq);
+    PPA_REQUIRE((kind == DCGS_FIRST && w && !u) || (kind == DCGS_LAGGED && u && w) ||
+                    (kind == DCGS_LAST && u && !w),
+                "delayed Gram-Schmidt: operands do not match the step kind");
+    const int nb = ws.nb;
+    hipLaunchKernelGGL(k_dproj, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, u, w, ws.partial, nb);
+    PPA_HIP(hipGetLastError());
+    reduce_cols(ws.partial, nb, 2 * jq + 3, ws.dred, s);
+    hipLaunchKernelGGL(k_dcoef, dim3(1), dim3(BS), 0, s, kind, jq, ws.dred, Hd, ldh, ws.coef, ws.scal,
+                       breakdown_tol);
+    PPA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dupdate, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, ws.coef, u, w,
+                       kind == DCGS_FIRST ? nullptr : q_out, kind == DCGS_LAST ? nullptr : u_out);
+    PPA_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- MFMA GEMM

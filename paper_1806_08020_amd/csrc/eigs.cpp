@@ -62,6 +62,58 @@ double set_unit(int64_t n, const double* v, double* dst, double* partial, int nb
     return nn;
 }
 
+// Arnoldi steps j0..m-1 on `op` (op(x, y): y = op x, length N) extending the
+// orthonormal basis V (ld) and the Hessenberg matrix Hd (ld ldh, device).
+// Default: classical Gram-Schmidt with one reorthogonalisation pass per
+// step.  lowsync: the reorthogonalisation delayed by one step (op acts on the
+// once-orthogonalised candidate, kept in ub0 / ub1).  mark(j, phase) is
+// called before op (0), after op (1) and after the orthogonalisation (2).
+// Breakdown is read from H afterwards.
+template <class Op, class Mark>
+void arnoldi_steps(int64_t N, int j0, int m, bool lowsync, double* V, int64_t ld, double* w,
+                   double* Hd, int64_t ldh, double* ub0, double* ub1, Cgs2Ws& cw, hipStream_t s,
+                   Op&& op, Mark&& mark, int64_t& dots, int64_t& vops) {
+    if (!lowsync) {
+        for (int j = j0; j < m; ++j) {
+            mark(j, 0);
+            op(V + (size_t)j * ld, w);
+            mark(j, 1);
+            double* vn = V + (size_t)(j + 1) * ld;
+            launch_cgs2(N, j + 1, V, ld, w, vn, Hd + (size_t)j * ldh, vn, kBreakdownTol, cw, s);
+            mark(j, 2);
+            dots += 2 * (j + 1) + 1;
+            vops += 4 * (j + 1) + 2;
+        }
+        return;
+    }
+    double* ub[2] = {ub0, ub1};
+    int cur = 0;
+    for (int j = j0; j < m; ++j) {
+        mark(j, 0);
+        op(j == j0 ? V + (size_t)j * ld : ub[cur], w);
+        mark(j, 1);
+        if (j == j0) {
+            launch_dcgs_step(DCGS_FIRST, N, j + 1, V, ld, nullptr, w, Hd, ldh, nullptr, ub[cur],
+                             kBreakdownTol, cw, s);
+            dots += j + 1;
+            vops += j + 1;
+        } else {
+            launch_dcgs_step(DCGS_LAGGED, N, j, V, ld, ub[cur], w, Hd, ldh, V + (size_t)j * ld,
+                             ub[1 - cur], kBreakdownTol, cw, s);
+            cur = 1 - cur;
+            dots += 2 * (j + 1);
+            vops += 2 * j + 3;
+        }
+        if (j == m - 1) {
+            launch_dcgs_step(DCGS_LAST, N, m, V, ld, ub[cur], nullptr, Hd, ldh, V + (size_t)m * ld,
+                             nullptr, kBreakdownTol, cw, s);
+            dots += m + 1;
+            vops += m + 1;
+        }
+        mark(j, 2);
+    }
+}
+
 // ---------------------------------------------------------------- GMRES
 struct GmresWs {
     double* V = nullptr;
@@ -72,12 +124,16 @@ struct GmresWs {
     ApplyWs aw;
     double* dpart = nullptr;
     double* dout = nullptr;
+    double* ub0 = nullptr;   // candidates of the delayed Gram-Schmidt
+    double* ub1 = nullptr;
 };
 
 void carve_gmres(Carver& c, int64_t n, int d, bool tau, GmresWs& g) {
     g.ld = col_ld(n);
     g.V = c.take<double>((size_t)g.ld * (d + 1));
     g.w = c.take<double>((size_t)n);
+    g.ub0 = c.take<double>((size_t)n);
+    g.ub1 = c.take<double>((size_t)n);
     g.H = c.take<double>((size_t)(d + 1) * d);
     carve_cgs2(c, n, g.cw);
     if (tau) {
@@ -105,7 +161,7 @@ void apply_tau(const Matrix& A, const std::vector<cplx>& roots1, const double* x
 // Returns the effective degree; Hbar receives (d_eff+1) x d_eff.
 int gmres_cycle(const Matrix& A, const std::vector<cplx>& roots1, int d, const double* b,
                 const double* b2, double sigma, GmresWs& g, hipStream_t s,
-                std::vector<double>& Hbar) {
+                std::vector<double>& Hbar, bool lowsync = false) {
     const int64_t n = A.n;
     const int64_t N = b2 ? 2 * n : n;
     launch_zero(g.H, (int64_t)(d + 1) * d, s);
@@ -124,26 +180,25 @@ int gmres_cycle(const Matrix& A, const std::vector<cplx>& roots1, int d, const d
     } else {
         set_unit(n, b, g.V, g.dpart, g.cw.nb, g.dout, s);
     }
-    for (int j = 0; j < d; ++j) {
-        const double* vj = g.V + (size_t)j * g.ld;
-        // (A - sigma I) v: the shift is the coefficient of the gathered vector
-        // itself in the fused epilogue
-        const bool sh = sigma != 0.0;
+    // (A - sigma I) v: the shift is the coefficient of the gathered vector
+    // itself in the fused epilogue
+    const bool sh = sigma != 0.0;
+    auto op = [&](const double* vj, double* y) {
         if (b2) {
             launch_fused_spmv(A, VecT::F64, VecT::F64, -sigma, sh ? vj : nullptr, 1.0, vj, 0.0,
-                              nullptr, 0.0, nullptr, g.w, s);
+                              nullptr, 0.0, nullptr, y, s);
             launch_fused_spmv(A, VecT::F64, VecT::F64, -sigma, sh ? vj + n : nullptr, 1.0, vj + n,
-                              0.0, nullptr, 0.0, nullptr, g.w + n, s);
+                              0.0, nullptr, 0.0, nullptr, y + n, s);
         } else if (roots1.empty()) {
             launch_fused_spmv(A, VecT::F64, VecT::F64, -sigma, sh ? vj : nullptr, 1.0, vj, 0.0,
-                              nullptr, 0.0, nullptr, g.w, s);
+                              nullptr, 0.0, nullptr, y, s);
         } else {
-            apply_tau(A, roots1, vj, g.w, g.aw, s, sigma);
+            apply_tau(A, roots1, vj, y, g.aw, s, sigma);
         }
-        double* vn = g.V + (size_t)(j + 1) * g.ld;
-        launch_cgs2(N, j + 1, g.V, g.ld, g.w, vn, g.H + (size_t)j * (d + 1), vn, kBreakdownTol,
-                    g.cw, s);
-    }
+    };
+    int64_t dots = 0, vops = 0;
+    arnoldi_steps(N, 0, d, lowsync, g.V, g.ld, g.w, g.H, d + 1, g.ub0, g.ub1, g.cw, s, op,
+                  [](int, int) {}, dots, vops);
     std::vector<double> H((size_t)(d + 1) * d);
     PPA_HIP(hipMemcpyAsync(H.data(), g.H, H.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     PPA_HIP(hipStreamSynchronize(s));
@@ -178,7 +233,7 @@ size_t poly_build_ws(int64_t n, int d, bool dbl) {
 }
 
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
-               hipStream_t s, Poly& out, double sigma) {
+               hipStream_t s, Poly& out, double sigma, bool lowsync) {
     const bool dbl = d2 > 0;
     const int dmax = std::max(d1, d2);
     PPA_REQUIRE(d1 >= 1 && dmax <= CGS_JMAX_ALL - 2, "polynomial degree out of range");
@@ -189,7 +244,7 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
     int status = PPA_OK;
     std::vector<double> Hb;
     out.shift = sigma;
-    int de = gmres_cycle(A, {}, d1, b, nullptr, sigma, g, s, Hb);
+    int de = gmres_cycle(A, {}, d1, b, nullptr, sigma, g, s, Hb, lowsync);
     if (de < d1) status = PPA_WARN_DEGREE_REDUCED;
     std::vector<cplx> r1 = leja_order(harmonic_ritz(de, Hb));
     if (!dbl) {
@@ -197,7 +252,7 @@ int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_
         out.roots1.clear();
         return status;
     }
-    de = gmres_cycle(A, r1, d2, b, nullptr, sigma, g, s, Hb);
+    de = gmres_cycle(A, r1, d2, b, nullptr, sigma, g, s, Hb, lowsync);
     if (de < d2) status = PPA_WARN_DEGREE_REDUCED;
     out.roots1 = r1;
     out.roots = leja_order(harmonic_ritz(de, Hb));
@@ -294,6 +349,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     bool fp32 = o.precision == PPA_MIXED;
     const bool timing = (o.flags & PPA_FLAG_TIMING) != 0;
     const bool harmonic = (o.flags & PPA_FLAG_HARMONIC) != 0;
+    const bool lowsync = (o.flags & PPA_FLAG_LOWSYNC) != 0;
     struct Events {
         std::vector<hipEvent_t> ev;
         ~Events() {
@@ -339,17 +395,14 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     int cycle = 0;
     for (cycle = 1; cycle <= o.max_cycles; ++cycle) {
         if (fp32) ++fp32_cycles;
-        for (int j = j0; j < m; ++j) {
-            if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j], s));
-            apply_op(e.V + (size_t)j * e.ld, e.w);
-            if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + 1], s));
-            double* vn = e.V + (size_t)(j + 1) * e.ld;
-            launch_cgs2(n, j + 1, e.V, e.ld, e.w, vn, e.Hd + (size_t)j * (m + 1), vn,
-                        kBreakdownTol, e.cw, s);
-            if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + 2], s));
-            dots += 2 * (j + 1) + 1;
-            vops += 4 * (j + 1) + 2;
-        }
+        // the delayed form keeps its candidates in two columns of V2, which is
+        // free until the restart
+        arnoldi_steps(n, j0, m, lowsync, e.V, e.ld, e.w, e.Hd, m + 1, e.V2, e.V2 + e.ld, e.cw, s,
+                      apply_op,
+                      [&](int j, int phase) {
+                          if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + phase], s));
+                      },
+                      dots, vops);
         PPA_HIP(hipMemcpyAsync(H.data(), e.Hd, H.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         PPA_HIP(hipStreamSynchronize(s));
         if (timing) {
@@ -563,7 +616,7 @@ ppa_eigs_opts test_opts(const ppa_poly_build_opts& o) {
     t.rtol = 0.0;
     t.anorm = 0.0;
     t.precision = PPA_F64;
-    t.flags = 0;
+    t.flags = o.flags & PPA_FLAG_LOWSYNC;
     return t;
 }
 
@@ -631,7 +684,8 @@ int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b
         damp_start(A, b, power, o.alpha, w.s1, w.tmp, s);
         if (b2) damp_start(A, b2, power, o.alpha, w.s2, w.tmp, s);
         std::vector<double> Hb;
-        const int de = gmres_cycle(A, {}, d, w.s1, b2 ? w.s2 : nullptr, o.shift, w.g, s, Hb);
+        const int de = gmres_cycle(A, {}, d, w.s1, b2 ? w.s2 : nullptr, o.shift, w.g, s, Hb,
+                                   (o.flags & PPA_FLAG_LOWSYNC) != 0);
         status = de < d ? PPA_WARN_DEGREE_REDUCED : PPA_OK;
         Poly p;
         p.roots = leja_order(harmonic_ritz(de, Hb));

@@ -147,6 +147,8 @@ struct Cgs2Ws {
     double* h2 = nullptr;        // JMAX_ALL
     double* scal = nullptr;      // [0] = ||w_in||^2, [1] = ||w_out||^2, [2] = 1/beta
     double* t = nullptr;         // n
+    double* dred = nullptr;      // delayed form: reduced inner products (2 JMAX_ALL + 3)
+    double* coef = nullptr;      // delayed form: a, g (JMAX_ALL each) and 4 scalars
     int nb = 0;                  // blocks of the streaming kernels
     int nbf = 0;                 // blocks of the fused update-projection kernel
 };
@@ -161,6 +163,20 @@ void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws);
 void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* w_out,
                  double* Hcol_d, double* v_next, double breakdown_tol, Cgs2Ws& ws,
                  hipStream_t s);
+
+// Arnoldi with delayed reorthogonalisation (one block of inner products per
+// step).  Step kinds, with Q = V[:, 0:jq] and H column-major (ld ldh):
+//   DCGS_FIRST   z = w (= op(q_{jq-1})): h = Q^T z -> H[:, jq-1] (provisional),
+//                u_out = z - Q h;
+//   DCGS_LAGGED  u = candidate for q_jq, w = op(u): a = Q^T u finishes
+//                H[:, jq-1] and q_jq -> q_out; op(q_jq)'s first pass gives
+//                H[:, jq] (provisional) and the next candidate u_out;
+//   DCGS_LAST    u = candidate for q_jq (no w): finishes H[:, jq-1] and q_jq.
+// ws.scal[0] carries ||h||^2 of the provisional column between steps.
+enum { DCGS_FIRST = 0, DCGS_LAGGED = 1, DCGS_LAST = 2 };
+void launch_dcgs_step(int kind, int64_t n, int jq, const double* V, int64_t ldv, const double* u,
+                      const double* w, double* Hd, int64_t ldh, double* q_out, double* u_out,
+                      double breakdown_tol, Cgs2Ws& ws, hipStream_t s);
 
 // C = V Q  (V n x kin, Q device kin x kout col-major ld kin) -- MFMA FP64
 void launch_gemm_tall(int64_t n, int kin, int kout, const double* V, int64_t ldv,
@@ -278,7 +294,7 @@ RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, doubl
 // polynomial construction and Arnoldi drivers (eigs.cpp)
 size_t poly_build_ws(int64_t n, int d, bool dbl);
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
-               hipStream_t s, Poly& out, double sigma = 0.0);
+               hipStream_t s, Poly& out, double sigma = 0.0, bool lowsync = false);
 size_t eigs_ws(const Matrix& A, const Poly* p, const ppa_eigs_opts& o);
 size_t poly_build_ex_ws(const Matrix& A, const ppa_poly_build_opts& o, bool two);
 int poly_build_ex(const Matrix& A, const ppa_poly_build_opts& o, const double* b, const double* b2,

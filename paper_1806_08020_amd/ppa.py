@@ -47,7 +47,7 @@ class EigsResult(C.Structure):
 
 class PolyBuildOpts(C.Structure):
     _fields_ = [("d", C.c_int), ("damp", C.c_int), ("alpha", C.c_double), ("test_m", C.c_int),
-                ("test_k", C.c_int), ("test_nev", C.c_int), ("shift", C.c_double)]
+                ("test_k", C.c_int), ("test_nev", C.c_int), ("shift", C.c_double), ("flags", C.c_int)]
 
 
 class PolyBuildInfo(C.Structure):
@@ -232,7 +232,11 @@ class Poly:
         return cls(h)
 
     @classmethod
-    def build(cls, A: Matrix, d: int, b: torch.Tensor):
+    def build(cls, A: Matrix, d: int, b: torch.Tensor, lowsync: bool = False):
+        """GMRES(d) polynomial from b (``lowsync``: the GMRES cycle uses the
+        delayed-reorthogonalisation Gram-Schmidt)."""
+        if lowsync:
+            return cls.build_ex(A, d, b, lowsync=True)[0]
         nb = C.c_size_t()
         _check(_lib.ppa_poly_build_workspace_bytes(A.h, d, 0, C.byref(nb)))
         ws = _workspace(nb.value)
@@ -252,13 +256,14 @@ class Poly:
 
     @classmethod
     def build_ex(cls, A: Matrix, d: int, b: torch.Tensor, b2: torch.Tensor | None = None,
-                 damp: int = 0, alpha: float = 0.0, test=None, shift: float = 0.0):
+                 damp: int = 0, alpha: float = 0.0, test=None, shift: float = 0.0,
+                 lowsync: bool = False):
         """GMRES polynomial with the safeguards of sections 5-6: damped start
         vector A^damp b (+ alpha b), optional second start vector b2, optional
         Ideal-Order-Condition test ``test = (m, k, nev)``, target ``shift``
         (the polynomial acts on A - shift I).  Returns (Poly, info)."""
         tm, tk, tn = test if test is not None else (0, 0, 0)
-        o = PolyBuildOpts(d, damp, alpha, tm, tk, tn, shift)
+        o = PolyBuildOpts(d, damp, alpha, tm, tk, tn, shift, 4 if lowsync else 0)
         nb = C.c_size_t()
         _check(_lib.ppa_poly_build_ex_workspace_bytes(A.h, C.byref(o), int(b2 is not None), C.byref(nb)))
         ws = _workspace(nb.value)
@@ -416,11 +421,12 @@ def eigs_workspace(A: Matrix, p: Poly | None, m, k, nev, precision="f64"):
 def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, rtol: float = 1e-8,
          max_cycles: int = 100, precision: str = "f64", anorm: float = 0.0,
          want_vectors: bool = False, ws=None, timing: bool = False,
-         harmonic: bool = False) -> EigsOut:
+         harmonic: bool = False, lowsync: bool = False) -> EigsOut:
     """Thick-restarted Arnoldi(m,k) on pi(A) for nev eigenpairs of A
-    (``harmonic``: restart with harmonic Ritz vectors)."""
+    (``harmonic``: restart with harmonic Ritz vectors; ``lowsync``: Gram-Schmidt
+    with the reorthogonalisation delayed by one step)."""
     o = EigsOpts(m, k, nev, max_cycles, rtol, anorm, _PREC[precision],
-                 (1 if timing else 0) | (2 if harmonic else 0))
+                 (1 if timing else 0) | (2 if harmonic else 0) | (4 if lowsync else 0))
     if ws is None:
         nb = C.c_size_t()
         _check(_lib.ppa_eigs_workspace_bytes(A.h, p.h if p else None, C.byref(o), C.byref(nb)))
