@@ -46,9 +46,15 @@ constexpr int NUM_XCD = 8;
 // Windowed SpMV (matrices whose row blocks touch a narrow column range, e.g.
 // band matrices with scattered columns): a block stages u[cmin .. cmax] of its
 // rows in LDS and gathers from there.
-constexpr int SPMV_WBS = 512;              // threads per windowed block
-constexpr int SPMV_WCHUNK_F32 = 8192;      // nonzeros per windowed block, FP32 values
-constexpr int SPMV_WCHUNK_F64 = 4096;      // nonzeros per windowed block, FP64 values
+#ifndef PPA_SPMV_WBS
+#define PPA_SPMV_WBS 1024
+#endif
+#ifndef PPA_SPMV_WCHUNK_F32
+#define PPA_SPMV_WCHUNK_F32 8192
+#endif
+constexpr int SPMV_WBS = PPA_SPMV_WBS;                // threads per windowed block
+constexpr int SPMV_WCHUNK_F32 = PPA_SPMV_WCHUNK_F32;  // nonzeros per windowed block, FP32 values
+constexpr int SPMV_WCHUNK_F64 = 4096;                 // nonzeros per windowed block, FP64 values
 
 struct Window {
     bool on = false;                 // selected for this value type
