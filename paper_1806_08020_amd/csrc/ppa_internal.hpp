@@ -54,7 +54,14 @@ constexpr int NUM_XCD = 8;
 #endif
 constexpr int SPMV_WBS = PPA_SPMV_WBS;                // threads per windowed block
 constexpr int SPMV_WCHUNK_F32 = PPA_SPMV_WCHUNK_F32;  // nonzeros per windowed block, FP32 values
-constexpr int SPMV_WCHUNK_F64 = 4096;                 // nonzeros per windowed block, FP64 values
+#ifndef PPA_SPMV_WCHUNK_F64
+#define PPA_SPMV_WCHUNK_F64 8192
+#endif
+#ifndef PPA_SPMV_WIN_LDS_MAX
+#define PPA_SPMV_WIN_LDS_MAX (160 * 1024)
+#endif
+constexpr int SPMV_WCHUNK_F64 = PPA_SPMV_WCHUNK_F64;  // nonzeros per windowed block, FP64 values
+constexpr int SPMV_WIN_LDS_MAX = PPA_SPMV_WIN_LDS_MAX;   // LDS budget of one windowed block
 
 struct Window {
     bool on = false;                 // selected for this value type

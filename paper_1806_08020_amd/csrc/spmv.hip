@@ -707,7 +707,7 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
     for (int64_t b = 0; b < nb; ++b) smax = std::max(smax, meta[2 * b + 1]);
     // products, then the window with room for the 16-byte aligned copy
     const size_t lds = (size_t)chunk * vbytes + (size_t)(smax + 8) * vbytes;
-    bool ok = lds <= (size_t)maxlds && lds <= 96 * 1024;
+    bool ok = lds <= (size_t)maxlds && lds <= (size_t)SPMV_WIN_LDS_MAX;
     if (ok) ok = allow_lds(vbytes, lds);
     PPA_HIP(hipFree(dblk));
     PPA_HIP(hipFree(dmeta));

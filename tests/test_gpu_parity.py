@@ -437,25 +437,34 @@ def test_windowed_spmv_bitwise_equal(lib, name):
 
 
 def test_windowed_with_long_rows(lib):
-    """Rows longer than the FP64 windowed block (4096 nonzeros) disable the
-    FP64 window; the FP32 window (8192 nonzeros per block) still takes them.
-    The plain kernel reduces rows longer than 2048 nonzeros with a block-wide
-    tree, so those rows agree to rounding, all others bitwise."""
+    """A 6000-nonzero row fits the windowed blocks (8192 nonzeros, FP64 and
+    FP32); the plain kernel reduces rows longer than 2048 nonzeros with a
+    block-wide tree, so those rows agree to rounding, all others bitwise.  A
+    row longer than the windowed block (10000 nonzeros) disables the window."""
     csr = MATS["long_rows"]
     A = lib.Matrix(csr, want_f32=True, window="force")
     Ap = lib.Matrix(csr, want_f32=True, window="off")
-    assert not A.windowed("f64") and A.windowed("f32")
+    assert A.windowed("f64") and A.windowed("f32")
     rng = np.random.default_rng(4)
-    uh = rng.standard_normal(csr.n).astype(np.float32)
-    u = dev(uh, torch.float32)
-    yw = host(lib.fused_spmv(A, 0.0, None, 1.0, u))
-    yp = host(lib.fused_spmv(Ap, 0.0, None, 1.0, u))
     lens = np.diff(csr.rowptr)
     short = lens <= 2048
-    assert np.array_equal(yw[short], yp[short])
     S = csr.to_scipy()
-    bound = lens * 2 * EPS32 * (abs(S) @ np.abs(uh.astype(float)))
-    assert np.all(np.abs(yw - yp) <= bound)
+    for dt, eps in ((torch.float32, EPS32), (torch.float64, EPS64)):
+        uh = rng.standard_normal(csr.n).astype(np.float32 if dt == torch.float32 else np.float64)
+        u = dev(uh, dt)
+        yw = host(lib.fused_spmv(A, 0.0, None, 1.0, u))
+        yp = host(lib.fused_spmv(Ap, 0.0, None, 1.0, u))
+        assert np.array_equal(yw[short], yp[short])
+        bound = lens * 2 * eps * (abs(S) @ np.abs(uh.astype(float)))
+        assert np.all(np.abs(yw - yp) <= bound)
+    n = 10000
+    rows = np.concatenate([np.arange(n), np.full(n, 3)])
+    cols = np.concatenate([np.arange(n), np.arange(n)])
+    vals = np.concatenate([np.full(n, 2.0), rng.standard_normal(n)])
+    keep = ~((rows == 3) & (cols == 3))
+    B = W._from_coo(n, rows[keep], cols[keep], vals[keep])
+    Ab = lib.Matrix(B, want_f32=True, window="force")
+    assert not Ab.windowed("f64") and not Ab.windowed("f32")
 
 
 def test_windowed_apply_matches_oracle(lib):
