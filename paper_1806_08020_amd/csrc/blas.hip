@@ -12,6 +12,8 @@
 #include "ppa_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 #include <cmath>
 
 namespace ppa {
@@ -156,6 +158,34 @@ __global__ __launch_bounds__(BS) void k_update(const double* __restrict__ V, int
     }
 }
 
+// f(integral_constant<int, I>) for I = 0..N-1, each index a compile-time constant.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// One butterfly reduce-scatter step and the ones after it: a lane keeps half
+// of its K columns (the upper half when bit O of its lane is set) and adds
+// the partner lane's copy of that half.
+template <int JT, int K, int O>
+__device__ __forceinline__ void butterfly(double (&v)[JT], int lane, int& col) {
+    if constexpr (K > 1) {
+        const bool up = (lane & O) != 0;
+        static_for<K / 2>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const double send = up ? v[i] : v[K / 2 + i];
+            const double keep = up ? v[K / 2 + i] : v[i];
+            v[i] = keep + __shfl_xor(send, O, 64);
+        });
+        if (up) col += K / 2;
+        butterfly<JT, K / 2, O / 2>(v, lane, col);
+    }
+}
+
 // The reorthogonalisation's update and projection in one pass over V:
 //   t = w - V h          (h = the first projection, length j)
 //   partial[c * nb + b] = sum over the block's rows of V[c][r] t[r]  (c < j)
@@ -178,35 +208,34 @@ __global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V
     const int64_t rr = r < n ? r : n - 1;
     // columns past j re-read column j - 1 (weight 0): unconditional loads
     // keep the register count lowest; the instance is chosen with JT < 2j
+    // every index into v is a compile-time constant (static_for), so the
+    // array lives in registers from the start; loop-indexed accesses let the
+    // compiler turn the butterfly's selects into dynamically indexed
+    // register reads (long compare-and-select chains) for some JT
     double v[JT];
-#pragma unroll
-    for (int c = 0; c < JT; ++c) v[c] = V[(int64_t)min(c, j - 1) * ldv + rr];
+    static_for<JT>([&](auto ic) {
+        constexpr int c = decltype(ic)::value;
+        v[c] = V[(int64_t)min(c, j - 1) * ldv + rr];
+    });
     double tv = w[rr];
     // h is staged in LDS after the row's loads are in flight
     for (int c = threadIdx.x; c < JT; c += BS) hs[c] = c < j ? h[c] : 0.0;
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < JT; ++c) tv -= v[c] * hs[c];
+    static_for<JT>([&](auto ic) {
+        constexpr int c = decltype(ic)::value;
+        tv -= v[c] * hs[c];
+    });
     if (r < n) t[r] = tv;
     const double wt = r < n ? tv : 0.0;
-#pragma unroll
-    for (int c = 0; c < JT; ++c) v[c] = c < j ? v[c] * wt : 0.0;
+    static_for<JT>([&](auto ic) {
+        constexpr int c = decltype(ic)::value;
+        v[c] = c < j ? v[c] * wt : 0.0;
+    });
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int col = 0;
-    int o = 32;
-#pragma unroll
-    for (int K = JT; K > 1; K >>= 1, o >>= 1) {
-        const bool up = (lane & o) != 0;
-#pragma unroll
-        for (int i = 0; i < K / 2; ++i) {
-            const double send = up ? v[i] : v[K / 2 + i];
-            const double keep = up ? v[K / 2 + i] : v[i];
-            v[i] = keep + __shfl_xor(send, o, 64);
-        }
-        if (up) col += K / 2;
-    }
+    butterfly<JT, JT, 32>(v, lane, col);
     // lanes that share a column now hold partial sums over disjoint lanes
-    for (; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
+    for (int o = 32 / JT; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
     if ((lane & (64 / JT - 1)) == 0) red[wave][col] = v[0];
     __syncthreads();
     for (int c = threadIdx.x; c < j; c += BS) {
