@@ -326,7 +326,7 @@ def main():
                          "safeguard or harmonic blocks (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs the solver on one GPU only (no multi-GPU path): --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -63,7 +63,7 @@ class BatchRequest(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        raise ImportError(f"{LIB_PATH} is not built: run python -m paper_1806_08020_amd.build")
     lib = C.CDLL(LIB_PATH)
     i, i64, d, sz = C.c_int, C.c_int64, C.c_double, C.c_size_t
     P = C.POINTER

@@ -22,7 +22,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def cdll():
     if not os.path.exists(LIB):
-        pytest.fail("libppa.so is not built (run __graft_entry__.build())")
+        pytest.fail("libppa.so is not built (run python -m paper_1806_08020_amd.build)")
     import torch  # noqa: F401  (same HIP runtime as the product path)
     return ctypes.CDLL(LIB)
 
