@@ -314,7 +314,8 @@ def served_mix_report(count):
     """Served mix (2-D convection-diffusion solves of random size, degree and
     nev, seeded): capacity from a closed-loop run (all requests at t = 0),
     then Poisson arrivals at 0.7 x capacity, FP64 and mixed precision (mixed
-    applies to the single-solve path; the batched small solves run FP64)."""
+    applies to the single-solve path; the batched small solves run FP64), and
+    FP64 with graph-replayed restart cycles on the single-solve path."""
     from paper_1806_08020_amd import serve as S
     reqs = S.served_mix(count=count, seed=5, rate=1e9, max_cycles=30)
     budget = 200 * 2**30
@@ -338,12 +339,16 @@ def served_mix_report(count):
     arr = np.cumsum(rng.exponential(1.0 / rate, size=count))
     rep = {"requests": count, "capacity_req_per_s": round(capacity, 2), "rate_req_per_s": round(rate, 2),
            "closed_loop": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in closed.items()}}
-    for prec in ("f64", "mixed"):
+    for name, prec, graph in (("f64", "f64", False), ("mixed", "mixed", False),
+                              ("f64_graph", "f64", True)):
         for r, t in zip(reqs, arr):
             r.arrival = float(t)
             r.precision = prec
+            r.graph = graph
         o = run(reqs)
-        rep[prec] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in o.items()}
+        rep[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in o.items()}
+    rep["note"] = ("f64_graph: the same arrivals with the single-solve path replaying each restart "
+                   "cycle from a HIP graph (PPA_FLAG_GRAPH)")
     return rep
 
 

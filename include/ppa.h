@@ -321,6 +321,15 @@ typedef struct ppa_eigs_opts {
  * Gram-Schmidt with reorthogonalisation; section 9 names communication-
  * avoiding variants as future work). */
 #define PPA_FLAG_LOWSYNC 4
+/* Record each restart cycle's Krylov steps (operator applications and
+ * Gram-Schmidt: every launch between two host synchronisations) into a HIP
+ * graph on a private capture stream, and replay it on `stream` whenever a
+ * later cycle starts from the same column with the same basis buffer and
+ * operator precision (at most four graphs per solve; the restart alternates
+ * two basis buffers).  The launches are the same, so results are bitwise
+ * those of the eager run; replays save the per-launch host overhead, which
+ * dominates for small and mid-size matrices.  Ignored with PPA_FLAG_TIMING. */
+#define PPA_FLAG_GRAPH 8
 
 typedef struct ppa_eigs_result {
     /* host arrays of capacity nev, filled with the returned pairs sorted by

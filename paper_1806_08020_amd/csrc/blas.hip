@@ -360,7 +360,7 @@ __global__ __launch_bounds__(BS) void k_dcoef(int kind, int jq, const double* __
                                               double tol) {
     __shared__ double sa[CGS_JMAX_ALL], sc[CGS_JMAX_ALL + 1];
     __shared__ double rsum[NW * 2];
-    __shared__ double s_inv, s_beta;
+    __shared__ double s_inv, s_gamma;
     double* g = coef + CGS_JMAX_ALL;
     double* sv = coef + 2 * CGS_JMAX_ALL;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -409,7 +409,6 @@ __global__ __launch_bounds__(BS) void k_dcoef(int kind, int jq, const double* __
         const double uu = dred[2 * jq];
         const double beta = sqrt(fmax(uu - ta, 0.0));
         const double zn = sqrt(scal[0] + uu);
-        s_beta = beta;
         s_inv = (beta > tol * zn && beta > 0.0) ? 1.0 / beta : 0.0;
         Hd[jq + (int64_t)(jq - 1) * ldh] = beta;
     }
@@ -427,6 +426,7 @@ __global__ __launch_bounds__(BS) void k_dcoef(int kind, int jq, const double* __
     // c = Hbar_jq a ((jq + 1) entries, columns 0..jq-1 final)
     for (int i = tid; i <= jq; i += BS) {
         double t = 0.0;
+#pragma unroll 8
         for (int l = 0; l < jq; ++l) t += Hd[i + (int64_t)l * ldh] * sa[l];
         sc[i] = t;
     }
@@ -458,10 +458,10 @@ __global__ __launch_bounds__(BS) void k_dcoef(int kind, int jq, const double* __
         sv[0] = inv;
         sv[1] = inv;
         sv[2] = gamma;
-        s_beta = gamma;   // reused to broadcast gamma
+        s_gamma = gamma;
     }
     __syncthreads();
-    const double gamma = s_beta;
+    const double gamma = s_gamma;
     for (int i = tid; i < jq; i += BS) g[i] = sc[i] * inv + g[i] - gamma * sa[i];
 }
 

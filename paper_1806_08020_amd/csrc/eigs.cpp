@@ -363,20 +363,45 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     double t_apply = 0.0, t_cgs = 0.0;
     int fp32_cycles = 0;
 
+    // stream of the Krylov steps: s, or the capture stream while a cycle's
+    // steps are recorded into a graph
+    hipStream_t cur = s;
     auto apply_op = [&](const double* x, double* y) {
         if (!p) {
             spmv_bytes += launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, x, 0.0, nullptr,
-                                            0.0, nullptr, y, s);
+                                            0.0, nullptr, y, cur);
         } else if (fp32) {
-            spmv_bytes += apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F32, e.aw32, s);
+            spmv_bytes += apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F32, e.aw32, cur);
         } else {
-            spmv_bytes += apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F64, e.aw64, s);
+            spmv_bytes += apply_poly(A, *p, VecT::F64, x, VecT::F64, y, VecT::F64, e.aw64, cur);
         }
         mvps += op_mvps;
         vops += op_vops;
         passes += op_mvps;
         if (fp32 && p) passes32 += op_mvps;
     };
+    // HIP graphs of a cycle's Krylov steps, keyed by the start column, the
+    // basis buffer (the restart swaps two) and the operator's precision; a
+    // replay adds the counters the recorded launches added
+    const bool graph = (o.flags & PPA_FLAG_GRAPH) != 0 && !timing;
+    struct CycleGraph {
+        int j0;
+        const double* V;
+        bool fp32;
+        hipGraphExec_t exec;
+        int64_t dm, dd, dv, dp, dp32;
+        double db;
+    };
+    struct Graphs {
+        std::vector<CycleGraph> g;
+        hipStream_t cs = nullptr;
+        ~Graphs() {
+            for (auto& x : g) (void)hipGraphExecDestroy(x.exec);
+            if (cs) (void)hipStreamDestroy(cs);
+        }
+    } graphs;
+    bool graph_ok = graph;
+    constexpr size_t kMaxGraphs = 4;
 
     launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
     set_unit(n, v0, e.V, e.dpart, nb, e.dout, s);
@@ -397,12 +422,54 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         if (fp32) ++fp32_cycles;
         // the delayed form keeps its candidates in two columns of V2, which is
         // free until the restart
-        arnoldi_steps(n, j0, m, lowsync, e.V, e.ld, e.w, e.Hd, m + 1, e.V2, e.V2 + e.ld, e.cw, s,
-                      apply_op,
-                      [&](int j, int phase) {
-                          if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + phase], s));
-                      },
-                      dots, vops);
+        auto steps = [&](hipStream_t st) {
+            cur = st;
+            arnoldi_steps(n, j0, m, lowsync, e.V, e.ld, e.w, e.Hd, m + 1, e.V2, e.V2 + e.ld, e.cw, st,
+                          apply_op,
+                          [&](int j, int phase) {
+                              if (timing) PPA_HIP(hipEventRecord(tev.ev[3 * j + phase], st));
+                          },
+                          dots, vops);
+            cur = s;
+        };
+        const CycleGraph* hit = nullptr;
+        if (graph_ok)
+            for (const auto& x : graphs.g)
+                if (x.j0 == j0 && x.V == e.V && x.fp32 == fp32) hit = &x;
+        if (hit) {
+            PPA_HIP(hipGraphLaunch(hit->exec, s));
+            mvps += hit->dm;
+            dots += hit->dd;
+            vops += hit->dv;
+            passes += hit->dp;
+            passes32 += hit->dp32;
+            spmv_bytes += hit->db;
+        } else if (graph_ok && graphs.g.size() < kMaxGraphs) {
+            if (!graphs.cs) PPA_HIP(hipStreamCreateWithFlags(&graphs.cs, hipStreamNonBlocking));
+            const int64_t m0 = mvps, d0 = dots, v0c = vops, p0 = passes, q0 = passes32;
+            const double b0 = spmv_bytes;
+            PPA_HIP(hipStreamBeginCapture(graphs.cs, hipStreamCaptureModeThreadLocal));
+            hipGraph_t gr = nullptr;
+            try {
+                steps(graphs.cs);
+            } catch (...) {
+                cur = s;
+                (void)hipStreamEndCapture(graphs.cs, &gr);
+                if (gr) (void)hipGraphDestroy(gr);
+                (void)hipGetLastError();
+                throw;
+            }
+            PPA_HIP(hipStreamEndCapture(graphs.cs, &gr));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            PPA_HIP(ie);
+            graphs.g.push_back({j0, e.V, fp32, ex, mvps - m0, dots - d0, vops - v0c, passes - p0,
+                                passes32 - q0, spmv_bytes - b0});
+            PPA_HIP(hipGraphLaunch(ex, s));
+        } else {
+            steps(s);
+        }
         PPA_HIP(hipMemcpyAsync(H.data(), e.Hd, H.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         PPA_HIP(hipStreamSynchronize(s));
         if (timing) {

@@ -421,12 +421,14 @@ def eigs_workspace(A: Matrix, p: Poly | None, m, k, nev, precision="f64"):
 def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, rtol: float = 1e-8,
          max_cycles: int = 100, precision: str = "f64", anorm: float = 0.0,
          want_vectors: bool = False, ws=None, timing: bool = False,
-         harmonic: bool = False, lowsync: bool = False) -> EigsOut:
+         harmonic: bool = False, lowsync: bool = False, graph: bool = False) -> EigsOut:
     """Thick-restarted Arnoldi(m,k) on pi(A) for nev eigenpairs of A
     (``harmonic``: restart with harmonic Ritz vectors; ``lowsync``: Gram-Schmidt
-    with the reorthogonalisation delayed by one step)."""
+    with the reorthogonalisation delayed by one step; ``graph``: replay each
+    cycle's Krylov steps from a HIP graph)."""
     o = EigsOpts(m, k, nev, max_cycles, rtol, anorm, _PREC[precision],
-                 (1 if timing else 0) | (2 if harmonic else 0) | (4 if lowsync else 0))
+                 (1 if timing else 0) | (2 if harmonic else 0) | (4 if lowsync else 0)
+                 | (8 if graph else 0))
     if ws is None:
         nb = C.c_size_t()
         _check(_lib.ppa_eigs_workspace_bytes(A.h, p.h if p else None, C.byref(o), C.byref(nb)))

@@ -43,6 +43,7 @@ class Request:
     max_cycles: int = 30
     arrival: float = 0.0          # seconds after the start of the run
     precision: str = "f64"        # "f64" or "mixed" (mixed applies to the stream path)
+    graph: bool = False           # stream path: replay restart cycles from HIP graphs
 
 
 @dataclass
@@ -75,7 +76,7 @@ def stream_footprint(rq: Request) -> int:
     if rq.precision == "mixed":
         f += 4 * rq.csr.nnz + 4 * 6 * n
     f += 8 * ld * (2 * (rq.m + 1) + 4 * rq.nev + 12)
-    f += 8 * ld * (rq.d + 2) + 8 * ld
+    f += 8 * ld * (rq.d + 5) + 8 * ld
     return int(f)
 
 
@@ -90,7 +91,7 @@ def _solve_stream(rq: Request, stream: torch.cuda.Stream) -> ppa.EigsOut:
         v0 = torch.as_tensor(rq.v0, device="cuda")
         P = ppa.Poly.build(A, rq.d, b)
         r = ppa.eigs(A, P, v0, rq.m, rq.k, rq.nev, rtol=rq.rtol, max_cycles=rq.max_cycles,
-                     precision=rq.precision)
+                     precision=rq.precision, graph=rq.graph)
         stream.synchronize()
     return r
 
@@ -196,7 +197,7 @@ class Server:
 
 # ---------------------------------------------------------------- served mix
 def served_mix(count: int = 512, seed: int = 5, rate: float = 50.0, side_max: int = 1000,
-               max_cycles: int = 30, precision: str = "f64") -> list[Request]:
+               max_cycles: int = 30, precision: str = "f64", graph: bool = False) -> list[Request]:
     """The served workload: 2-D convection-diffusion operators with grid side
     log-uniform in [32, side_max], beta*h uniform in [0, 0.8], nev uniform in
     {5..20}, d uniform in {10..60}, Arnoldi(max(30, 2(nev+5)), nev+5),
@@ -214,7 +215,7 @@ def served_mix(count: int = 512, seed: int = 5, rate: float = 50.0, side_max: in
         b, v0 = W.start_vectors(csr.n, 1000 * seed + i)
         k = nev + 5
         m = max(30, 2 * k)
-        out.append(Request(i, csr, d, m, k, nev, b, v0, 1e-8, max_cycles, t, precision))
+        out.append(Request(i, csr, d, m, k, nev, b, v0, 1e-8, max_cycles, t, precision, graph))
     return out
 
 

@@ -161,3 +161,18 @@ def test_band_full_eigs_reported_residuals(lib, band):
     assert np.all(np.abs(np.linalg.norm(X, axis=1) - 1) < 1e-12)
     res = host_residuals(band, r.mu, X)
     assert np.allclose(res, r.resid, rtol=1e-6, atol=1e-14 * A.norm_inf)
+
+
+def test_cd2_full_harmonic_properties(lib, cd2):
+    """The benchmark's operator with the harmonic restart (d = 50,
+    Arnoldi(50,25), nev = 20): converged, every returned pair's residual
+    recomputed on the host within rtol and equal to the reported one."""
+    b, v0 = W.start_vectors(cd2.n, 2)
+    A = lib.Matrix(cd2)
+    P = lib.Poly.build(A, 50, dev(b))
+    r = lib.eigs(A, P, dev(v0), 50, 25, 20, rtol=1e-8, max_cycles=40, harmonic=True, want_vectors=True)
+    assert r.converged and r.nconv == 20
+    X = host(r.X)
+    res = host_residuals(cd2, r.mu, X)
+    assert np.all(res <= 1e-8 * A.norm_inf * 1.001)
+    assert np.allclose(res, r.resid, rtol=1e-6, atol=1e-14 * A.norm_inf)
