@@ -553,12 +553,15 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         if (converged || broke || cycle == o.max_cycles) break;
 
         if (fp32) {
-            // leave the FP32 phase when the wanted residuals stop improving
-            // or approach the FP32 floor; restart in FP64 from the sum of the
-            // wanted unit Ritz vectors
+            // leave the FP32 phase when the wanted residuals reach the FP32
+            // floor, or stop improving within three decades of it (slow
+            // progress far above the floor is the method's, not the
+            // precision's, and FP64 cycles would not speed it up); restart in
+            // FP64 from the sum of the wanted unit Ritz vectors
             const size_t hc = hist.size();
-            const bool floor = mx <= 100.0 * 1.1920929e-07 * anorm;
-            const bool stall = hc >= 3 && hist[hc - 1] > 0.5 * hist[hc - 3];
+            const double floor_abs = 100.0 * 1.1920929e-07 * anorm;
+            const bool floor = mx <= floor_abs;
+            const bool stall = hc >= 3 && hist[hc - 1] > 0.5 * hist[hc - 3] && mx <= 1e3 * floor_abs;
             if (floor || stall) {
                 fp32 = false;
                 std::vector<double> coef(R.ycols, 0.0);
