@@ -641,7 +641,11 @@ void launch_dcgs_step(int kind, int64_t n, int jq, const double* V, int64_t ldv,
 // Operand layout of the 16x16x4 FP64 MFMA (wave of 64 lanes):
 //   A[i][k] in lane i + 16k;  B[k][j] in lane j + 16k;
 //   D[i][j] in lane j + 16 (i % 4), element i / 4.
+// The product is formed transposed, C_tile^T = Q_tile^T V_tile^T (A from Q,
+// B from V), so that each lane's outputs lie in one row of C and a store
+// instruction covers 16 consecutive rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
+
 
 template <int NT, int RT>
 __global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int kin, int kout,
@@ -658,7 +662,9 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int kin, int kout,
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t rbase = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
+    // the block stages Q once and walks row chunks of 4 waves x 16 RT rows
+    for (int64_t chunk = blockIdx.x; chunk * 4 * 16 * RT < n; chunk += gridDim.x) {
+    const int64_t rbase = (chunk * 4 + wave) * (16 * RT);
     v4d acc[RT][NT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -677,20 +683,23 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int64_t n, int kin, int kout,
             const double bq = Qs[kc * NP + t * 16 + li];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-                acc[rt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], bq, acc[rt][t], 0, 0, 0);
+                acc[rt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(bq, a[rt], acc[rt][t], 0, 0, 0);
         }
     }
+    // D = Q_tile^T V_tile^T: lane li + 16 lk holds rows li of columns
+    // t*16 + 4e + lk, so a store writes 16 consecutive rows of 4 columns
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int col = t * 16 + li;
+            const int64_t row = rbase + rt * 16 + li;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t row = rbase + rt * 16 + lk + 4 * e;
+                const int col = t * 16 + 4 * e + lk;
                 if (row < n && col < kout) C[(int64_t)col * ldc + row] = acc[rt][t][e];
             }
         }
+    }
 }
 
 void launch_gemm_tall(int64_t n, int kin, int kout, const double* V, int64_t ldv, const double* Q_d,
@@ -699,7 +708,8 @@ void launch_gemm_tall(int64_t n, int kin, int kout, const double* V, int64_t ldv
                 kin, kout);
     if (n <= 0) return;
     constexpr int RT = 2;
-    const unsigned grid = (unsigned)((n + 4 * 16 * RT - 1) / (4 * 16 * RT));
+    // enough blocks to fill the chip several times over; each stages Q once
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 4 * 16 * RT - 1) / (4 * 16 * RT), 2048);
     const int KP = (kin + 3) & ~3;
     const int NT = (kout + 15) / 16;
     const size_t lds = (size_t)KP * NT * 16 * sizeof(double);
