@@ -269,8 +269,9 @@ def harmonic_report():
 # nev = 15, mean of 10 trials on the paper's (unstated) machine:
 # degree -> (cycles, mvps in thousands, time in minutes).
 TABLE_8_1 = {"0": (7436.1, 223.1, 246.3), "10": (259.0, 78.3, 18.7), "25": (84.3, 64.2, 11.6),
-             "50": (41.2, 63.6, 10.0), "100": (20.6, 64.8, 9.5), "15x20": (3.8, 41.0, 1.7),
-             "25x40": (1.0, 51.0, 2.1)}
+             "50": (41.2, 63.6, 10.0), "100": (20.6, 64.8, 9.5), "125": (16.5, 65.3, 9.8),
+             "150": (14.0, 67.0, 9.9), "15x20": (3.8, 41.0, 1.7), "15x40": (2.0, 48.9, 2.0),
+             "15x50": (2.0, 61.2, 2.5), "25x40": (1.0, 51.0, 2.1), "25x60": (1.0, 76.5, 3.1)}
 
 
 def table81_report(max_cycles_d0):

@@ -21,6 +21,7 @@ PPA_OK = 0
 PPA_WARN_DEGREE_REDUCED = 1
 PPA_WARN_NOT_CONVERGED = 2
 PPA_WARN_BREAKDOWN = 3
+PPA_ERR_INVALID, PPA_ERR_HIP, PPA_ERR_WORKSPACE, PPA_ERR_NONFINITE = -1, -2, -3, -4
 PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
 PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF = 1, 2, 4
 _PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
