@@ -340,16 +340,18 @@ def served_mix_report(count):
     arr = np.cumsum(rng.exponential(1.0 / rate, size=count))
     rep = {"requests": count, "capacity_req_per_s": round(capacity, 2), "rate_req_per_s": round(rate, 2),
            "closed_loop": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in closed.items()}}
-    for name, prec, graph in (("f64", "f64", False), ("mixed", "mixed", False),
-                              ("f64_graph", "f64", True)):
+    for name, prec, graph, ls in (("f64", "f64", False, False), ("mixed", "mixed", False, False),
+                                  ("f64_graph", "f64", True, False), ("f64_lowsync", "f64", False, True)):
         for r, t in zip(reqs, arr):
             r.arrival = float(t)
             r.precision = prec
             r.graph = graph
+            r.lowsync = ls
         o = run(reqs)
         rep[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in o.items()}
-    rep["note"] = ("f64_graph: the same arrivals with the single-solve path replaying each restart "
-                   "cycle from a HIP graph (PPA_FLAG_GRAPH)")
+    rep["note"] = ("the same arrivals with the single-solve path replaying each restart cycle from "
+                   "a HIP graph (f64_graph, PPA_FLAG_GRAPH) or using the delayed-reorthogonalisation "
+                   "Gram-Schmidt (f64_lowsync, PPA_FLAG_LOWSYNC); the batched small solves are the same")
     return rep
 
 

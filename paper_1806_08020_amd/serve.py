@@ -44,6 +44,7 @@ class Request:
     arrival: float = 0.0          # seconds after the start of the run
     precision: str = "f64"        # "f64" or "mixed" (mixed applies to the stream path)
     graph: bool = False           # stream path: replay restart cycles from HIP graphs
+    lowsync: bool = False         # stream path: delayed-reorthogonalisation Gram-Schmidt
 
 
 @dataclass
@@ -89,9 +90,9 @@ def _solve_stream(rq: Request, stream: torch.cuda.Stream) -> ppa.EigsOut:
         A = ppa.Matrix(rq.csr, want_f32=(rq.precision == "mixed"))
         b = torch.as_tensor(rq.b, device="cuda")
         v0 = torch.as_tensor(rq.v0, device="cuda")
-        P = ppa.Poly.build(A, rq.d, b)
+        P = ppa.Poly.build(A, rq.d, b, lowsync=rq.lowsync)
         r = ppa.eigs(A, P, v0, rq.m, rq.k, rq.nev, rtol=rq.rtol, max_cycles=rq.max_cycles,
-                     precision=rq.precision, graph=rq.graph)
+                     precision=rq.precision, graph=rq.graph, lowsync=rq.lowsync)
         stream.synchronize()
     return r
 
