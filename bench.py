@@ -32,15 +32,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # the factors the same counters give for a plain 2 GiB device copy (FETCH_SIZE
 # reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config and
 # by the hash of the plain kernel's source (spmv.hip up to the windowed
-# variant) the counters were taken on and by the kernel's cache policy: any
-# change of that kernel makes the entry stale and the field null.
+# variant) the counters were taken on, by the cache policy and by the block
+# shape (nonzeros per block): any change of that kernel makes the entry stale
+# and the field null.
 MEASURED_TRAFFIC = {
-    ("c2", "bbda6c4e7141181c", "keep"): {"fetch_kib": 36517.35, "write_kib": 7817.53,
-                                        "fetch_factor": 2.0, "write_factor": 1.0},
-    ("c2", "bbda6c4e7141181c", "keep_ntst"): {"fetch_kib": 36526.83, "write_kib": 8084.75,
+    ("c2", "56f5605001f9c127", "keep", 512): {"fetch_kib": 36645.08, "write_kib": 7812.75,
                                              "fetch_factor": 2.0, "write_factor": 1.0},
-    ("c2", "bbda6c4e7141181c", "stream"): {"fetch_kib": 36909.38, "write_kib": 7812.87,
-                                          "fetch_factor": 2.0, "write_factor": 1.0},
+    ("c2", "56f5605001f9c127", "keep", 2048): {"fetch_kib": 36511.82, "write_kib": 7817.22,
+                                              "fetch_factor": 2.0, "write_factor": 1.0},
 }
 
 CONFIGS = {
@@ -372,6 +371,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--cache-policy", default="auto", choices=("auto", "stream", "keep", "keep_ntst"),
                     help="override the SpMV cache policy the matrix setup chose (for counter runs)")
+    ap.add_argument("--spmv-blocks", default="auto", choices=("auto", "2048", "512"),
+                    help="override the SpMV block shape (nonzeros per block) the matrix setup chose")
     ap.add_argument("--table-d0-cycles", type=int, default=1500,
                     help="restart cycles allowed to standard Arnoldi in the Table 8.1 block")
     ap.add_argument("--lowsync", action="store_true",
@@ -398,6 +399,8 @@ def main():
     A = ppa.Matrix(csr, want_f32=(prec != "f64"))
     if args.cache_policy != "auto":
         A.set_cache_policy(args.cache_policy, "f32" if prec == "mixed" else "f64")
+    if args.spmv_blocks != "auto":
+        A.set_spmv_blocks(int(args.spmv_blocks), "f32" if prec == "mixed" else "f64")
     bt = torch.as_tensor(b, device="cuda")
     vt = torch.as_tensor(v0, device="cuda")
     dbl = isinstance(cfg["d"], tuple)
@@ -439,7 +442,8 @@ def main():
     ksrc = open(os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")).read()
     khash = hashlib.sha256(ksrc[:ksrc.index("// Windowed variant:")].encode()).hexdigest()[:16]
     policy = A.cache_policy("f32" if prec == "mixed" else "f64")
-    tr = MEASURED_TRAFFIC.get((args.config, khash, policy))
+    blocks = A.spmv_blocks("f32" if prec == "mixed" else "f64")
+    tr = MEASURED_TRAFFIC.get((args.config, khash, policy, blocks))
     traffic = (round(1024 * (tr["fetch_kib"] * tr["fetch_factor"] + tr["write_kib"] * tr["write_factor"]))
                if tr else None)
     line = {
@@ -469,7 +473,7 @@ def main():
                   "mu_head": [[round(z.real, 10), round(z.imag, 10)] for z in results[-1].mu[:4]],
                   "fp32_cycles": results[-1].fp32_cycles},
         "roofline": {"kernel": "k_fused_spmv", "bound": "hbm",
-                     "cache_policy": policy,
+                     "cache_policy": policy, "nnz_per_block": blocks,
                      "achieved": round(kern_gbs, 1) if kern_gbs else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4) if kern_gbs else None,
                      "traffic": traffic, "bytes_per_launch": round(pi_bytes / max(passes, 1)),

@@ -110,7 +110,8 @@ int ppa_matrix_spmv_variant(const ppa_matrix* A, int precision, int* windowed);
  *   PPA_CACHE_KEEP_NTST  plain loads, non-temporal stores of the output.
  * ppa_matrix_create picks KEEP when one pass moves at most 128 MB and STREAM
  * otherwise, and on large matrices (n >= 200000, nnz >= 10^6) times the
- * three and switches to another only when it is at least 3% faster.  The setter overrides that choice
+ * three (with both block shapes, ppa_matrix_spmv_blocks) and switches only
+ * when another is at least 3% faster.  The setter overrides that choice
  * (PPA_ERR_INVALID for an unknown policy or precision, or PPA_F32 without
  * FP32 values); it must not race with launches that use A. */
 #define PPA_CACHE_STREAM 0
@@ -118,6 +119,16 @@ int ppa_matrix_spmv_variant(const ppa_matrix* A, int precision, int* windowed);
 #define PPA_CACHE_KEEP_NTST 2
 int ppa_matrix_cache_policy(const ppa_matrix* A, int precision, int* policy);
 int ppa_matrix_set_cache_policy(ppa_matrix* A, int precision, int policy);
+
+/* Block shape of the plain SpMV kernel, per value precision: *nnz_per_block
+ * = 2048 (blocks of 256 threads, the default) or 512 (blocks of 128
+ * threads).  Both sum each row in column order, so they agree bitwise on
+ * rows of at most 512 nonzeros; longer rows are reduced across a block in
+ * the small shape and agree to rounding.  ppa_matrix_create times both
+ * shapes with the cache policies on large matrices and switches only for a
+ * 3% gain; the setter overrides (PPA_ERR_INVALID for another value). */
+int ppa_matrix_spmv_blocks(const ppa_matrix* A, int precision, int* nnz_per_block);
+int ppa_matrix_set_spmv_blocks(ppa_matrix* A, int precision, int nnz_per_block);
 
 /* ------------------------------------------------------------------------
  * Polynomial pi in factored form, eq. (2.1): pi(z) = prod_i (1 - z/theta_i),

@@ -146,6 +146,30 @@ int ppa_matrix_set_cache_policy(ppa_matrix* h, int precision, int policy) {
     });
 }
 
+int ppa_matrix_spmv_blocks(const ppa_matrix* h, int precision, int* nnz_per_block) {
+    return guarded([&] {
+        PPA_REQUIRE(h && nnz_per_block, "matrix and nnz_per_block are required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        const Matrix* A = reinterpret_cast<const Matrix*>(h);
+        const int b = precision == PPA_F64 ? A->blk64 : A->blk32;
+        *nnz_per_block = b == 1 ? SPMV_CHUNK_S : SPMV_CHUNK;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_set_spmv_blocks(ppa_matrix* h, int precision, int nnz_per_block) {
+    return guarded([&] {
+        PPA_REQUIRE(h, "matrix is required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        PPA_REQUIRE(nnz_per_block == SPMV_CHUNK || nnz_per_block == SPMV_CHUNK_S,
+                    "nnz_per_block must be %d or %d", SPMV_CHUNK, SPMV_CHUNK_S);
+        Matrix* A = reinterpret_cast<Matrix*>(h);
+        PPA_REQUIRE(precision == PPA_F64 || A->v32, "the matrix has no FP32 values");
+        (precision == PPA_F64 ? A->blk64 : A->blk32) = nnz_per_block == SPMV_CHUNK_S ? 1 : 0;
+        return PPA_OK;
+    });
+}
+
 static std::vector<cplx> read_roots(int deg, const double* re, const double* im) {
     PPA_REQUIRE(deg >= 1 && re, "polynomial needs deg >= 1 roots");
     std::vector<cplx> r(deg);

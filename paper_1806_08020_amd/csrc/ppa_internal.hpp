@@ -39,6 +39,9 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 #endif
 constexpr int SPMV_BS = PPA_SPMV_BS;
 constexpr int SPMV_CHUNK = PPA_SPMV_CHUNK;
+// the plain kernel's second block shape: 128 threads, 512 nonzeros
+constexpr int SPMV_BS_S = 128;
+constexpr int SPMV_CHUNK_S = 512;
 constexpr int SPMV_MAXROWS = PPA_SPMV_CHUNK;
 // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin.
 constexpr int NUM_XCD = 8;
@@ -86,6 +89,9 @@ struct Matrix {
     int64_t nblocks = 0;
     int align = 1;                   // block ranges start at multiples of this (1 or 4)
     int cp64 = CP_KEEP, cp32 = CP_KEEP;   // cache policy of the plain SpMV kernel per value type
+    int4* bm_s = nullptr;            // partition into SPMV_CHUNK_S-nonzero blocks
+    int64_t nblocks_s = 0;
+    int blk64 = 0, blk32 = 0;        // plain kernel block shape per value type: 0 large, 1 small
     double norm_inf = 0.0;
     int device = 0;
     Window win64, win32;

@@ -7,17 +7,18 @@
 // z, z2 for the double-polynomial epilogue of section 8) and writes out.
 //
 // Layout and mapping (gfx950):
-//  * rows are cut into row blocks of at most SPMV_CHUNK nonzeros; a block of
-//    SPMV_BS threads first loads its contiguous nonzero range (colind, values)
-//    with unit-stride loads (non-temporal for matrices far larger than the
+//  * rows are cut into row blocks of at most 2048 nonzeros for blocks of 256
+//    threads, or of 512 for blocks of 128 (a per-matrix choice); a block
+//    first loads its contiguous nonzero range (colind, values) with
+//    unit-stride loads (non-temporal for matrices far larger than the
 //    last-level cache, cached otherwise: a per-matrix policy that the setup
-//    times on large matrices), multiplies by the gathered u and
-//    stages the products in LDS, then each thread sums whole rows from LDS and
+//    times on large matrices), multiplies by the gathered u and stages the
+//    products in LDS, then each thread sums whole rows from LDS and
 //    applies the axpy epilogue -- every global access but the gather of u is
 //    coalesced.  The row pointers and streamed vectors of a thread's first
 //    rows are loaded before the LDS barrier so their latency overlaps the
 //    product phase;
-//  * a row with more than SPMV_CHUNK nonzeros gets a block of its own that
+//  * a row longer than the block's nonzero budget gets a block of its own that
 //    reduces it across the block;
 //  * block ids are remapped so that each of the 8 XCDs walks one contiguous
 //    range of rows: neighbouring row blocks share gathered u lines in the same
@@ -198,34 +199,34 @@ __device__ __forceinline__ Grp<G, T> load_grp(const T* __restrict__ p, int idx, 
 // Main fused kernel.  Each thread reads column indices and values as groups
 // of G consecutive nonzeros (16-byte loads for G = 4 and 4-byte indices);
 // groups start at the block's first nonzero rounded down to a multiple of G
-// (the partition guarantees that this aligned range holds at most
-// SPMV_CHUNK entries).  Positions outside the block are masked to zero, the
+// (the partition guarantees that this aligned range holds at most CH_
+// entries, the block's nonzero budget, with BS_ threads).  Positions outside the block are masked to zero, the
 // products land in LDS at their aligned position and each thread sums whole
 // rows from an offset view.  Every load of the block is issued before the
 // first gathered value is used.
-template <typename VT, typename IT, typename OT, int G, bool EPI, int CP>
-__global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
+template <typename VT, typename IT, typename OT, int G, bool EPI, int CP, int BS_, int CH_>
+__global__ __launch_bounds__(BS_) void k_fused_spmv(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const VT* __restrict__ val, const int4* __restrict__ bm, int nblk, int nnz,
     const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
     const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
-    constexpr int PER = SPMV_CHUNK / SPMV_BS;
-    static_assert(PER * SPMV_BS == SPMV_CHUNK, "chunk must be a multiple of the block size");
+    constexpr int PER = CH_ / BS_;
+    static_assert(PER * BS_ == CH_, "chunk must be a multiple of the block size");
     constexpr int NG = (PER + G - 1) / G;      // groups per thread (the last may be idle)
     // products at their aligned positions; the long-row path reuses it for its partials
-    __shared__ __align__(16) VT prod_ext[NG * G * SPMV_BS];
+    __shared__ __align__(16) VT prod_ext[NG * G * BS_];
     const int b = xcd_remap(blockIdx.x, nblk);
     const int4 m = bm[b];   // rows [r0, r1), nonzeros [p0, p1): one 16-byte load
     const int r0 = m.x, r1 = m.y, p0 = m.z, p1 = m.w;
     const int tid = threadIdx.x;
     const int base = p0 & ~(G - 1);
-    if (p1 - base > SPMV_CHUNK) {
+    if (p1 - base > CH_) {
         // only a block of one row can exceed the budget (partition invariant)
-        long_row<VT, IT, OT, SPMV_BS>(rowptr, colind, val, r0, p0, p1, x, u, z, z2, out, alpha,
+        long_row<VT, IT, OT, BS_>(rowptr, colind, val, r0, p0, p1, x, u, z, z2, out, alpha,
                                       beta, gamma, delta, prod_ext);
         return;
     }
-    const int ra = r0 + tid, rb = r0 + tid + SPMV_BS;
+    const int ra = r0 + tid, rb = r0 + tid + BS_;
     RowPre<VT> qa, qb;
     if constexpr (G == 1) {
         // positions past the block re-read its last nonzero (masked below)
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
         if (cnt > 0) {
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                const int j = min(p0 + tid + k * SPMV_BS, last);
+                const int j = min(p0 + tid + k * BS_, last);
                 c[k] = stream_load<CP>(colind + j);
                 v[k] = stream_load<CP>(val + j);
             }
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
             for (int k = 0; k < PER; ++k) g[k] = (VT)u[c[k]];
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                const int i = tid + k * SPMV_BS;
+                const int i = tid + k * BS_;
                 prod_ext[i] = i < cnt ? v[k] * g[k] : (VT)0;
             }
         }
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
         if (p1 > p0) {
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
-                const int idx = base + G * min(tid + k * SPMV_BS, gmax);
+                const int idx = base + G * min(tid + k * BS_, gmax);
                 const bool full = idx + G <= nnz;
                 c[k] = load_grp<G, CP>(colind, idx, full, nnz - 1);
                 v[k] = load_grp<G, CP>(val, idx, full, nnz - 1);
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
                 for (int j = 0; j < G; ++j) g[k][j] = (VT)u[c[k].v[j]];
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
-                const int pos = G * (tid + k * SPMV_BS);
+                const int pos = G * (tid + k * BS_);
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
                     const int e = base + pos + j;
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(SPMV_BS) void k_fused_spmv(
     const VT* prod = prod_ext + (p0 - base);
     if (ra < r1) row_out<CP>(qa, prod, p0, ra, out, alpha, beta, gamma, delta);
     if (rb < r1) row_out<CP>(qb, prod, p0, rb, out, alpha, beta, gamma, delta);
-    for (int r = r0 + tid + 2 * SPMV_BS; r < r1; r += SPMV_BS) {
+    for (int r = r0 + tid + 2 * BS_; r < r1; r += BS_) {
         const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
         row_out<CP>(q, prod, p0, r, out, alpha, beta, gamma, delta);
     }
@@ -424,20 +425,28 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, double al
                 : go(k_fused_spmv_win<VT, IT, OT, CH, 1, false>);
     } else {
         const bool grp = G > 1 && A.align % G == 0 && valg;
-        auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)A.nblocks), dim3(SPMV_BS), 0, s, A.rowptr,
-                               A.colind, val, A.bm, (int)A.nblocks, (int)A.nnz, (const IT*)x,
-                               (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o, (VT)alpha,
-                               (VT)beta, (VT)gamma, (VT)delta);
+        const bool small = (sizeof(VT) == 8 ? A.blk64 : A.blk32) == 1;
+        const int4* bm = small ? A.bm_s : A.bm;
+        const int64_t nblk = small ? A.nblocks_s : A.nblocks;
+        auto go = [&](auto kern, int bs) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(bs), 0, s, A.rowptr, A.colind, val,
+                               bm, (int)nblk, (int)A.nnz, (const IT*)x, (const IT*)u, (const IT*)z,
+                               (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+        };
+        auto shape = [&](auto cp, auto bsc, auto chc) {
+            constexpr int P = decltype(cp)::value, B = decltype(bsc)::value, H = decltype(chc)::value;
+            if (grp)
+                epi ? go(k_fused_spmv<VT, IT, OT, G, true, P, B, H>, B)
+                    : go(k_fused_spmv<VT, IT, OT, G, false, P, B, H>, B);
+            else
+                epi ? go(k_fused_spmv<VT, IT, OT, 1, true, P, B, H>, B)
+                    : go(k_fused_spmv<VT, IT, OT, 1, false, P, B, H>, B);
         };
         auto pick = [&](auto cp) {
-            constexpr int P = decltype(cp)::value;
-            if (grp)
-                epi ? go(k_fused_spmv<VT, IT, OT, G, true, P>)
-                    : go(k_fused_spmv<VT, IT, OT, G, false, P>);
+            if (small)
+                shape(cp, std::integral_constant<int, SPMV_BS_S>(), std::integral_constant<int, SPMV_CHUNK_S>());
             else
-                epi ? go(k_fused_spmv<VT, IT, OT, 1, true, P>)
-                    : go(k_fused_spmv<VT, IT, OT, 1, false, P>);
+                shape(cp, std::integral_constant<int, SPMV_BS>(), std::integral_constant<int, SPMV_CHUNK>());
         };
         const int cp = sizeof(VT) == 8 ? A.cp64 : A.cp32;
         if (cp == CP_KEEP)
@@ -788,6 +797,21 @@ void matrix_setup(Matrix& A, hipStream_t s) {
     PPA_HIP(hipMalloc(&A.bm, rec.size() * sizeof(int32_t)));
     PPA_HIP(hipMemcpyAsync(A.bm, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     PPA_HIP(hipStreamSynchronize(s));
+    // the small-block partition (the setup timing may choose it)
+    {
+        std::vector<int32_t> bs = partition(rp, n, SPMV_CHUNK_S, SPMV_CHUNK_S, A.align, nullptr);
+        A.nblocks_s = (int64_t)bs.size() - 1;
+        std::vector<int32_t> rs(4 * std::max<int64_t>(A.nblocks_s, 1), 0);
+        for (int64_t b = 0; b < A.nblocks_s; ++b) {
+            rs[4 * b] = bs[b];
+            rs[4 * b + 1] = bs[b + 1];
+            rs[4 * b + 2] = rp[bs[b]];
+            rs[4 * b + 3] = rp[bs[b + 1]];
+        }
+        PPA_HIP(hipMalloc(&A.bm_s, rs.size() * sizeof(int32_t)));
+        PPA_HIP(hipMemcpyAsync(A.bm_s, rs.data(), rs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        PPA_HIP(hipStreamSynchronize(s));
+    }
     // untimed default cache policy: cached loads when one pass (matrix,
     // row pointers, two vectors in and one out) fits well inside the 256 MB
     // last-level cache, streaming loads otherwise; matrix_tune times the
@@ -799,16 +823,25 @@ void matrix_setup(Matrix& A, hipStream_t s) {
     A.cp32 = ws32 <= keep ? CP_KEEP : CP_STREAM;
 }
 
-// Average time of `reps` passes u -> y with the current kernel choice.
+// Average time of `reps` passes with the current kernel choice.
+// The passes form a chain, each reading the previous one's output (u and y
+// alternate), as the factors of a polynomial do, so that the treatment of
+// the output by the cache is timed together with its reuse.  The scaling
+// keeps the values bounded.
 static float time_passes(const Matrix& A, bool f32, void* u, void* y, int reps, hipStream_t s) {
     hipEvent_t e0, e1;
     PPA_HIP(hipEventCreate(&e0));
     PPA_HIP(hipEventCreate(&e1));
     const VecT t = f32 ? VecT::F32 : VecT::F64;
-    launch_fused_spmv(A, t, t, 1.0, u, -0.5, u, 0.0, nullptr, 0.0, nullptr, y, s);
+    const double beta = A.norm_inf > 0.0 ? -0.5 / A.norm_inf : -0.5;
+    auto pass = [&](int i) {
+        void* in = (i & 1) ? y : u;
+        void* out = (i & 1) ? u : y;
+        launch_fused_spmv(A, t, t, 1.0, in, beta, in, 0.0, nullptr, 0.0, nullptr, out, s);
+    };
+    pass(0);
     PPA_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i)
-        launch_fused_spmv(A, t, t, 1.0, u, -0.5, u, 0.0, nullptr, 0.0, nullptr, y, s);
+    for (int i = 1; i <= reps; ++i) pass(i);
     PPA_HIP(hipEventRecord(e1, s));
     PPA_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -819,9 +852,9 @@ static float time_passes(const Matrix& A, bool f32, void* u, void* y, int reps, 
 }
 
 void matrix_tune(Matrix& A, int mode, hipStream_t s) {
-    // Only large matrices are timed (a few passes each): the cache policy of
-    // the plain kernel, then, where the column ranges allow it, the windowed
-    // kernel against the plain one.  Short timings alternate the candidates
+    // Only large matrices are timed (a few passes each): the cache policy and
+    // block shape of the plain kernel, then, where the column ranges allow
+    // it, the windowed kernel against the plain one.  Short timings alternate the candidates
     // over three trials after a warm-up and compare the best trials: a single
     // timing favours whichever variant runs second on warm caches.
     if (A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
@@ -853,19 +886,25 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
         void* uu = u;
         if (f32) launch_cast_f64_f32(u, (float*)y, A.n, s), uu = y;   // FP32 copy of the ramp
         void* yy = f32 ? (void*)((float*)y + ((A.n + 63) & ~int64_t(63))) : (void*)y;
+        int& blk = f32 ? A.blk32 : A.blk64;
         const bool won = W.on;
         W.on = false;
         const int cp0 = cp;
-        float tcp[3] = {1e30f, 1e30f, 1e30f};
+        // candidates: cache policy c (0..2) with block shape b (0 large, 1 small)
+        float tc[6] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
         for (int trial = 0; trial < 4; ++trial)
-            for (int c = 0; c < 3; ++c) {
-                cp = c;
+            for (int c = 0; c < 6; ++c) {
+                cp = c % 3;
+                blk = c / 3;
                 const float t = time_passes(A, f32, uu, yy, 8, s);
-                if (trial > 0) tcp[c] = std::min(tcp[c], t);
+                if (trial > 0) tc[c] = std::min(tc[c], t);
             }
-        // the size rule's choice stays unless another policy is clearly faster
-        const int c_best = (int)(std::min_element(tcp, tcp + 3) - tcp);
-        cp = tcp[c_best] < 0.97f * tcp[cp0] ? c_best : cp0;
+        // the size rule's policy with large blocks stays unless another
+        // candidate is clearly faster
+        const int c_best = (int)(std::min_element(tc, tc + 6) - tc);
+        const int c_keep = tc[c_best] < 0.97f * tc[cp0] ? c_best : cp0;
+        cp = c_keep % 3;
+        blk = c_keep / 3;
         W.on = won;
         if (mode != 0 || !W.bm) continue;
         float t_plain = 1e30f, t_win = 1e30f;
@@ -899,6 +938,8 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
 
 void matrix_release(Matrix& A) {
     if (A.bm) (void)hipFree(A.bm);
+    if (A.bm_s) (void)hipFree(A.bm_s);
+    A.bm_s = nullptr;
     if (A.v32_owned) (void)hipFree(A.v32_owned);
     for (Window* W : {&A.win64, &A.win32}) {
         if (W->bm) (void)hipFree(W->bm);

@@ -77,6 +77,8 @@ def _load():
         "ppa_matrix_spmv_variant": (i, [vp, i, P(i)]),
         "ppa_matrix_cache_policy": (i, [vp, i, P(i)]),
         "ppa_matrix_set_cache_policy": (i, [vp, i, i]),
+        "ppa_matrix_spmv_blocks": (i, [vp, i, P(i)]),
+        "ppa_matrix_set_spmv_blocks": (i, [vp, i, i]),
         "ppa_poly_from_roots": (i, [i, P(d), P(d), i, P(d), P(d), P(vp)]),
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
@@ -198,6 +200,15 @@ class Matrix:
     def set_cache_policy(self, policy: str, precision: str = "f64") -> None:
         _check(_lib.ppa_matrix_set_cache_policy(self.h, _PREC[precision],
                                                 self.CACHE_POLICIES.index(policy)))
+
+    def spmv_blocks(self, precision: str = "f64") -> int:
+        """Nonzeros per block of the plain SpMV kernel (2048 or 512)."""
+        c = C.c_int()
+        _check(_lib.ppa_matrix_spmv_blocks(self.h, _PREC[precision], C.byref(c)))
+        return c.value
+
+    def set_spmv_blocks(self, nnz_per_block: int, precision: str = "f64") -> None:
+        _check(_lib.ppa_matrix_set_spmv_blocks(self.h, _PREC[precision], int(nnz_per_block)))
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -33,19 +33,32 @@ def test_policies_bitwise_equal(lib, name):
     A = lib.Matrix(csr, want_f32=True, window="off")
     rng = np.random.default_rng(5)
     u, x, z, z2 = (rng.standard_normal(csr.n) for _ in range(4))
+    lens = np.diff(csr.rowptr)
+    short = torch.as_tensor(lens <= 512, device="cuda")
     for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
         outs = []
-        for p in POL:
-            A.set_cache_policy(p, prec)
-            assert A.cache_policy(prec) == p
-            outs.append((lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt)),
-                         lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt), 1.5, dev(z, dt), -0.25,
-                                        dev(z2, dt)),
-                         lib.fused_spmv(A, 1.0, dev(u, dt), -0.5, dev(u, dt),
-                                        out_dtype=torch.float64 if prec == "f32" else None)))
-        for o in outs[1:]:
-            for a, b in zip(outs[0], o):
+        for blocks in (2048, 512):
+            A.set_spmv_blocks(blocks, prec)
+            assert A.spmv_blocks(prec) == blocks
+            for p in POL:
+                A.set_cache_policy(p, prec)
+                assert A.cache_policy(prec) == p
+                outs.append((lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt)),
+                             lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt), 1.5, dev(z, dt),
+                                            -0.25, dev(z2, dt)),
+                             lib.fused_spmv(A, 1.0, dev(u, dt), -0.5, dev(u, dt),
+                                            out_dtype=torch.float64 if prec == "f32" else None)))
+        # every policy of one block shape bitwise; the two shapes bitwise on
+        # rows of at most 512 nonzeros and to rounding on longer ones
+        for i in (1, 2, 4, 5):
+            ref = outs[0] if i < 3 else outs[3]
+            for a, b in zip(ref, outs[i]):
                 assert torch.equal(a, b)
+        for a, b in zip(outs[0], outs[3]):
+            assert torch.equal(a[short], b[short])
+            eps = 2.0 ** -52 if dt == torch.float64 else 2.0 ** -23
+            assert torch.all((a - b).abs() <= 64 * eps * (a.abs() + b.abs() + 1))
+        A.set_spmv_blocks(2048, prec)
     S = csr.to_scipy()
     ref = 0.5 * x - 2.0 * (S @ u) + 1.5 * z - 0.25 * z2
     nnzr = max(1, int(np.diff(csr.rowptr).max()))
@@ -53,6 +66,23 @@ def test_policies_bitwise_equal(lib, name):
     A.set_cache_policy("keep", "f64")
     y = host(lib.fused_spmv(A, 0.5, dev(x), -2.0, dev(u), 1.5, dev(z), -0.25, dev(z2)))
     assert np.all(np.abs(y - ref) <= (nnzr + 5) * EPS64 * scale)
+
+
+def test_tuned_shape_c3_fp32_and_c2(lib):
+    """The shape and policy the setup timing picked give the same bits as
+    the defaults (large blocks, streaming loads) on the benchmark's 2-D
+    operator and on a 3-D operator in FP32."""
+    for csr, prec, dt in ((W.convdiff_2d(1000, 0.5), "f64", torch.float64),
+                          (W.convdiff_3d(100, 0.3), "f32", torch.float32)):
+        A = lib.Matrix(csr, want_f32=(prec == "f32"))
+        assert A.spmv_blocks(prec) in (512, 2048)
+        rng = np.random.default_rng(9)
+        u = dev(rng.standard_normal(csr.n), dt)
+        y1 = lib.fused_spmv(A, 1.0, u, -0.5, u)
+        A.set_spmv_blocks(2048, prec)
+        A.set_cache_policy("stream", prec)
+        y0 = lib.fused_spmv(A, 1.0, u, -0.5, u)
+        assert torch.equal(y0, y1)
 
 
 def test_default_policy_and_errors(lib):
@@ -65,6 +95,9 @@ def test_default_policy_and_errors(lib):
         A.set_cache_policy("keep", "f32")
     with pytest.raises(ValueError):
         A.set_cache_policy("bogus", "f64")
+    assert A.spmv_blocks("f64") == 2048
+    with pytest.raises(RuntimeError):
+        A.set_spmv_blocks(1000, "f64")
 
 
 def test_tuned_policy_full_size_bitwise(lib):
