@@ -375,6 +375,8 @@ def main():
                     help="override the SpMV block shape (nonzeros per block) the matrix setup chose")
     ap.add_argument("--table-d0-cycles", type=int, default=1500,
                     help="restart cycles allowed to standard Arnoldi in the Table 8.1 block")
+    ap.add_argument("--precision", default="auto", choices=("auto", "f64", "mixed"),
+                    help="run the workload's solve in this precision instead of its own (profiling)")
     ap.add_argument("--lowsync", action="store_true",
                     help="headline solve with the delayed-reorthogonalisation Gram-Schmidt")
     ap.add_argument("--headline-only", action="store_true",
@@ -395,7 +397,7 @@ def main():
     cfg = CONFIGS[args.config]
     csr = make_matrix(cfg)
     b, v0 = W.start_vectors(csr.n, cfg["seed"])
-    prec = cfg["precision"]
+    prec = cfg["precision"] if args.precision == "auto" else args.precision
     A = ppa.Matrix(csr, want_f32=(prec != "f64"))
     if args.cache_policy != "auto":
         A.set_cache_policy(args.cache_policy, "f32" if prec == "mixed" else "f64")
@@ -459,7 +461,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == "f64" else "f32 pi(A)v + f64",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "n": csr.n, "nnz": csr.nnz, "max_cycles": args.max_cycles,
+        "config": {"workload": cfg["desc"] if args.precision == "auto" else
+                   cfg["desc"].rsplit(", ", 1)[0] + (", FP64" if prec == "f64" else ", mixed"),
+                   "n": csr.n, "nnz": csr.nnz, "max_cycles": args.max_cycles,
+                   "precision": prec,
                    "gram_schmidt": "delayed reorthogonalisation" if args.lowsync else "cgs2"},
         "eigenpairs_per_s": round(nconv / wall, 4),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
@@ -473,6 +478,7 @@ def main():
                   "mu_head": [[round(z.real, 10), round(z.imag, 10)] for z in results[-1].mu[:4]],
                   "fp32_cycles": results[-1].fp32_cycles},
         "roofline": {"kernel": "k_fused_spmv", "bound": "hbm",
+                     "spmv_variant": A.spmv_variant("f32" if prec == "mixed" else "f64"),
                      "cache_policy": policy, "nnz_per_block": blocks,
                      "achieved": round(kern_gbs, 1) if kern_gbs else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4) if kern_gbs else None,

@@ -80,14 +80,17 @@ const char* ppa_last_error(void);
  * computes ||A||_inf, and builds the row-block partitions used by the SpMV
  * kernels (allocated by the library, freed by ppa_matrix_destroy).  For large
  * matrices (n >= 200000, nnz >= 10^6) whose row blocks touch narrow column
- * ranges it also times the LDS-windowed SpMV against the plain one and keeps
- * the faster; both sum each row in column order, so they agree bitwise on
- * every row of at most 2048 nonzeros (longer rows are tree-reduced by the
- * plain kernel and agree to rounding).
+ * ranges it also times the LDS-windowed and sliding-window SpMVs against the
+ * plain one and keeps the fastest (a staged variant only for a 5% gain); all
+ * sum each row in column order, so they agree bitwise on every row of at
+ * most 2048 nonzeros (longer rows are tree-reduced by the plain kernel and
+ * agree to rounding).
  * ------------------------------------------------------------------------ */
 #define PPA_MATRIX_F32 1            /* build an FP32 copy of the values           */
 #define PPA_MATRIX_WINDOW_FORCE 2   /* use the windowed SpMV whenever it fits     */
-#define PPA_MATRIX_WINDOW_OFF 4     /* never use the windowed SpMV                */
+#define PPA_MATRIX_WINDOW_OFF 4     /* never use a windowed SpMV (either kind)    */
+#define PPA_MATRIX_RING_FORCE 8     /* use the sliding-window SpMV whenever it fits
+                                       (not with PPA_MATRIX_WINDOW_FORCE)         */
 int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
                       const double* val64_d, const float* val32_d, int flags,
                       void* stream, ppa_matrix** out);
@@ -96,7 +99,11 @@ int ppa_matrix_destroy(ppa_matrix* A);
 int ppa_matrix_info(const ppa_matrix* A, int64_t* n, int64_t* nnz, double* norm_inf,
                     int64_t* nblocks);
 /* SpMV variant in use for FP64 (precision PPA_F64) or FP32 (PPA_F32) values:
- * *windowed = 1 for the LDS-windowed kernel, 0 for the plain one. */
+ * *windowed = 0 for the plain kernel, 1 for the LDS-windowed one (each row
+ * block stages its column range of u in LDS), 2 for the sliding-window one
+ * (one persistent block per CU walks consecutive row chunks and keeps u in
+ * an LDS ring, loading only the columns each chunk adds; band matrices).
+ * All three sum each row in column order. */
 int ppa_matrix_spmv_variant(const ppa_matrix* A, int precision, int* windowed);
 
 /* Cache policy of the plain (non-windowed) SpMV kernel, per value precision

@@ -77,7 +77,12 @@ int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_
                 PPA_HIP(hipStreamSynchronize(s));
                 A->v32 = A->v32_owned;
             }
-            const int wmode = (flags & PPA_MATRIX_WINDOW_OFF) ? -1 : (flags & PPA_MATRIX_WINDOW_FORCE) ? 1 : 0;
+            PPA_REQUIRE(!((flags & PPA_MATRIX_WINDOW_FORCE) && (flags & PPA_MATRIX_RING_FORCE)),
+                        "PPA_MATRIX_WINDOW_FORCE and PPA_MATRIX_RING_FORCE exclude each other");
+            const int wmode = (flags & PPA_MATRIX_WINDOW_OFF)     ? -1
+                              : (flags & PPA_MATRIX_WINDOW_FORCE) ? 1
+                              : (flags & PPA_MATRIX_RING_FORCE)   ? 2
+                                                                  : 0;
             matrix_tune(*A, wmode, s);
             A->rp_host.clear();
             A->rp_host.shrink_to_fit();
@@ -118,7 +123,10 @@ int ppa_matrix_spmv_variant(const ppa_matrix* h, int precision, int* windowed) {
     return guarded([&] {
         PPA_REQUIRE(h && windowed, "matrix and windowed are required");
         const Matrix* A = reinterpret_cast<const Matrix*>(h);
-        *windowed = precision == PPA_F64 ? (A->win64.on ? 1 : 0) : (A->win32.on ? 1 : 0);
+        const bool f64 = precision == PPA_F64;
+        const Window& W = f64 ? A->win64 : A->win32;
+        const Ring& R = f64 ? A->ring64 : A->ring32;
+        *windowed = R.on ? 2 : W.on ? 1 : 0;
         return PPA_OK;
     });
 }

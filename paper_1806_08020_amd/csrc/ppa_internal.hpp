@@ -75,6 +75,45 @@ struct Window {
     size_t lds_bytes = 0;
 };
 
+// Sliding-window SpMV (band matrices): one persistent block per CU walks a
+// segment of consecutive row chunks and keeps u in an LDS ring of
+// SPMV_RING_F64 / SPMV_RING_F32 entries; each chunk only adds the columns
+// it reaches beyond the previous ones.  LDS per block: the ring and two
+// product buffers of one chunk, 160 KB in both precisions.
+#ifndef PPA_SPMV_RING_F64
+#define PPA_SPMV_RING_F64 12288
+#endif
+#ifndef PPA_SPMV_RING_F32
+#define PPA_SPMV_RING_F32 24576
+#endif
+#ifndef PPA_SPMV_RCHUNK_F64
+#define PPA_SPMV_RCHUNK_F64 4096
+#endif
+#ifndef PPA_SPMV_RCHUNK_F32
+#define PPA_SPMV_RCHUNK_F32 8192
+#endif
+#ifndef PPA_SPMV_RING_NEW
+#define PPA_SPMV_RING_NEW 1
+#endif
+#ifndef PPA_SPMV_RING_D
+#define PPA_SPMV_RING_D 3
+#endif
+constexpr int SPMV_RING_F64 = PPA_SPMV_RING_F64;      // ring entries, FP64 values (96 KB)
+constexpr int SPMV_RING_F32 = PPA_SPMV_RING_F32;      // ring entries, FP32 values (96 KB)
+constexpr int SPMV_RCHUNK_F64 = PPA_SPMV_RCHUNK_F64;  // nonzeros per chunk, FP64 values
+constexpr int SPMV_RCHUNK_F32 = PPA_SPMV_RCHUNK_F32;  // nonzeros per chunk, FP32 values
+constexpr int SPMV_RING_NEW = PPA_SPMV_RING_NEW;      // new ring columns per thread and chunk
+constexpr int SPMV_RING_D = PPA_SPMV_RING_D;          // chunks held in registers
+
+struct Ring {
+    bool on = false;
+    int4* rm = nullptr;              // device, per chunk {r0, r1, p0, p1}, {lo, hi, 0, 0}
+    int4* seg = nullptr;             // device, per segment {t0, t1, 0, 0}
+    int align = 1;
+    int64_t nchunks = 0, nseg = 0;
+    size_t lds_bytes = 0;
+};
+
 // Cache policies of the plain SpMV kernel (values match ppa.h's PPA_CACHE_*).
 enum { CP_STREAM = 0, CP_KEEP = 1, CP_KEEP_NTST = 2 };
 
@@ -95,6 +134,7 @@ struct Matrix {
     double norm_inf = 0.0;
     int device = 0;
     Window win64, win32;
+    Ring ring64, ring32;
     std::vector<int32_t> rp_host;    // host copy of rowptr (setup only)
 };
 

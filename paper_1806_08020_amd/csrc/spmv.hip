@@ -391,9 +391,238 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     }
 }
 
+// Sliding-window variant for band matrices.  Block s (one per CU) walks the
+// chunks [t0, t1) of its segment in order; a chunk is a row range of at most
+// CH nonzeros (aligned start as above) with the record {r0, r1, p0, p1},
+// {lo, hi, -, -}.  u is kept in an LDS ring of RW entries, column c at
+// position c mod RW; chunk t needs the columns [lo, hi) beyond those of the
+// chunks before it (the segment's first chunk: its whole range, loaded by a
+// loop; later chunks at most RN * SPMV_WBS columns).  One barrier per chunk:
+// between barriers k - 1 and k the block sums the rows of chunk k - 1 from
+// one product buffer, gathers chunk k into the other, and writes the ring
+// entries of chunk k + 1.  The setup accepts a matrix only if those writes
+// cannot touch a column chunk k gathers, i.e. every column of chunk k is at
+// least hi(k + 1) - RW.  Column indices, values, the new ring entries and
+// the first row's epilogue operands of the next chunks are held in registers
+// as loaded (no conversion or masking until use), so their memory latency
+// overlaps the work of the chunks before them.
+// Loaded values are kept as loaded (no conversion or masking until use), so
+// that nothing waits for them before the chunk that needs them.
+template <typename VT, typename IT, int NG, int G, int RN>
+struct RingSlot {
+    int r0, r1, p0, p1, lo, hi;
+    Grp<G, int32_t> c[NG];
+    Grp<G, VT> v[NG];
+    IT w[RN];
+    int a, e;
+    IT x, z, z2;
+};
+
+template <class F, int... I>
+__device__ __forceinline__ void ring_unroll_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void ring_unroll(F&& f) {
+    ring_unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Ring position of column c (c >= 0).
+template <int RW>
+__device__ __forceinline__ int ring_pos(int c) {
+    if constexpr ((RW & (RW - 1)) == 0)
+        return c & (RW - 1);
+    else
+        return (int)((unsigned)c % (unsigned)RW);
+}
+
+// Row sum in column order with eight LDS reads in flight; past the row's end
+// the reads repeat its last entry and add +0 instead (the running sum starts
+// at +0 and so is never -0: adding +0 leaves it unchanged), so the result is
+// bitwise that of row_out.
+template <typename VT, typename OT>
+__device__ __forceinline__ void row_out8(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
+                                         VT alpha, VT beta, VT gamma, VT delta) {
+    VT s = 0;
+    const int e = q.e - p0;
+    for (int k = q.a - p0; k < e; k += 8) {
+        VT a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = prod[min(k + i, e - 1)];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += k + i < e ? a[i] : (VT)0;
+    }
+    out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
+}
+
+// Row sum in column order with four LDS reads in flight (same order as
+// row_out, so the result is bitwise the same).
+template <typename VT, typename OT>
+__device__ __forceinline__ void row_out4(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
+                                         VT alpha, VT beta, VT gamma, VT delta) {
+    VT s = 0;
+    int k = q.a - p0;
+    const int e = q.e - p0;
+    for (; k + 4 <= e; k += 4) {
+        const VT a0 = prod[k], a1 = prod[k + 1], a2 = prod[k + 2], a3 = prod[k + 3];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
+    }
+    for (; k < e; ++k) s += prod[k];
+    out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
+}
+
+template <typename VT, typename IT, typename OT, int CH, int RW, int G, bool EPI>
+__global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const VT* __restrict__ val, const int4* __restrict__ rm, const int4* __restrict__ seg,
+    int nseg, int nnz, int n, const IT* __restrict__ x, const IT* __restrict__ u,
+    const IT* __restrict__ z, const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta,
+    VT gamma, VT delta) {
+    constexpr int PER = CH / SPMV_WBS;
+    static_assert(PER % G == 0, "groups must tile the per-thread share");
+    constexpr int NG = PER / G;
+    constexpr int RN = SPMV_RING_NEW;
+    constexpr int D = SPMV_RING_D;   // chunks in registers: summed, gathered, ring source, ...
+    static_assert(D >= 3, "a step uses three slots");
+    using Slot = RingSlot<VT, IT, NG, G, RN>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    VT* prod2 = reinterpret_cast<VT*>(smem);   // two product buffers of CH
+    VT* ring = prod2 + 2 * CH;
+    const int tid = threadIdx.x;
+    const int4 sg = seg[xcd_remap(blockIdx.x, nseg)];
+    const int t0 = sg.x, t1 = sg.y;
+    if (t0 >= t1) return;
+    // absent epilogue vectors are read through u and multiplied by nothing:
+    // every load of a slot is unconditional, so the compiler's wait for a
+    // slot counts the loads of the slots issued after it
+    const IT* xs = x ? x : u;
+    const IT* zs = z ? z : u;
+    const IT* z2s = z2 ? z2 : u;
+
+    // chunk t's operands into a slot; t past the segment re-reads its last chunk
+    auto load = [&](Slot& S, int t) {
+        t = min(t, t1 - 1);
+        const int4 m0 = rm[2 * t], m1 = rm[2 * t + 1];
+        S.r0 = m0.x;
+        S.r1 = m0.y;
+        S.p0 = m0.z;
+        S.p1 = m0.w;
+        S.lo = m1.x;
+        S.hi = m1.y;
+        const int base = S.p0 & ~(G - 1);
+        const int gmax = max((S.p1 - base - 1) / G, 0);
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int idx = base + G * min(tid + k * SPMV_WBS, gmax);
+            const bool full = idx + G <= nnz;
+            S.c[k] = load_grp<G, CP_STREAM>(colind, idx, full, nnz - 1);
+            S.v[k] = load_grp<G, CP_STREAM>(val, idx, full, nnz - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < RN; ++j) S.w[j] = u[min(S.lo + tid + j * SPMV_WBS, n - 1)];
+        const int r = min(S.r0 + tid, S.r1 - 1);
+        S.a = rowptr[r];
+        S.e = rowptr[r + 1];
+        S.x = xs[r];
+        if constexpr (EPI) {
+            S.z = zs[r];
+            S.z2 = z2s[r];
+        }
+    };
+    auto gather = [&](const Slot& C, VT* prod) {
+        const int base = C.p0 & ~(G - 1);
+        if (C.p1 > C.p0) {
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                const int pos = G * (tid + k * SPMV_WBS);
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int e = base + pos + j;
+                    const VT w = ring[ring_pos<RW>(C.c[k].v[j])];
+                    prod[pos + j] = (e >= C.p0 && e < C.p1) ? C.v[k].v[j] * w : (VT)0;
+                }
+            }
+        }
+    };
+    auto rowsum = [&](const Slot& C, const VT* prod_al) {
+        const VT* prod = prod_al + (C.p0 - (C.p0 & ~(G - 1)));
+        const int ra = C.r0 + tid;
+        if (ra < C.r1) {
+            RowPre<VT> q;
+            q.a = C.a;
+            q.e = C.e;
+            q.x = x ? (VT)C.x : (VT)0;
+            if constexpr (EPI) {
+                q.z = z ? (VT)C.z : (VT)0;
+                q.z2 = z2 ? (VT)C.z2 : (VT)0;
+            } else {
+                q.z = (VT)0;
+                q.z2 = (VT)0;
+            }
+            row_out8(q, prod, C.p0, ra, out, alpha, beta, gamma, delta);
+        }
+        for (int r = ra + SPMV_WBS; r < C.r1; r += SPMV_WBS) {
+            const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
+            row_out8(q, prod, C.p0, r, out, alpha, beta, gamma, delta);
+        }
+    };
+    auto ring_put = [&](const Slot& N) {
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+            const int col = N.lo + tid + j * SPMV_WBS;
+            if (col < N.hi) ring[ring_pos<RW>(col)] = (VT)N.w[j];
+        }
+    };
+    // chunk c lives in slot (c - t0) mod D and product buffer (c - t0) mod 2
+    Slot S[D];
+    // step k, k = t0 + 1 + i (mod D): sum chunk k - 1 (slot i), gather chunk k
+    // (slot i + 1) if it exists, write chunk k + 1's ring entries (slot i + 2)
+    // if it exists; then slot i takes chunk k - 1 + D
+    auto step = [&](auto ic, int k, bool full) {
+        constexpr int i = decltype(ic)::value;
+        rowsum(S[i], prod2 + ((k - 1 - t0) & 1) * CH);
+        if (full || k < t1) gather(S[(i + 1) % D], prod2 + ((k - t0) & 1) * CH);
+        if (full || k + 1 < t1) ring_put(S[(i + 2) % D]);
+        __syncthreads();
+        load(S[i], k - 1 + D);
+    };
+
+    {
+        // the first chunk's whole column range
+        const int4 m1 = rm[2 * t0 + 1];
+        for (int col = m1.x + tid; col < m1.y; col += SPMV_WBS) ring[ring_pos<RW>(col)] = (VT)u[col];
+    }
+    ring_unroll<D>([&](auto dc) { load(S[decltype(dc)::value], t0 + decltype(dc)::value); });
+    __syncthreads();
+    // step t0: gather the first chunk and write the second one's entries
+    gather(S[0], prod2);
+    if (t0 + 1 < t1) ring_put(S[1]);
+    __syncthreads();
+    // steps t0 + 1 .. t1: groups of D steps that all gather and write ring
+    // entries, then the rest (at most D + 1 steps) with the bounds checked
+    int k = t0 + 1;
+    for (; k + D < t1; k += D)
+        ring_unroll<D>([&](auto ic) { step(ic, k + decltype(ic)::value, true); });
+    for (; k <= t1; k += D)
+        ring_unroll<D>([&](auto ic) {
+            if (k + decltype(ic)::value <= t1) step(ic, k + decltype(ic)::value, false);
+        });
+}
+
 template <typename VT>
 constexpr int win_chunk() {
     return sizeof(VT) == 4 ? SPMV_WCHUNK_F32 : SPMV_WCHUNK_F64;
+}
+template <typename VT>
+constexpr int ring_chunk() {
+    return sizeof(VT) == 4 ? SPMV_RCHUNK_F32 : SPMV_RCHUNK_F64;
+}
+template <typename VT>
+constexpr int ring_size() {
+    return sizeof(VT) == 4 ? SPMV_RING_F32 : SPMV_RING_F64;
 }
 template <typename VT>
 constexpr int grp_width() {
@@ -401,14 +630,29 @@ constexpr int grp_width() {
 }
 
 template <typename VT, typename IT, typename OT>
-static void run_fused(const Matrix& A, const VT* val, const Window& W, double alpha, const void* x,
-                      double beta, const void* u, double gamma, const void* z, double delta,
-                      const void* z2, void* o, hipStream_t s) {
+static void run_fused(const Matrix& A, const VT* val, const Window& W, const Ring& R, double alpha,
+                      const void* x, double beta, const void* u, double gamma, const void* z,
+                      double delta, const void* z2, void* o, hipStream_t s) {
     if (A.nblocks == 0) return;
     constexpr int G = grp_width<VT>();
     const bool epi = z != nullptr || z2 != nullptr;
     const bool valg = reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
-    if (W.on && reinterpret_cast<uintptr_t>(u) % 16 == 0) {
+    if (R.on) {
+        constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>();
+        const bool grp = G > 1 && R.align % G == 0 && valg;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)R.nseg), dim3(SPMV_WBS), R.lds_bytes, s,
+                               A.rowptr, A.colind, val, R.rm, R.seg, (int)R.nseg, (int)A.nnz,
+                               (int)A.n, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o,
+                               (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+        };
+        if (grp)
+            epi ? go(k_fused_spmv_ring<VT, IT, OT, CH, RW, G, true>)
+                : go(k_fused_spmv_ring<VT, IT, OT, CH, RW, G, false>);
+        else
+            epi ? go(k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, true>)
+                : go(k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, false>);
+    } else if (W.on && reinterpret_cast<uintptr_t>(u) % 16 == 0) {
         constexpr int CH = win_chunk<VT>();
         const bool grp = G > 1 && W.align % G == 0 && valg;
         auto go = [&](auto kern) {
@@ -487,20 +731,21 @@ size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const
     PPA_REQUIRE(o != u, "fused spmv: out must not alias u");
     const size_t bytes = fused_spmv_bytes(A, in, out, x, u, z, z2);
     if (in == VecT::F64 && out == VecT::F64) {
-        run_fused<double, double, double>(A, A.v64, A.win64, alpha, x, beta, u, gamma, z, delta, z2,
-                                          o, s);
+        run_fused<double, double, double>(A, A.v64, A.win64, A.ring64, alpha, x, beta, u, gamma, z,
+                                          delta, z2, o, s);
         return bytes;
     }
     PPA_REQUIRE(A.v32 != nullptr, "FP32 path needs FP32 matrix values (want_f32 at create)");
     const Window& W = A.win32;
+    const Ring& R = A.ring32;
     if (in == VecT::F32 && out == VecT::F32)
-        run_fused<float, float, float>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, float, float>(A, A.v32, W, R, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else if (in == VecT::F64 && out == VecT::F32)
-        run_fused<float, double, float>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, double, float>(A, A.v32, W, R, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else if (in == VecT::F32 && out == VecT::F64)
-        run_fused<float, float, double>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, float, double>(A, A.v32, W, R, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     else
-        run_fused<float, double, double>(A, A.v32, W, alpha, x, beta, u, gamma, z, delta, z2, o, s);
+        run_fused<float, double, double>(A, A.v32, W, R, alpha, x, beta, u, gamma, z, delta, z2, o, s);
     return bytes;
 }
 
@@ -744,6 +989,128 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
     W.on = false;
 }
 
+// Allow the sliding-window kernel instances of one value type `bytes` of
+// dynamic LDS.
+template <typename VT, typename IT, typename OT>
+static bool allow_ring_one(int b) {
+    constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>(), G = grp_width<VT>();
+    bool ok = true;
+    for (const void* f : {(const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, G, true>,
+                          (const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, G, false>,
+                          (const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, true>,
+                          (const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, false>})
+        ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+    return ok;
+}
+static bool allow_ring_lds(size_t vbytes, size_t bytes) {
+    const int b = (int)bytes;
+    bool ok = true;
+    if (vbytes == 8) {
+        ok &= allow_ring_one<double, double, double>(b);
+    } else {
+        ok &= allow_ring_one<float, float, float>(b);
+        ok &= allow_ring_one<float, double, float>(b);
+        ok &= allow_ring_one<float, float, double>(b);
+        ok &= allow_ring_one<float, double, double>(b);
+    }
+    (void)hipGetLastError();
+    return ok;
+}
+
+// Sliding-window schedule for one value type: chunks of at most `chunk`
+// nonzeros, one segment of consecutive chunks per CU (balanced by nonzeros
+// plus rows), and for each chunk the column range it adds to the ring.  The
+// matrix qualifies only if every segment's first range fits the ring, every
+// later chunk adds at most SPMV_RING_NEW * SPMV_WBS columns, and no chunk
+// gathers a column that a later load has overwritten.  On success R holds
+// the device arrays but stays off until matrix_tune selects it.
+static void build_ring(Matrix& A, Ring& R, int chunk, int rw, size_t vbytes, hipStream_t s) {
+    if (A.nnz == 0) return;
+    bool lg = false;
+    std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, A.align, &lg);
+    if (lg) return;
+    const int64_t nb = (int64_t)blk.size() - 1;
+    int maxlds = 0, ncu = 0;
+    PPA_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, A.device));
+    PPA_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, A.device));
+    const size_t lds = (2 * (size_t)chunk + (size_t)rw) * vbytes;
+    if (lds > (size_t)maxlds || lds > (size_t)SPMV_WIN_LDS_MAX) return;
+    int32_t* dblk = nullptr;
+    int32_t* dmeta = nullptr;
+    PPA_HIP(hipMalloc(&dblk, blk.size() * sizeof(int32_t)));
+    PPA_HIP(hipMalloc(&dmeta, 2 * nb * sizeof(int32_t)));
+    PPA_HIP(hipMemcpyAsync(dblk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_block_span, dim3((unsigned)nb), dim3(256), 0, s, A.rowptr, A.colind, dblk, dmeta);
+    PPA_HIP(hipGetLastError());
+    std::vector<int32_t> meta(2 * nb);
+    PPA_HIP(hipMemcpyAsync(meta.data(), dmeta, meta.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    PPA_HIP(hipFree(dblk));
+    PPA_HIP(hipFree(dmeta));
+    const std::vector<int32_t>& rp = A.rp_host;
+    const int64_t nseg = std::min<int64_t>(nb, std::max(ncu, 1));
+    // segment g holds the chunks [sb[g], sb[g + 1])
+    std::vector<int32_t> sb(nseg + 1, 0);
+    const int64_t total = A.nnz + A.n;
+    int64_t t = 0;
+    for (int64_t g = 1; g < nseg; ++g) {
+        const int64_t target = total * g / nseg;
+        while (t < nb && (int64_t)rp[blk[t + 1]] + blk[t + 1] <= target) ++t;
+        sb[g] = (int32_t)t;
+    }
+    sb[nseg] = (int32_t)nb;
+    std::vector<int32_t> rec(8 * nb, 0);
+    const int64_t new_max = (int64_t)SPMV_RING_NEW * SPMV_WBS;
+    for (int64_t g = 0; g < nseg; ++g) {
+        const int32_t t0 = sb[g], t1 = sb[g + 1];
+        const int64_t none = (int64_t)1 << 62;
+        int64_t L = none;
+        for (int32_t c = t0; c < t1; ++c)
+            if (meta[2 * c + 1] > 0) L = std::min<int64_t>(L, meta[2 * c]);
+        if (L == none) L = 0;
+        int64_t H = L - 1;   // highest column loaded so far
+        for (int32_t c = t0; c < t1; ++c) {
+            const int64_t cmin = meta[2 * c], span = meta[2 * c + 1];
+            const int64_t lo = c == t0 ? L : H + 1;
+            if (span > 0) H = std::max(H, cmin + span - 1);
+            const int64_t hi = H + 1;
+            if (hi - lo > (c == t0 ? (int64_t)rw : new_max)) return;
+            // the next chunk's entries are written while this one gathers
+            int64_t hn = hi;
+            if (c + 1 < t1 && meta[2 * (c + 1) + 1] > 0)
+                hn = std::max(hi, (int64_t)meta[2 * (c + 1)] + meta[2 * (c + 1) + 1]);
+            if (span > 0 && cmin < hn - rw) return;
+            int32_t* q = &rec[8 * c];
+            q[0] = blk[c];
+            q[1] = blk[c + 1];
+            q[2] = rp[blk[c]];
+            q[3] = rp[blk[c + 1]];
+            q[4] = (int32_t)lo;
+            q[5] = (int32_t)hi;
+        }
+    }
+    if (!allow_ring_lds(vbytes, lds)) return;
+    std::vector<int32_t> srec(4 * nseg, 0);
+    for (int64_t g = 0; g < nseg; ++g) {
+        srec[4 * g] = sb[g];
+        srec[4 * g + 1] = sb[g + 1];
+    }
+    int4* drm = nullptr;
+    int4* dseg = nullptr;
+    PPA_HIP(hipMalloc(&drm, rec.size() * sizeof(int32_t)));
+    PPA_HIP(hipMalloc(&dseg, srec.size() * sizeof(int32_t)));
+    PPA_HIP(hipMemcpyAsync(drm, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PPA_HIP(hipMemcpyAsync(dseg, srec.data(), srec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    R.rm = drm;
+    R.seg = dseg;
+    R.align = A.align;
+    R.nchunks = nb;
+    R.nseg = nseg;
+    R.lds_bytes = lds;
+    R.on = false;
+}
+
 void matrix_setup(Matrix& A, hipStream_t s) {
     const int64_t n = A.n;
     std::vector<int32_t>& rp = A.rp_host;
@@ -857,19 +1224,33 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
     // it, the windowed kernel against the plain one.  Short timings alternate the candidates
     // over three trials after a warm-up and compare the best trials: a single
     // timing favours whichever variant runs second on warm caches.
-    if (A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
-        if (mode == 1 && A.nnz > 0) {
+    auto build_all = [&](bool win, bool ring) {
+        if (win) {
             build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
             if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
+        }
+        if (ring) {
+            build_ring(A, A.ring64, SPMV_RCHUNK_F64, SPMV_RING_F64, sizeof(double), s);
+            if (A.v32) build_ring(A, A.ring32, SPMV_RCHUNK_F32, SPMV_RING_F32, sizeof(float), s);
+        }
+    };
+    auto force = [&]() {
+        if (mode == 1) {
             A.win64.on = A.win64.bm != nullptr;
             A.win32.on = A.win32.bm != nullptr;
+        } else if (mode == 2) {
+            A.ring64.on = A.ring64.rm != nullptr;
+            A.ring32.on = A.ring32.rm != nullptr;
+        }
+    };
+    if (A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
+        if (mode >= 1 && A.nnz > 0) {
+            build_all(mode == 1, mode == 2);
+            force();
         }
         return;
     }
-    if (mode >= 0) {
-        build_window(A, A.win64, SPMV_WCHUNK_F64, sizeof(double), s);
-        if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
-    }
+    if (mode >= 0) build_all(mode <= 1, mode == 0 || mode == 2);
     double* u = nullptr;
     double* y = nullptr;
     // u: the FP64 test vector; y: output (FP64) or, for FP32, an FP32 copy of
@@ -882,6 +1263,7 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
         const bool f32 = pass == 1;
         if (f32 && !A.v32) continue;
         Window& W = f32 ? A.win32 : A.win64;
+        Ring& R = f32 ? A.ring32 : A.ring64;
         int& cp = f32 ? A.cp32 : A.cp64;
         void* uu = u;
         if (f32) launch_cast_f64_f32(u, (float*)y, A.n, s), uu = y;   // FP32 copy of the ramp
@@ -889,6 +1271,7 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
         int& blk = f32 ? A.blk32 : A.blk64;
         const bool won = W.on;
         W.on = false;
+        R.on = false;
         const int cp0 = cp;
         // candidates: cache policy c (0..2) with block shape b (0 large, 1 small)
         float tc[6] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
@@ -906,31 +1289,33 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
         cp = c_keep % 3;
         blk = c_keep / 3;
         W.on = won;
-        if (mode != 0 || !W.bm) continue;
-        float t_plain = 1e30f, t_win = 1e30f;
-        bool win_ok = true;
-        for (int trial = 0; trial < 4 && win_ok; ++trial) {
-            W.on = false;
-            const float tp = time_passes(A, f32, uu, yy, 8, s);
-            W.on = true;
-            float tw = 0.f;
-            try {
-                tw = time_passes(A, f32, uu, yy, 8, s);
-            } catch (const Error&) {
-                (void)hipGetLastError();
-                win_ok = false;
-                break;
+        if (mode != 0 || (!W.bm && !R.rm)) continue;
+        // plain (0), windowed (1), sliding window (2): best trial of each
+        float tv[3] = {1e30f, 1e30f, 1e30f};
+        bool ok[3] = {true, W.bm != nullptr, R.rm != nullptr};
+        for (int trial = 0; trial < 4; ++trial)
+            for (int v = 0; v < 3; ++v) {
+                if (!ok[v]) continue;
+                W.on = v == 1;
+                R.on = v == 2;
+                float tm = 0.f;
+                try {
+                    tm = time_passes(A, f32, uu, yy, 8, s);
+                } catch (const Error&) {
+                    (void)hipGetLastError();
+                    ok[v] = false;
+                    continue;
+                }
+                if (trial > 0) tv[v] = std::min(tv[v], tm);   // trial 0: warm-up
             }
-            if (trial == 0) continue;   // warm-up
-            t_plain = std::min(t_plain, tp);
-            t_win = std::min(t_win, tw);
-        }
-        W.on = win_ok && t_win < 0.95f * t_plain;
+        // a staged variant replaces the plain kernel only for a clear gain
+        int best = 0;
+        for (int v = 1; v < 3; ++v)
+            if (ok[v] && tv[v] < 0.95f * tv[0] && tv[v] < tv[best]) best = v;
+        W.on = best == 1;
+        R.on = best == 2;
     }
-    if (mode == 1) {
-        A.win64.on = A.win64.bm != nullptr;
-        A.win32.on = A.win32.bm != nullptr;
-    }
+    force();
     PPA_HIP(hipStreamSynchronize(s));
     PPA_HIP(hipFree(u));
     PPA_HIP(hipFree(y));
@@ -944,6 +1329,12 @@ void matrix_release(Matrix& A) {
     for (Window* W : {&A.win64, &A.win32}) {
         if (W->bm) (void)hipFree(W->bm);
         W->bm = nullptr;
+    }
+    for (Ring* R : {&A.ring64, &A.ring32}) {
+        if (R->rm) (void)hipFree(R->rm);
+        if (R->seg) (void)hipFree(R->seg);
+        R->rm = nullptr;
+        R->seg = nullptr;
     }
     A.bm = nullptr;
     A.v32_owned = nullptr;

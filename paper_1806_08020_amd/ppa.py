@@ -23,7 +23,7 @@ PPA_WARN_NOT_CONVERGED = 2
 PPA_WARN_BREAKDOWN = 3
 PPA_ERR_INVALID, PPA_ERR_HIP, PPA_ERR_WORKSPACE, PPA_ERR_NONFINITE = -1, -2, -3, -4
 PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
-PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF = 1, 2, 4
+PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF, PPA_MATRIX_RING_FORCE = 1, 2, 4, 8
 _PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
 
 vp = C.c_void_p
@@ -160,8 +160,9 @@ class Matrix:
     the device copies are owned by this object and borrowed by the handle."""
 
     def __init__(self, csr, want_f32: bool = False, window: str = "auto"):
-        """window: "auto" (time both SpMV variants on large matrices),
-        "force" (windowed whenever it fits) or "off"."""
+        """window: "auto" (time the SpMV variants on large matrices),
+        "force" (LDS-windowed whenever it fits), "ring" (sliding window
+        whenever it fits) or "off" (plain kernel only)."""
         dev = torch.device("cuda")
         self.n = int(csr.n)
         self.rowptr = torch.as_tensor(np.asarray(csr.rowptr, dtype=np.int32)).to(dev)
@@ -172,7 +173,8 @@ class Matrix:
             self.vals = torch.zeros(1, dtype=torch.float64, device=dev)
         self.vals32 = self.vals.float() if want_f32 else None
         h = vp()
-        flags = {"auto": 0, "force": PPA_MATRIX_WINDOW_FORCE, "off": PPA_MATRIX_WINDOW_OFF}[window]
+        flags = {"auto": 0, "force": PPA_MATRIX_WINDOW_FORCE, "ring": PPA_MATRIX_RING_FORCE,
+                 "off": PPA_MATRIX_WINDOW_OFF}[window]
         _check(_lib.ppa_matrix_create(self.n, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.vals),
                                       _ptr(self.vals32), flags, _stream(), C.byref(h)))
         self.h = h
@@ -185,9 +187,17 @@ class Matrix:
         return self.vals32 is not None
 
     def windowed(self, precision: str = "f64") -> bool:
+        """True when either LDS-staged SpMV variant is in use."""
+        return self.spmv_variant(precision) != "plain"
+
+    SPMV_VARIANTS = ("plain", "window", "ring")
+
+    def spmv_variant(self, precision: str = "f64") -> str:
+        """SpMV kernel in use: "plain", "window" (per-block LDS window) or
+        "ring" (sliding window)."""
         w = C.c_int()
         _check(_lib.ppa_matrix_spmv_variant(self.h, _PREC[precision], C.byref(w)))
-        return bool(w.value)
+        return self.SPMV_VARIANTS[w.value]
 
     CACHE_POLICIES = ("stream", "keep", "keep_ntst")
 
