@@ -112,11 +112,30 @@ __device__ __forceinline__ RowPre<VT> row_pre(const int32_t* __restrict__ rowptr
     return q;
 }
 
+// Row sum in column order, PPA_SPMV_ROWSUM LDS reads in flight at a time;
+// past the row's end the reads repeat its last entry and add +0 instead (the
+// running sum starts at +0 and so is never -0: adding +0 leaves it
+// unchanged), so the result does not depend on the batch width.
+#ifndef PPA_SPMV_ROWSUM
+#define PPA_SPMV_ROWSUM 8
+#endif
 template <int CP, typename VT, typename OT>
 __device__ __forceinline__ void row_out(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
                                         VT alpha, VT beta, VT gamma, VT delta) {
+    constexpr int W = PPA_SPMV_ROWSUM;
     VT s = 0;
-    for (int k = q.a - p0; k < q.e - p0; ++k) s += prod[k];
+    const int e = q.e - p0;
+    if constexpr (W <= 1) {
+        for (int k = q.a - p0; k < e; ++k) s += prod[k];
+    } else {
+        for (int k = q.a - p0; k < e; k += W) {
+            VT a[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) a[i] = prod[min(k + i, e - 1)];
+#pragma unroll
+            for (int i = 0; i < W; ++i) s += k + i < e ? a[i] : (VT)0;
+        }
+    }
     out_store<CP>(out + r, (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2));
 }
 
@@ -436,44 +455,6 @@ __device__ __forceinline__ int ring_pos(int c) {
         return (int)((unsigned)c % (unsigned)RW);
 }
 
-// Row sum in column order with eight LDS reads in flight; past the row's end
-// the reads repeat its last entry and add +0 instead (the running sum starts
-// at +0 and so is never -0: adding +0 leaves it unchanged), so the result is
-// bitwise that of row_out.
-template <typename VT, typename OT>
-__device__ __forceinline__ void row_out8(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
-                                         VT alpha, VT beta, VT gamma, VT delta) {
-    VT s = 0;
-    const int e = q.e - p0;
-    for (int k = q.a - p0; k < e; k += 8) {
-        VT a[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = prod[min(k + i, e - 1)];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) s += k + i < e ? a[i] : (VT)0;
-    }
-    out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
-}
-
-// Row sum in column order with four LDS reads in flight (same order as
-// row_out, so the result is bitwise the same).
-template <typename VT, typename OT>
-__device__ __forceinline__ void row_out4(const RowPre<VT>& q, const VT* prod, int p0, int r, OT* out,
-                                         VT alpha, VT beta, VT gamma, VT delta) {
-    VT s = 0;
-    int k = q.a - p0;
-    const int e = q.e - p0;
-    for (; k + 4 <= e; k += 4) {
-        const VT a0 = prod[k], a1 = prod[k + 1], a2 = prod[k + 2], a3 = prod[k + 3];
-        s += a0;
-        s += a1;
-        s += a2;
-        s += a3;
-    }
-    for (; k < e; ++k) s += prod[k];
-    out[r] = (OT)(beta * s + alpha * q.x + gamma * q.z + delta * q.z2);
-}
-
 template <typename VT, typename IT, typename OT, int CH, int RW, int G, bool EPI>
 __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
@@ -562,11 +543,11 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
                 q.z = (VT)0;
                 q.z2 = (VT)0;
             }
-            row_out8(q, prod, C.p0, ra, out, alpha, beta, gamma, delta);
+            row_out<CP_KEEP>(q, prod, C.p0, ra, out, alpha, beta, gamma, delta);
         }
         for (int r = ra + SPMV_WBS; r < C.r1; r += SPMV_WBS) {
             const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
-            row_out8(q, prod, C.p0, r, out, alpha, beta, gamma, delta);
+            row_out<CP_KEEP>(q, prod, C.p0, r, out, alpha, beta, gamma, delta);
         }
     };
     auto ring_put = [&](const Slot& N) {
