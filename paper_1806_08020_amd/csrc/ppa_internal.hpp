@@ -92,6 +92,18 @@ struct Window {
 #ifndef PPA_SPMV_RCHUNK_F32
 #define PPA_SPMV_RCHUNK_F32 8192
 #endif
+#ifndef PPA_SPMV_RBS_F64
+#define PPA_SPMV_RBS_F64 1024
+#endif
+#ifndef PPA_SPMV_RBS_F32
+#define PPA_SPMV_RBS_F32 1024
+#endif
+#ifndef PPA_SPMV_RPERCU_F64
+#define PPA_SPMV_RPERCU_F64 1
+#endif
+#ifndef PPA_SPMV_RPERCU_F32
+#define PPA_SPMV_RPERCU_F32 1
+#endif
 #ifndef PPA_SPMV_RING_NEW
 #define PPA_SPMV_RING_NEW 1
 #endif
@@ -102,6 +114,10 @@ constexpr int SPMV_RING_F64 = PPA_SPMV_RING_F64;      // ring entries, FP64 valu
 constexpr int SPMV_RING_F32 = PPA_SPMV_RING_F32;      // ring entries, FP32 values (96 KB)
 constexpr int SPMV_RCHUNK_F64 = PPA_SPMV_RCHUNK_F64;  // nonzeros per chunk, FP64 values
 constexpr int SPMV_RCHUNK_F32 = PPA_SPMV_RCHUNK_F32;  // nonzeros per chunk, FP32 values
+constexpr int SPMV_RBS_F64 = PPA_SPMV_RBS_F64;        // threads per block, FP64 values
+constexpr int SPMV_RBS_F32 = PPA_SPMV_RBS_F32;        // threads per block, FP32 values
+constexpr int SPMV_RPERCU_F64 = PPA_SPMV_RPERCU_F64;  // blocks (segments) per CU, FP64 values
+constexpr int SPMV_RPERCU_F32 = PPA_SPMV_RPERCU_F32;  // blocks (segments) per CU, FP32 values
 constexpr int SPMV_RING_NEW = PPA_SPMV_RING_NEW;      // new ring columns per thread and chunk
 constexpr int SPMV_RING_D = PPA_SPMV_RING_D;          // chunks held in registers
 

@@ -455,14 +455,14 @@ __device__ __forceinline__ int ring_pos(int c) {
         return (int)((unsigned)c % (unsigned)RW);
 }
 
-template <typename VT, typename IT, typename OT, int CH, int RW, int G, bool EPI>
-__global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
+template <typename VT, typename IT, typename OT, int BS, int CH, int RW, int G, bool EPI>
+__global__ __launch_bounds__(BS) void k_fused_spmv_ring(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
     const VT* __restrict__ val, const int4* __restrict__ rm, const int4* __restrict__ seg,
     int nseg, int nnz, int n, const IT* __restrict__ x, const IT* __restrict__ u,
     const IT* __restrict__ z, const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta,
     VT gamma, VT delta) {
-    constexpr int PER = CH / SPMV_WBS;
+    constexpr int PER = CH / BS;
     static_assert(PER % G == 0, "groups must tile the per-thread share");
     constexpr int NG = PER / G;
     constexpr int RN = SPMV_RING_NEW;
@@ -497,13 +497,13 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
         const int gmax = max((S.p1 - base - 1) / G, 0);
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
-            const int idx = base + G * min(tid + k * SPMV_WBS, gmax);
+            const int idx = base + G * min(tid + k * BS, gmax);
             const bool full = idx + G <= nnz;
             S.c[k] = load_grp<G, CP_STREAM>(colind, idx, full, nnz - 1);
             S.v[k] = load_grp<G, CP_STREAM>(val, idx, full, nnz - 1);
         }
 #pragma unroll
-        for (int j = 0; j < RN; ++j) S.w[j] = u[min(S.lo + tid + j * SPMV_WBS, n - 1)];
+        for (int j = 0; j < RN; ++j) S.w[j] = u[min(S.lo + tid + j * BS, n - 1)];
         const int r = min(S.r0 + tid, S.r1 - 1);
         S.a = rowptr[r];
         S.e = rowptr[r + 1];
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
         if (C.p1 > C.p0) {
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
-                const int pos = G * (tid + k * SPMV_WBS);
+                const int pos = G * (tid + k * BS);
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
                     const int e = base + pos + j;
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
             }
             row_out<CP_KEEP>(q, prod, C.p0, ra, out, alpha, beta, gamma, delta);
         }
-        for (int r = ra + SPMV_WBS; r < C.r1; r += SPMV_WBS) {
+        for (int r = ra + BS; r < C.r1; r += BS) {
             const RowPre<VT> q = row_pre<VT, EPI>(rowptr, r, x, z, z2);
             row_out<CP_KEEP>(q, prod, C.p0, r, out, alpha, beta, gamma, delta);
         }
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
     auto ring_put = [&](const Slot& N) {
 #pragma unroll
         for (int j = 0; j < RN; ++j) {
-            const int col = N.lo + tid + j * SPMV_WBS;
+            const int col = N.lo + tid + j * BS;
             if (col < N.hi) ring[ring_pos<RW>(col)] = (VT)N.w[j];
         }
     };
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_ring(
     {
         // the first chunk's whole column range
         const int4 m1 = rm[2 * t0 + 1];
-        for (int col = m1.x + tid; col < m1.y; col += SPMV_WBS) ring[ring_pos<RW>(col)] = (VT)u[col];
+        for (int col = m1.x + tid; col < m1.y; col += BS) ring[ring_pos<RW>(col)] = (VT)u[col];
     }
     ring_unroll<D>([&](auto dc) { load(S[decltype(dc)::value], t0 + decltype(dc)::value); });
     __syncthreads();
@@ -606,6 +606,10 @@ constexpr int ring_size() {
     return sizeof(VT) == 4 ? SPMV_RING_F32 : SPMV_RING_F64;
 }
 template <typename VT>
+constexpr int ring_threads() {
+    return sizeof(VT) == 4 ? SPMV_RBS_F32 : SPMV_RBS_F64;
+}
+template <typename VT>
 constexpr int grp_width() {
     return sizeof(VT) == 8 ? PPA_SPMV_G64 : PPA_SPMV_G32;
 }
@@ -619,20 +623,20 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, const Rin
     const bool epi = z != nullptr || z2 != nullptr;
     const bool valg = reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
     if (R.on) {
-        constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>();
+        constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>(), BS = ring_threads<VT>();
         const bool grp = G > 1 && R.align % G == 0 && valg;
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)R.nseg), dim3(SPMV_WBS), R.lds_bytes, s,
+            hipLaunchKernelGGL(kern, dim3((unsigned)R.nseg), dim3(BS), R.lds_bytes, s,
                                A.rowptr, A.colind, val, R.rm, R.seg, (int)R.nseg, (int)A.nnz,
                                (int)A.n, (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o,
                                (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
         };
         if (grp)
-            epi ? go(k_fused_spmv_ring<VT, IT, OT, CH, RW, G, true>)
-                : go(k_fused_spmv_ring<VT, IT, OT, CH, RW, G, false>);
+            epi ? go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, true>)
+                : go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, false>);
         else
-            epi ? go(k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, true>)
-                : go(k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, false>);
+            epi ? go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, 1, true>)
+                : go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, 1, false>);
     } else if (W.on && reinterpret_cast<uintptr_t>(u) % 16 == 0) {
         constexpr int CH = win_chunk<VT>();
         const bool grp = G > 1 && W.align % G == 0 && valg;
@@ -975,11 +979,12 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
 template <typename VT, typename IT, typename OT>
 static bool allow_ring_one(int b) {
     constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>(), G = grp_width<VT>();
+    constexpr int BS = ring_threads<VT>();
     bool ok = true;
-    for (const void* f : {(const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, G, true>,
-                          (const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, G, false>,
-                          (const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, true>,
-                          (const void*)k_fused_spmv_ring<VT, IT, OT, CH, RW, 1, false>})
+    for (const void* f : {(const void*)k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, true>,
+                          (const void*)k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, false>,
+                          (const void*)k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, 1, true>,
+                          (const void*)k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, 1, false>})
         ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
     return ok;
 }
@@ -999,13 +1004,15 @@ static bool allow_ring_lds(size_t vbytes, size_t bytes) {
 }
 
 // Sliding-window schedule for one value type: chunks of at most `chunk`
-// nonzeros, one segment of consecutive chunks per CU (balanced by nonzeros
-// plus rows), and for each chunk the column range it adds to the ring.  The
-// matrix qualifies only if every segment's first range fits the ring, every
-// later chunk adds at most SPMV_RING_NEW * SPMV_WBS columns, and no chunk
+// nonzeros, `per_cu` segments of consecutive chunks per CU (balanced by
+// nonzeros plus rows; one block of `bs` threads each), and for each chunk the
+// column range it adds to the ring.  The matrix qualifies only if every
+// segment's first range fits the ring, every later chunk adds at most
+// SPMV_RING_NEW * bs columns, and no chunk
 // gathers a column that a later load has overwritten.  On success R holds
 // the device arrays but stays off until matrix_tune selects it.
-static void build_ring(Matrix& A, Ring& R, int chunk, int rw, size_t vbytes, hipStream_t s) {
+static void build_ring(Matrix& A, Ring& R, int chunk, int rw, int bs, int per_cu, size_t vbytes,
+                       hipStream_t s) {
     if (A.nnz == 0) return;
     bool lg = false;
     std::vector<int32_t> blk = partition(A.rp_host, A.n, chunk, SPMV_WBS * 4, A.align, &lg);
@@ -1029,7 +1036,7 @@ static void build_ring(Matrix& A, Ring& R, int chunk, int rw, size_t vbytes, hip
     PPA_HIP(hipFree(dblk));
     PPA_HIP(hipFree(dmeta));
     const std::vector<int32_t>& rp = A.rp_host;
-    const int64_t nseg = std::min<int64_t>(nb, std::max(ncu, 1));
+    const int64_t nseg = std::min<int64_t>(nb, (int64_t)std::max(ncu, 1) * per_cu);
     // segment g holds the chunks [sb[g], sb[g + 1])
     std::vector<int32_t> sb(nseg + 1, 0);
     const int64_t total = A.nnz + A.n;
@@ -1041,7 +1048,7 @@ static void build_ring(Matrix& A, Ring& R, int chunk, int rw, size_t vbytes, hip
     }
     sb[nseg] = (int32_t)nb;
     std::vector<int32_t> rec(8 * nb, 0);
-    const int64_t new_max = (int64_t)SPMV_RING_NEW * SPMV_WBS;
+    const int64_t new_max = (int64_t)SPMV_RING_NEW * bs;
     for (int64_t g = 0; g < nseg; ++g) {
         const int32_t t0 = sb[g], t1 = sb[g + 1];
         const int64_t none = (int64_t)1 << 62;
@@ -1211,8 +1218,11 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
             if (A.v32) build_window(A, A.win32, SPMV_WCHUNK_F32, sizeof(float), s);
         }
         if (ring) {
-            build_ring(A, A.ring64, SPMV_RCHUNK_F64, SPMV_RING_F64, sizeof(double), s);
-            if (A.v32) build_ring(A, A.ring32, SPMV_RCHUNK_F32, SPMV_RING_F32, sizeof(float), s);
+            build_ring(A, A.ring64, SPMV_RCHUNK_F64, SPMV_RING_F64, SPMV_RBS_F64, SPMV_RPERCU_F64,
+                       sizeof(double), s);
+            if (A.v32)
+                build_ring(A, A.ring32, SPMV_RCHUNK_F32, SPMV_RING_F32, SPMV_RBS_F32, SPMV_RPERCU_F32,
+                           sizeof(float), s);
         }
     };
     auto force = [&]() {
