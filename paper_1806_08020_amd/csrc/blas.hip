@@ -278,12 +278,45 @@ __global__ void k_cgs_finalize(const double* __restrict__ h1, const double* __re
     }
 }
 
-__global__ void k_scale(const double* __restrict__ in, double* __restrict__ out, int64_t n,
-                        const double* __restrict__ sc) {
-    const double s = *sc;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = in[i] * s;
+// k_reduce_cols on the one column of ||w_out||^2 partials, k_cgs_finalize
+// and v_next = w_out * scal[2] in one launch: every block sums the partials
+// in k_reduce_cols' order (so all blocks, and the separate launches, get the
+// same bits), block 0 writes the Hessenberg column and scal, and each block
+// scales its share of w_out into v_next.
+__global__ __launch_bounds__(BS) void k_finalize_scale(const double* __restrict__ partial, int nb,
+                                                       const double* __restrict__ h1,
+                                                       const double* __restrict__ h2, int j,
+                                                       double* __restrict__ scal,
+                                                       double* __restrict__ Hcol, double tol,
+                                                       const double* __restrict__ w_out,
+                                                       double* __restrict__ v_next, int64_t n) {
+    __shared__ double red[NW];
+    __shared__ double inv_s;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) s += partial[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += red[q];
+        const double beta = sqrt(t);
+        const double w0 = sqrt(h1[j]);
+        const double inv = (beta > tol * w0 && beta > 0.0) ? 1.0 / beta : 0.0;
+        inv_s = inv;
+        if (blockIdx.x == 0) {
+            scal[0] = h1[j];
+            scal[1] = t;
+            scal[2] = inv;
+            Hcol[j] = beta;
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < j; i += BS) Hcol[i] = h1[i] + h2[i];
+    __syncthreads();
+    const double inv = inv_s;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        v_next[i] = w_out[i] * inv;
 }
 
 // ---------------------------------------------------------------- delayed form
@@ -605,14 +638,17 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
     }
     // w_out = t - V h2 and ||w_out||^2
     update(n, j, V, ldv, ws.h2, ws.t, w_out, ws.partial, nb, s);
+    if (v_next) {
+        // reduction, Hessenberg column and v_next = w_out / beta in one launch
+        hipLaunchKernelGGL(k_finalize_scale, dim3(sgrid(n)), dim3(BS), 0, s, ws.partial, nb, ws.h1,
+                           ws.h2, j, ws.scal, Hcol_d, breakdown_tol, w_out, v_next, n);
+        PPA_HIP(hipGetLastError());
+        return;
+    }
     reduce_cols(ws.partial, nb, 1, ws.scal + 1, s);
     hipLaunchKernelGGL(k_cgs_finalize, dim3(1), dim3(256), 0, s, ws.h1, ws.h2, j, ws.scal, Hcol_d,
                        breakdown_tol);
     PPA_HIP(hipGetLastError());
-    if (v_next) {
-        hipLaunchKernelGGL(k_scale, dim3(sgrid(n)), dim3(256), 0, s, w_out, v_next, n, ws.scal + 2);
-        PPA_HIP(hipGetLastError());
-    }
 }
 
 void launch_dcgs_step(int kind, int64_t n, int jq, const double* V, int64_t ldv, const double* u,
