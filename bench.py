@@ -36,9 +36,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # shape (nonzeros per block): any change of that kernel makes the entry stale
 # and the field null.
 MEASURED_TRAFFIC = {
-    ("c2", "d04dd22016809fc5", "keep", 512): {"fetch_kib": 36655.08, "write_kib": 7812.74,
+    ("c2", "9f058091bdec7e59", "keep", 256): {"fetch_kib": 36809.45, "write_kib": 7812.65,
                                              "fetch_factor": 2.0, "write_factor": 1.0},
-    ("c2", "d04dd22016809fc5", "keep", 2048): {"fetch_kib": 36547.28, "write_kib": 7817.42,
+    ("c2", "9f058091bdec7e59", "keep", 2048): {"fetch_kib": 36548.35, "write_kib": 7817.07,
                                               "fetch_factor": 2.0, "write_factor": 1.0},
 }
 
@@ -371,7 +371,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--cache-policy", default="auto", choices=("auto", "stream", "keep", "keep_ntst"),
                     help="override the SpMV cache policy the matrix setup chose (for counter runs)")
-    ap.add_argument("--spmv-blocks", default="auto", choices=("auto", "2048", "512"),
+    ap.add_argument("--spmv-blocks", default="auto", choices=("auto", "2048", "256"),
                     help="override the SpMV block shape (nonzeros per block) the matrix setup chose")
     ap.add_argument("--table-d0-cycles", type=int, default=1500,
                     help="restart cycles allowed to standard Arnoldi in the Table 8.1 block")

@@ -128,9 +128,9 @@ int ppa_matrix_cache_policy(const ppa_matrix* A, int precision, int* policy);
 int ppa_matrix_set_cache_policy(ppa_matrix* A, int precision, int policy);
 
 /* Block shape of the plain SpMV kernel, per value precision: *nnz_per_block
- * = 2048 (blocks of 256 threads, the default) or 512 (blocks of 128
+ * = 2048 (blocks of 256 threads, the default) or 256 (blocks of 64
  * threads).  Both sum each row in column order, so they agree bitwise on
- * rows of at most 512 nonzeros; longer rows are reduced across a block in
+ * rows of at most 256 nonzeros; longer rows are reduced across a block in
  * the small shape and agree to rounding.  ppa_matrix_create times both
  * shapes with the cache policies on large matrices and switches only for a
  * 3% gain; the setter overrides (PPA_ERR_INVALID for another value). */

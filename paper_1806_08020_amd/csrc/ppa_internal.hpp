@@ -39,9 +39,15 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 #endif
 constexpr int SPMV_BS = PPA_SPMV_BS;
 constexpr int SPMV_CHUNK = PPA_SPMV_CHUNK;
-// the plain kernel's second block shape: 128 threads, 512 nonzeros
-constexpr int SPMV_BS_S = 128;
-constexpr int SPMV_CHUNK_S = 512;
+// the plain kernel's second block shape: 64 threads, 256 nonzeros
+#ifndef PPA_SPMV_BS_S
+#define PPA_SPMV_BS_S 64
+#endif
+#ifndef PPA_SPMV_CHUNK_S
+#define PPA_SPMV_CHUNK_S 256
+#endif
+constexpr int SPMV_BS_S = PPA_SPMV_BS_S;
+constexpr int SPMV_CHUNK_S = PPA_SPMV_CHUNK_S;
 constexpr int SPMV_MAXROWS = PPA_SPMV_CHUNK;
 // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin.
 constexpr int NUM_XCD = 8;

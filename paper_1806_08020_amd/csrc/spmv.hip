@@ -8,7 +8,7 @@
 //
 // Layout and mapping (gfx950):
 //  * rows are cut into row blocks of at most 2048 nonzeros for blocks of 256
-//    threads, or of 512 for blocks of 128 (a per-matrix choice); a block
+//    threads, or of 256 for blocks of 64 (a per-matrix choice); a block
 //    first loads its contiguous nonzero range (colind, values) with
 //    unit-stride loads (non-temporal for matrices far larger than the
 //    last-level cache, cached otherwise: a per-matrix policy that the setup

@@ -212,7 +212,7 @@ class Matrix:
                                                 self.CACHE_POLICIES.index(policy)))
 
     def spmv_blocks(self, precision: str = "f64") -> int:
-        """Nonzeros per block of the plain SpMV kernel (2048 or 512)."""
+        """Nonzeros per block of the plain SpMV kernel (2048 or 256)."""
         c = C.c_int()
         _check(_lib.ppa_matrix_spmv_blocks(self.h, _PREC[precision], C.byref(c)))
         return c.value

@@ -34,10 +34,10 @@ def test_policies_bitwise_equal(lib, name):
     rng = np.random.default_rng(5)
     u, x, z, z2 = (rng.standard_normal(csr.n) for _ in range(4))
     lens = np.diff(csr.rowptr)
-    short = torch.as_tensor(lens <= 512, device="cuda")
+    short = torch.as_tensor(lens <= 256, device="cuda")
     for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
         outs = []
-        for blocks in (2048, 512):
+        for blocks in (2048, 256):
             A.set_spmv_blocks(blocks, prec)
             assert A.spmv_blocks(prec) == blocks
             for p in POL:
@@ -49,7 +49,7 @@ def test_policies_bitwise_equal(lib, name):
                              lib.fused_spmv(A, 1.0, dev(u, dt), -0.5, dev(u, dt),
                                             out_dtype=torch.float64 if prec == "f32" else None)))
         # every policy of one block shape bitwise; the two shapes bitwise on
-        # rows of at most 512 nonzeros and to rounding on longer ones
+        # rows of at most 256 nonzeros and to rounding on longer ones
         for i in (1, 2, 4, 5):
             ref = outs[0] if i < 3 else outs[3]
             for a, b in zip(ref, outs[i]):
@@ -75,7 +75,7 @@ def test_tuned_shape_c3_fp32_and_c2(lib):
     for csr, prec, dt in ((W.convdiff_2d(1000, 0.5), "f64", torch.float64),
                           (W.convdiff_3d(100, 0.3), "f32", torch.float32)):
         A = lib.Matrix(csr, want_f32=(prec == "f32"))
-        assert A.spmv_blocks(prec) in (512, 2048)
+        assert A.spmv_blocks(prec) in (256, 2048)
         rng = np.random.default_rng(9)
         u = dev(rng.standard_normal(csr.n), dt)
         y1 = lib.fused_spmv(A, 1.0, u, -0.5, u)
