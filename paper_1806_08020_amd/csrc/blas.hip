@@ -11,6 +11,8 @@
 // so every result is bitwise reproducible run to run.
 #include "ppa_internal.hpp"
 
+#include <initializer_list>
+
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -104,6 +106,54 @@ __global__ __launch_bounds__(BS) void k_proj(const double* __restrict__ V, int64
             const double* col = V + (int64_t)min(c0 + c, j - 1) * ldv;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) acc[c] += col[rr[i]] * wr[i];
+        }
+        block_reduce_store<CT>(acc, min(CT, j - c0), red, partial + (int64_t)c0 * nb + blockIdx.x, nb);
+        __syncthreads();
+    }
+}
+
+// k_proj on row pairs: thread t of block b reads rows r, r + 1 with
+// r = b * BS * RPT + 2 t + 2 i BS (i < RPT / 2) as one 16-byte load per
+// column.  For even n, 16-byte aligned V and w and even ldv; pairs past n
+// re-read the last pair with weight zero.
+__global__ __launch_bounds__(BS) void k_proj2(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                              int j, const double* __restrict__ w,
+                                              double* __restrict__ partial, int nb, int with_norm) {
+    constexpr int RP = RPT / 2;
+    __shared__ double red[NW * CT];
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + 2 * threadIdx.x;
+    double2 wr[RP];
+    int64_t rr[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+        const int64_t r = base + (int64_t)i * 2 * BS;
+        rr[i] = r < n ? r : n - 2;
+        const double2 v = *reinterpret_cast<const double2*>(w + rr[i]);
+        wr[i] = r < n ? v : make_double2(0.0, 0.0);
+    }
+    if (with_norm) {
+        double a[1] = {0.0};
+#pragma unroll
+        for (int i = 0; i < RP; ++i) {
+            a[0] += wr[i].x * wr[i].x;
+            a[0] += wr[i].y * wr[i].y;
+        }
+        block_reduce_store<1>(a, 1, red, partial + (int64_t)j * nb + blockIdx.x, nb);
+        __syncthreads();
+    }
+    for (int c0 = 0; c0 < j; c0 += CT) {
+        double acc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, j - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RP; ++i) {
+                const double2 v = *reinterpret_cast<const double2*>(col + rr[i]);
+                acc[c] += v.x * wr[i].x;
+                acc[c] += v.y * wr[i].y;
+            }
         }
         block_reduce_store<CT>(acc, min(CT, j - c0), red, partial + (int64_t)c0 * nb + blockIdx.x, nb);
         __syncthreads();
@@ -275,6 +325,59 @@ __global__ void k_cgs_finalize(const double* __restrict__ h1, const double* __re
         const double w0 = sqrt(h1[j]);
         Hcol[j] = beta;
         scal[2] = (beta > tol * w0 && beta > 0.0) ? 1.0 / beta : 0.0;
+    }
+}
+
+// k_update on row pairs (same mapping and conditions as k_proj2; t and out
+// 16-byte aligned).
+__global__ __launch_bounds__(BS) void k_update2(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                                int j, const double* __restrict__ h,
+                                                const double* t, double* out,
+                                                double* __restrict__ partial, int nb) {
+    constexpr int RP = RPT / 2;
+    __shared__ double hs[CGS_JMAX_ALL + 8];
+    __shared__ double red[NW];
+    for (int c = threadIdx.x; c < CGS_JMAX_ALL + 8; c += BS) hs[c] = c < j ? h[c] : 0.0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + 2 * threadIdx.x;
+    double2 tv[RP];
+    int64_t rr[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+        const int64_t r = base + (int64_t)i * 2 * BS;
+        rr[i] = r < n ? r : n - 2;
+        tv[i] = *reinterpret_cast<const double2*>(t + rr[i]);
+    }
+    for (int c0 = 0; c0 < j; c0 += 8) {
+        double2 v[8][RP];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, j - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RP; ++i) v[c][i] = *reinterpret_cast<const double2*>(col + rr[i]);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double hc = hs[c0 + c];
+#pragma unroll
+            for (int i = 0; i < RP; ++i) {
+                tv[i].x -= v[c][i].x * hc;
+                tv[i].y -= v[c][i].y * hc;
+            }
+        }
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+        if (base + (int64_t)i * 2 * BS < n) {
+            *reinterpret_cast<double2*>(out + rr[i]) = tv[i];
+            nrm += tv[i].x * tv[i].x;
+            nrm += tv[i].y * tv[i].y;
+        }
+    }
+    if (partial) {
+        double acc[1] = {nrm};
+        block_reduce_store<1>(acc, 1, red, partial + blockIdx.x, nb);
     }
 }
 
@@ -586,15 +689,29 @@ static unsigned sgrid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
 }
 
+// the row-pair kernels (16-byte loads) apply for even n, even ldv and
+// 16-byte aligned vectors
+static bool pairs_ok(int64_t n, int64_t ldv, std::initializer_list<const void*> ptrs) {
+    bool ok = n >= 2 && n % 2 == 0 && ldv % 2 == 0;
+    for (const void* p : ptrs) ok = ok && reinterpret_cast<uintptr_t>(p) % 16 == 0;
+    return ok;
+}
+
 static void proj(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* partial,
                  int nb, int with_norm, hipStream_t s) {
-    hipLaunchKernelGGL(k_proj, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, w, partial, nb, with_norm);
+    if (pairs_ok(n, ldv, {V, w}))
+        hipLaunchKernelGGL(k_proj2, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, w, partial, nb, with_norm);
+    else
+        hipLaunchKernelGGL(k_proj, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, w, partial, nb, with_norm);
     PPA_HIP(hipGetLastError());
 }
 
 static void update(int64_t n, int j, const double* V, int64_t ldv, const double* h, const double* t,
                    double* out, double* partial, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, h, t, out, partial, nb);
+    if (pairs_ok(n, ldv, {V, t, out}))
+        hipLaunchKernelGGL(k_update2, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, h, t, out, partial, nb);
+    else
+        hipLaunchKernelGGL(k_update, dim3(nb), dim3(BS), 0, s, V, ldv, n, j, h, t, out, partial, nb);
     PPA_HIP(hipGetLastError());
 }
 
