@@ -410,23 +410,22 @@ __global__ __launch_bounds__(SPMV_WBS) void k_fused_spmv_win(
     }
 }
 
-// Sliding-window variant for band matrices.  Block s (one per CU) walks the
-// chunks [t0, t1) of its segment in order; a chunk is a row range of at most
-// CH nonzeros (aligned start as above) with the record {r0, r1, p0, p1},
-// {lo, hi, -, -}.  u is kept in an LDS ring of RW entries, column c at
-// position c mod RW; chunk t needs the columns [lo, hi) beyond those of the
-// chunks before it (the segment's first chunk: its whole range, loaded by a
-// loop; later chunks at most RN * SPMV_WBS columns).  One barrier per chunk:
+// Sliding-window variant for band matrices.  Block s (BS threads; one or a
+// few per CU) walks the chunks [t0, t1) of its segment in order; a chunk is a
+// row range of at most CH nonzeros (aligned start as above) with the record
+// {r0, r1, p0, p1}, {lo, hi, -, -}.  u is kept in an LDS ring of RW entries,
+// column c at position c mod RW; chunk t needs the columns [lo, hi) beyond
+// those of the chunks before it (the segment's first chunk: its whole range,
+// loaded by a loop; later chunks at most RN * BS columns).  One barrier per chunk:
 // between barriers k - 1 and k the block sums the rows of chunk k - 1 from
 // one product buffer, gathers chunk k into the other, and writes the ring
 // entries of chunk k + 1.  The setup accepts a matrix only if those writes
 // cannot touch a column chunk k gathers, i.e. every column of chunk k is at
 // least hi(k + 1) - RW.  Column indices, values, the new ring entries and
 // the first row's epilogue operands of the next chunks are held in registers
-// as loaded (no conversion or masking until use), so their memory latency
-// overlaps the work of the chunks before them.
-// Loaded values are kept as loaded (no conversion or masking until use), so
-// that nothing waits for them before the chunk that needs them.
+// as loaded (no conversion or masking until use), so that nothing waits for
+// them before the chunk that needs them and their memory latency overlaps the
+// work of the chunks before them.
 template <typename VT, typename IT, int NG, int G, int RN>
 struct RingSlot {
     int r0, r1, p0, p1, lo, hi;
