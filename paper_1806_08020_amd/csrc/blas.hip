@@ -295,6 +295,61 @@ __global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V
     }
 }
 
+// k_update_proj for 32 < j <= 64 with half the registers: a block covers
+// BS / 2 rows; waves 0 and 1 hold the columns 0 .. 31 of those rows, waves 2
+// and 3 the columns 32 .. 63 (the half is uniform in a wave, so column
+// addresses stay scalar).  Each lane sums its half of V h, the halves meet
+// in LDS, and the row's update is (w - s_0) - s_1 on both sides.
+__global__ __launch_bounds__(BS) void k_update_proj_halves(const double* __restrict__ V, int64_t ldv,
+                                                           int64_t n, int j,
+                                                           const double* __restrict__ h,
+                                                           const double* __restrict__ w,
+                                                           double* __restrict__ t,
+                                                           double* __restrict__ partial, int nb) {
+    static_assert(BS == 256, "two waves per half");
+    constexpr int JH = 32;
+    __shared__ double hs[2 * JH];
+    __shared__ double sx[BS];
+    __shared__ double red[NW][JH];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int half = wave >> 1;
+    const int64_t r = (int64_t)blockIdx.x * (BS / 2) + (wave & 1) * 64 + lane;
+    const int64_t rr = r < n ? r : n - 1;
+    double v[JH];
+    static_for<JH>([&](auto ic) {
+        constexpr int c = decltype(ic)::value;
+        v[c] = V[(int64_t)min(JH * half + c, j - 1) * ldv + rr];
+    });
+    const double tw = w[rr];
+    for (int c = threadIdx.x; c < 2 * JH; c += BS) hs[c] = c < j ? h[c] : 0.0;
+    __syncthreads();
+    double sp = 0.0;
+    static_for<JH>([&](auto ic) {
+        constexpr int c = decltype(ic)::value;
+        sp += v[c] * hs[JH * half + c];
+    });
+    sx[threadIdx.x] = sp;
+    __syncthreads();
+    const double so = sx[threadIdx.x ^ 128];
+    const double tv = (tw - (half ? so : sp)) - (half ? sp : so);
+    if (half == 0 && r < n) t[r] = tv;
+    const double wt = r < n ? tv : 0.0;
+    static_for<JH>([&](auto ic) {
+        constexpr int c = decltype(ic)::value;
+        v[c] = JH * half + c < j ? v[c] * wt : 0.0;
+    });
+    int col = 0;
+    butterfly<JH, JH, 32>(v, lane, col);
+    v[0] += __shfl_xor(v[0], 1, 64);
+    if ((lane & 1) == 0) red[wave][col] = v[0];
+    __syncthreads();
+    for (int c = threadIdx.x; c < j; c += BS) {
+        const double s = c < JH ? red[0][c] + red[1][c] : red[2][c - JH] + red[3][c - JH];
+        partial[(int64_t)c * nb + blockIdx.x] = s;
+    }
+}
+
 // out[c] = sum_b partial[c * nb + b], one block per column, fixed tree.
 __global__ __launch_bounds__(BS) void k_reduce_cols(const double* __restrict__ partial, int nb,
                                                     double* __restrict__ out) {
@@ -665,18 +720,20 @@ int cgs_blocks(int64_t n) {
     return (int)std::max<int64_t>(1, nb);
 }
 
-// blocks of the fused update-projection kernel (one row per thread)
-static int cgs_blocks_fused(int64_t n) {
-    const int64_t nb = (n + BS - 1) / BS;
+// blocks of the fused update-projection kernels (one row per thread, or per
+// lane pair for the half-row form)
+static int cgs_blocks_fused(int64_t n, int rows_per_block) {
+    const int64_t nb = (n + rows_per_block - 1) / rows_per_block;
     PPA_REQUIRE(nb <= (int64_t(1) << 27), "vector too long for the Gram-Schmidt kernels");
     return (int)std::max<int64_t>(1, nb);
 }
 
 void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws) {
     ws.nb = cgs_blocks(n);
-    ws.nbf = cgs_blocks_fused(n);
+    ws.nbf = cgs_blocks_fused(n, BS);
+    ws.nbh = cgs_blocks_fused(n, BS / 2);
     ws.partial = c.take<double>(std::max<size_t>((size_t)(2 * CGS_JMAX_ALL + 4) * ws.nb,
-                                                 (size_t)CGS_JFUSED * ws.nbf));
+                                                 (size_t)CGS_JFUSED * ws.nbh));
     ws.dred = c.take<double>(2 * CGS_JMAX_ALL + 4);
     ws.coef = c.take<double>(2 * CGS_JMAX_ALL + 8);
     ws.h1 = c.take<double>(CGS_JMAX_ALL);
@@ -731,7 +788,7 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
     // reorthogonalisation: t = w - V h1, h2 = V^T t (one pass over V when
     // the basis fits the fused kernel's registers)
     if (j <= CGS_JFUSED) {
-        const int nbf = ws.nbf;
+        const int nbf = j <= 32 ? ws.nbf : ws.nbh;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nbf), dim3(BS), 0, s, V, ldv, n, j, ws.h1, w, ws.t,
                                ws.partial, nbf);
@@ -745,7 +802,7 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
         else if (j <= 32)
             go(k_update_proj<32>);
         else
-            go(k_update_proj<64>);
+            go(k_update_proj_halves);
         PPA_HIP(hipGetLastError());
         reduce_cols(ws.partial, nbf, j, ws.h2, s);
     } else {

@@ -232,6 +232,7 @@ struct Cgs2Ws {
     double* coef = nullptr;      // delayed form: a, g (JMAX_ALL each) and 4 scalars
     int nb = 0;                  // blocks of the streaming kernels
     int nbf = 0;                 // blocks of the fused update-projection kernel
+    int nbh = 0;                 // blocks of its half-row form (j > 32)
 };
 constexpr int CGS_JMAX_ALL = 256;
 constexpr int CGS_JFUSED = 64;   // widest basis of the fused update-projection

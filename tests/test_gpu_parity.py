@@ -211,7 +211,8 @@ def test_apply_double_poly(lib):
 
 
 # ---------------------------------------------------------------- CGS2, GEMM
-@pytest.mark.parametrize("n,j", [(1000, 1), (5003, 7), (20000, 30), (4097, 64), (3000, 100)])
+@pytest.mark.parametrize("n,j", [(1000, 1), (5003, 7), (20000, 30), (20000, 33), (4098, 50), (301, 47),
+                                 (4097, 64), (3000, 100)])
 def test_cgs2_vs_oracle(lib, n, j):
     rng = np.random.default_rng(n + j)
     Q, _ = np.linalg.qr(rng.standard_normal((n, j)))
