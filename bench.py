@@ -310,7 +310,7 @@ def table81_report(max_cycles_d0):
     return out
 
 
-def served_mix_report(count):
+def served_mix_report(count, closed_only=False):
     """Served mix (2-D convection-diffusion solves of random size, degree and
     nev, seeded): capacity from a closed-loop run (all requests at t = 0),
     then Poisson arrivals at 0.7 x capacity, FP64 and mixed precision (mixed
@@ -339,6 +339,8 @@ def served_mix_report(count):
     arr = np.cumsum(rng.exponential(1.0 / rate, size=count))
     rep = {"requests": count, "capacity_req_per_s": round(capacity, 2), "rate_req_per_s": round(rate, 2),
            "closed_loop": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in closed.items()}}
+    if closed_only:
+        return rep
     for name, prec, graph, ls in (("f64", "f64", False, False), ("mixed", "mixed", False, False),
                                   ("f64_graph", "f64", True, False), ("f64_lowsync", "f64", False, True)):
         for r, t in zip(reqs, arr):
@@ -368,6 +370,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the solve in the other precision (mixed vs FP64)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served mix")
+    ap.add_argument("--served-only", action="store_true",
+                    help="only the served mix's closed loop (for profiler runs); prints its own JSON line")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--cache-policy", default="auto", choices=("auto", "stream", "keep", "keep_ntst"),
                     help="override the SpMV cache policy the matrix setup chose (for counter runs)")
@@ -388,6 +392,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.served_only:
+        print(json.dumps({"served": served_mix_report(args.serve_requests, closed_only=True)}))
+        return
     if args.copy_probe:
         copy_probe(torch, args.steps)
         return
