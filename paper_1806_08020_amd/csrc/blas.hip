@@ -351,12 +351,21 @@ __global__ __launch_bounds__(BS) void k_update_proj_halves(const double* __restr
 }
 
 // out[c] = sum_b partial[c * nb + b], one block per column, fixed tree.
+// Each thread sums its strided share in order, eight loads in flight at a time.
 __global__ __launch_bounds__(BS) void k_reduce_cols(const double* __restrict__ partial, int nb,
                                                     double* __restrict__ out) {
     __shared__ double red[NW];
     const double* p = partial + (int64_t)blockIdx.x * nb;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BS) s += p[b];
+    int b = threadIdx.x;
+    for (; b + 7 * BS < nb; b += 8 * BS) {
+        double a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = p[b + i * BS];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += a[i];
+    }
+    for (; b < nb; b += BS) s += p[b];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
