@@ -82,9 +82,10 @@ const char* ppa_last_error(void);
  * matrices (n >= 200000, nnz >= 10^6) whose row blocks touch narrow column
  * ranges it also times the LDS-windowed and sliding-window SpMVs against the
  * plain one and keeps the fastest (a staged variant only for a 5% gain); all
- * sum each row in column order, so they agree bitwise on every row of at
- * most 2048 nonzeros (longer rows are tree-reduced by the plain kernel and
- * agree to rounding).
+ * sum each row in column order, so they agree bitwise on every row that fits
+ * one block of the plain kernel's block shape (2048 or 256 nonzeros, see
+ * ppa_matrix_spmv_blocks); longer rows are tree-reduced by the plain kernel
+ * and agree to rounding.
  * ------------------------------------------------------------------------ */
 #define PPA_MATRIX_F32 1            /* build an FP32 copy of the values           */
 #define PPA_MATRIX_WINDOW_FORCE 2   /* use the windowed SpMV whenever it fits     */
