@@ -80,8 +80,9 @@ const char* ppa_last_error(void);
  * computes ||A||_inf, and builds the row-block partitions used by the SpMV
  * kernels (allocated by the library, freed by ppa_matrix_destroy).  For large
  * matrices (n >= 200000, nnz >= 10^6) whose row blocks touch narrow column
- * ranges it also times the LDS-windowed and sliding-window SpMVs against the
- * plain one and keeps the fastest (a staged variant only for a 5% gain); all
+ * ranges and whose tuned plain pass runs below half the HBM peak (4 TB/s) it
+ * also times the LDS-windowed and sliding-window SpMVs against the plain one
+ * and keeps the fastest (a staged variant only for a 5% gain); all
  * sum each row in column order, so they agree bitwise on every row that fits
  * one block of the plain kernel's block shape (2048 or 256 nonzeros, see
  * ppa_matrix_spmv_blocks); longer rows are tree-reduced by the plain kernel

@@ -136,6 +136,11 @@ struct Ring {
     size_t lds_bytes = 0;
 };
 
+// The windowed and sliding-window variants are timed at matrix creation only
+// when the plain kernel's tuned pass runs below this rate (GB/s; half the
+// MI355X HBM peak).
+constexpr double SPMV_STAGED_GATE_GBS = 4000.0;
+
 // Cache policies of the plain SpMV kernel (values match ppa.h's PPA_CACHE_*).
 enum { CP_STREAM = 0, CP_KEEP = 1, CP_KEEP_NTST = 2 };
 

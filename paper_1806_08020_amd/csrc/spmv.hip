@@ -1280,6 +1280,15 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
         blk = c_keep / 3;
         W.on = won;
         if (mode != 0 || (!W.bm && !R.rm)) continue;
+        // the staged variants exist for gather-bound matrices: when the plain
+        // kernel already streams at half the HBM peak they cannot gain much,
+        // and their timing is skipped (it also costs setup time)
+        {
+            const VecT t = f32 ? VecT::F32 : VecT::F64;
+            const double bytes = (double)fused_spmv_bytes(A, t, t, uu, uu, nullptr, nullptr);
+            const double gbs = bytes / ((double)tc[c_keep] * 1e-3) * 1e-9;
+            if (gbs >= SPMV_STAGED_GATE_GBS) continue;
+        }
         // plain (0), windowed (1), sliding window (2): best trial of each
         float tv[3] = {1e30f, 1e30f, 1e30f};
         bool ok[3] = {true, W.bm != nullptr, R.rm != nullptr};

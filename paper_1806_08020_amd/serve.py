@@ -85,9 +85,9 @@ def batch_footprint(rq: Request) -> int:
     return csr_bytes(rq.csr) + 16 * rq.csr.n + ppa.batch_workspace_bytes(rq.csr.n, rq.d, rq.m, rq.nev)
 
 
-def _solve_stream(rq: Request, stream: torch.cuda.Stream) -> ppa.EigsOut:
+def _solve_stream(rq: Request, stream: torch.cuda.Stream, window: str = "auto") -> ppa.EigsOut:
     with torch.cuda.stream(stream):
-        A = ppa.Matrix(rq.csr, want_f32=(rq.precision == "mixed"))
+        A = ppa.Matrix(rq.csr, want_f32=(rq.precision == "mixed"), window=window)
         b = torch.as_tensor(rq.b, device="cuda")
         v0 = torch.as_tensor(rq.v0, device="cuda")
         P = ppa.Poly.build(A, rq.d, b, lowsync=rq.lowsync)
@@ -99,8 +99,11 @@ def _solve_stream(rq: Request, stream: torch.cuda.Stream) -> ppa.EigsOut:
 
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 256, small_n: int = 16384,
-                 stream_workers: int = 3):
+                 stream_workers: int = 3, matrix_window: str = "auto"):
+        """matrix_window: SpMV variant choice for the matrices of whole solves
+        (ppa.Matrix's ``window``: "auto" times the variants at creation)."""
         self.budget = int(hbm_budget)
+        self.matrix_window = matrix_window
         self.small_n = small_n
         self.batch_stream = torch.cuda.Stream()
         self.batch = ppa.Batch(max_slots, stream=self.batch_stream)
@@ -155,7 +158,7 @@ class Server:
                     if not free_streams:
                         continue
                     st = free_streams.pop()
-                    fut = self.pool.submit(_solve_stream, rq, st)
+                    fut = self.pool.submit(_solve_stream, rq, st, self.matrix_window)
                     in_stream[fut] = (rq, clock() - t0, fp, st)
                 used += fp
                 waiting.remove(rq)
