@@ -93,6 +93,10 @@ const char* ppa_last_error(void);
 #define PPA_MATRIX_WINDOW_OFF 4     /* never use a windowed SpMV (either kind)    */
 #define PPA_MATRIX_RING_FORCE 8     /* use the sliding-window SpMV whenever it fits
                                        (not with PPA_MATRIX_WINDOW_FORCE)         */
+#define PPA_MATRIX_NO_TUNE 16       /* no timing at creation: the size rule's cache
+                                       policy, large blocks, no staged variant
+                                       unless forced (for matrices used briefly,
+                                       where the timing would not pay)           */
 int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
                       const double* val64_d, const float* val32_d, int flags,
                       void* stream, ppa_matrix** out);

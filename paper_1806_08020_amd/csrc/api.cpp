@@ -83,7 +83,7 @@ int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_
                               : (flags & PPA_MATRIX_WINDOW_FORCE) ? 1
                               : (flags & PPA_MATRIX_RING_FORCE)   ? 2
                                                                   : 0;
-            matrix_tune(*A, wmode, s);
+            matrix_tune(*A, wmode, (flags & PPA_MATRIX_NO_TUNE) == 0, s);
             A->rp_host.clear();
             A->rp_host.shrink_to_fit();
         } catch (...) {

@@ -218,7 +218,7 @@ void matrix_setup(Matrix& A, hipStream_t s);   // validate, norm, partition
 // Choose between the plain and the windowed SpMV for each available value
 // type: mode 0 times both on a scratch vector (large matrices only), mode 1
 // forces the windowed kernel whenever it fits, mode -1 keeps the plain one.
-void matrix_tune(Matrix& A, int mode, hipStream_t s);
+void matrix_tune(Matrix& A, int mode, bool timing, hipStream_t s);
 void matrix_release(Matrix& A);
 // out = a x + b y + c z (y, z may be null), element types as given
 void launch_axpy3(int64_t n, VecT in, VecT out_t, double a, const void* x, double b, const void* y,

@@ -1205,7 +1205,7 @@ static float time_passes(const Matrix& A, bool f32, void* u, void* y, int reps, 
     return ms / reps;
 }
 
-void matrix_tune(Matrix& A, int mode, hipStream_t s) {
+void matrix_tune(Matrix& A, int mode, bool timing, hipStream_t s) {
     // Only large matrices are timed (a few passes each): the cache policy and
     // block shape of the plain kernel, then, where the column ranges allow
     // it, the windowed kernel against the plain one.  Short timings alternate the candidates
@@ -1233,7 +1233,9 @@ void matrix_tune(Matrix& A, int mode, hipStream_t s) {
             A.ring32.on = A.ring32.rm != nullptr;
         }
     };
-    if (A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
+    if (!timing || A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
+        // small matrices, or no timing asked for: the size rule's choice, and
+        // a forced staged variant if it fits
         if (mode >= 1 && A.nnz > 0) {
             build_all(mode == 1, mode == 2);
             force();

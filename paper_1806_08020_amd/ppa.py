@@ -24,6 +24,7 @@ PPA_WARN_BREAKDOWN = 3
 PPA_ERR_INVALID, PPA_ERR_HIP, PPA_ERR_WORKSPACE, PPA_ERR_NONFINITE = -1, -2, -3, -4
 PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
 PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF, PPA_MATRIX_RING_FORCE = 1, 2, 4, 8
+PPA_MATRIX_NO_TUNE = 16
 _PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
 
 vp = C.c_void_p
@@ -159,10 +160,11 @@ class Matrix:
     """Device CSR matrix handle.  ``csr`` is a workloads.CSR (host arrays);
     the device copies are owned by this object and borrowed by the handle."""
 
-    def __init__(self, csr, want_f32: bool = False, window: str = "auto"):
+    def __init__(self, csr, want_f32: bool = False, window: str = "auto", tune: bool = True):
         """window: "auto" (time the SpMV variants on large matrices),
         "force" (LDS-windowed whenever it fits), "ring" (sliding window
-        whenever it fits) or "off" (plain kernel only)."""
+        whenever it fits) or "off" (plain kernel only).  tune=False skips the
+        timing at creation (size-rule cache policy, large blocks)."""
         dev = torch.device("cuda")
         self.n = int(csr.n)
         self.rowptr = torch.as_tensor(np.asarray(csr.rowptr, dtype=np.int32)).to(dev)
@@ -175,6 +177,8 @@ class Matrix:
         h = vp()
         flags = {"auto": 0, "force": PPA_MATRIX_WINDOW_FORCE, "ring": PPA_MATRIX_RING_FORCE,
                  "off": PPA_MATRIX_WINDOW_OFF}[window]
+        if not tune:
+            flags |= PPA_MATRIX_NO_TUNE
         _check(_lib.ppa_matrix_create(self.n, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.vals),
                                       _ptr(self.vals32), flags, _stream(), C.byref(h)))
         self.h = h

@@ -85,9 +85,10 @@ def batch_footprint(rq: Request) -> int:
     return csr_bytes(rq.csr) + 16 * rq.csr.n + ppa.batch_workspace_bytes(rq.csr.n, rq.d, rq.m, rq.nev)
 
 
-def _solve_stream(rq: Request, stream: torch.cuda.Stream, window: str = "auto") -> ppa.EigsOut:
+def _solve_stream(rq: Request, stream: torch.cuda.Stream, window: str = "auto",
+                  tune: bool = True) -> ppa.EigsOut:
     with torch.cuda.stream(stream):
-        A = ppa.Matrix(rq.csr, want_f32=(rq.precision == "mixed"), window=window)
+        A = ppa.Matrix(rq.csr, want_f32=(rq.precision == "mixed"), window=window, tune=tune)
         b = torch.as_tensor(rq.b, device="cuda")
         v0 = torch.as_tensor(rq.v0, device="cuda")
         P = ppa.Poly.build(A, rq.d, b, lowsync=rq.lowsync)
@@ -99,11 +100,14 @@ def _solve_stream(rq: Request, stream: torch.cuda.Stream, window: str = "auto") 
 
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 256, small_n: int = 16384,
-                 stream_workers: int = 3, matrix_window: str = "auto"):
-        """matrix_window: SpMV variant choice for the matrices of whole solves
-        (ppa.Matrix's ``window``: "auto" times the variants at creation)."""
+                 stream_workers: int = 3, matrix_window: str = "auto", matrix_tune: bool = False):
+        """matrix_window, matrix_tune: SpMV kernel choice for the matrices of
+        whole solves (ppa.Matrix's ``window`` and ``tune``).  A served matrix
+        is used for one solve, so by default it skips the timing of kernel
+        variants at creation, which would cost more than it saves."""
         self.budget = int(hbm_budget)
         self.matrix_window = matrix_window
+        self.matrix_tune = matrix_tune
         self.small_n = small_n
         self.batch_stream = torch.cuda.Stream()
         self.batch = ppa.Batch(max_slots, stream=self.batch_stream)
@@ -158,7 +162,7 @@ class Server:
                     if not free_streams:
                         continue
                     st = free_streams.pop()
-                    fut = self.pool.submit(_solve_stream, rq, st, self.matrix_window)
+                    fut = self.pool.submit(_solve_stream, rq, st, self.matrix_window, self.matrix_tune)
                     in_stream[fut] = (rq, clock() - t0, fp, st)
                 used += fp
                 waiting.remove(rq)
