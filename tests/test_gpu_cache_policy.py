@@ -113,3 +113,21 @@ def test_tuned_policy_full_size_bitwise(lib):
     A.set_cache_policy("stream", "f64")
     y0 = lib.fused_spmv(A, 1.0, x, -0.5, u)
     assert torch.equal(y0, y1)
+
+
+def test_no_tune_keeps_size_rule(lib):
+    """PPA_MATRIX_NO_TUNE: no timing at creation, so the size rule's cache
+    policy, the large block shape and the plain kernel (a forced variant is
+    still built); results equal the timed matrix's bit for bit."""
+    csr = W.convdiff_2d(1000, 0.5)
+    A = lib.Matrix(csr, want_f32=True, tune=False)
+    for prec in ("f64", "f32"):
+        assert A.spmv_blocks(prec) == 2048
+        assert A.cache_policy(prec) == "keep"
+        assert A.spmv_variant(prec) == "plain"
+    B = lib.Matrix(csr, want_f32=True)
+    rng = np.random.default_rng(21)
+    u = dev(rng.standard_normal(csr.n))
+    assert torch.equal(lib.fused_spmv(A, 1.0, u, -0.5, u), lib.fused_spmv(B, 1.0, u, -0.5, u))
+    R = lib.Matrix(W.random_banded(300_000, 9, 2000, seed=8), window="ring", tune=False)
+    assert R.spmv_variant("f64") == "ring"
