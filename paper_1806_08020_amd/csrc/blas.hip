@@ -295,11 +295,12 @@ __global__ __launch_bounds__(BS) void k_update_proj(const double* __restrict__ V
     }
 }
 
-// k_update_proj for 32 < j <= 64 with half the registers: a block covers
-// BS / 2 rows; waves 0 and 1 hold the columns 0 .. 31 of those rows, waves 2
-// and 3 the columns 32 .. 63 (the half is uniform in a wave, so column
-// addresses stay scalar).  Each lane sums its half of V h, the halves meet
-// in LDS, and the row's update is (w - s_0) - s_1 on both sides.
+// k_update_proj for JH < j <= 2 JH with half the registers: a block covers
+// BS / 2 rows; waves 0 and 1 hold the columns 0 .. JH - 1 of those rows,
+// waves 2 and 3 the columns JH .. 2 JH - 1 (the half is uniform in a wave, so
+// column addresses stay scalar).  Each lane sums its half of V h, the halves
+// meet in LDS, and the row's update is (w - s_0) - s_1 on both sides.
+template <int JH>
 __global__ __launch_bounds__(BS) void k_update_proj_halves(const double* __restrict__ V, int64_t ldv,
                                                            int64_t n, int j,
                                                            const double* __restrict__ h,
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(BS) void k_update_proj_halves(const double* __restr
                                                            double* __restrict__ t,
                                                            double* __restrict__ partial, int nb) {
     static_assert(BS == 256, "two waves per half");
-    constexpr int JH = 32;
+    static_assert(JH == 16 || JH == 32, "JH: 16 or 32");
     __shared__ double hs[2 * JH];
     __shared__ double sx[BS];
     __shared__ double red[NW][JH];
@@ -341,8 +342,9 @@ __global__ __launch_bounds__(BS) void k_update_proj_halves(const double* __restr
     });
     int col = 0;
     butterfly<JH, JH, 32>(v, lane, col);
-    v[0] += __shfl_xor(v[0], 1, 64);
-    if ((lane & 1) == 0) red[wave][col] = v[0];
+    // lanes that share a column hold partial sums over disjoint lanes
+    for (int o = 32 / JH; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o, 64);
+    if ((lane & (64 / JH - 1)) == 0) red[wave][col] = v[0];
     __syncthreads();
     for (int c = threadIdx.x; c < j; c += BS) {
         const double s = c < JH ? red[0][c] + red[1][c] : red[2][c - JH] + red[3][c - JH];
@@ -797,7 +799,7 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
     // reorthogonalisation: t = w - V h1, h2 = V^T t (one pass over V when
     // the basis fits the fused kernel's registers)
     if (j <= CGS_JFUSED) {
-        const int nbf = j <= 32 ? ws.nbf : ws.nbh;
+        const int nbf = j <= 16 ? ws.nbf : ws.nbh;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nbf), dim3(BS), 0, s, V, ldv, n, j, ws.h1, w, ws.t,
                                ws.partial, nbf);
@@ -809,9 +811,9 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
         else if (j <= 16)
             go(k_update_proj<16>);
         else if (j <= 32)
-            go(k_update_proj<32>);
+            go(k_update_proj_halves<16>);
         else
-            go(k_update_proj_halves);
+            go(k_update_proj_halves<32>);
         PPA_HIP(hipGetLastError());
         reduce_cols(ws.partial, nbf, j, ws.h2, s);
     } else {
