@@ -825,7 +825,9 @@ void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w
     update(n, j, V, ldv, ws.h2, ws.t, w_out, ws.partial, nb, s);
     if (v_next) {
         // reduction, Hessenberg column and v_next = w_out / beta in one launch
-        hipLaunchKernelGGL(k_finalize_scale, dim3(sgrid(n)), dim3(BS), 0, s, ws.partial, nb, ws.h1,
+        // at most 1024 blocks: each repeats the norm's reduction, then scales
+        // its grid-stride share of w_out
+        hipLaunchKernelGGL(k_finalize_scale, dim3(std::min(sgrid(n), 1024u)), dim3(BS), 0, s, ws.partial, nb, ws.h1,
                            ws.h2, j, ws.scal, Hcol_d, breakdown_tol, w_out, v_next, n);
         PPA_HIP(hipGetLastError());
         return;
