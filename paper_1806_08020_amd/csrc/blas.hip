@@ -731,6 +731,10 @@ int cgs_blocks(int64_t n) {
     return (int)std::max<int64_t>(1, nb);
 }
 
+int ritz_blocks(int64_t n) {
+    return (int)std::min<int64_t>(4 * (int64_t)cgs_blocks(n), std::max(cgs_blocks(n), 2048));
+}
+
 // blocks of the fused update-projection kernels (one row per thread, or per
 // lane pair for the half-row form)
 static int cgs_blocks_fused(int64_t n, int rows_per_block) {

@@ -297,7 +297,7 @@ void carve_eigs(Carver& c, const Matrix& A, const Poly* p, const ppa_eigs_opts& 
     e.ycols = 2 * o.nev;
     e.Y = c.take<double>((size_t)e.ld * e.ycols);
     e.AY = c.take<double>((size_t)e.ld * e.ycols);
-    e.dpart = c.take<double>((size_t)MAX_DOTS * cgs_blocks(n));
+    e.dpart = c.take<double>((size_t)MAX_DOTS * ritz_blocks(n));
     e.dout = c.take<double>(MAX_DOTS);
     e.cmap = c.take<int>((size_t)2 * o.nev);
     e.cscale = c.take<double>((size_t)2 * o.nev);
@@ -515,7 +515,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
                 L.a[t] = e.Y + (size_t)q.a * e.ld;
                 L.b[t] = (q.kind == 1 ? e.Y : e.AY) + (size_t)q.b * e.ld;
             }
-            launch_dots(n, L, e.dpart, nb, e.dout, s);
+            launch_dots(n, L, e.dpart, ritz_blocks(n), e.dout, s);
             PPA_HIP(hipMemcpyAsync(dv.data() + off, e.dout, L.count * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         PPA_HIP(hipStreamSynchronize(s));
@@ -536,7 +536,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
                         P.v[q][t] = t < c.nterms ? (c.kind[t] == 0 ? e.AY : e.Y) + (size_t)c.col[t] * e.ld : nullptr;
                         P.c[q][t] = t < c.nterms ? c.c[t] : 0.0;
                     }
-                launch_combo_norms(n, P, e.dpart, nb, e.dout, s);
+                launch_combo_norms(n, P, e.dpart, ritz_blocks(n), e.dout, s);
                 PPA_HIP(hipMemcpyAsync(rn.data() + done, e.dout, P.count * sizeof(double), hipMemcpyDeviceToHost, s));
                 done += P.count;
             }

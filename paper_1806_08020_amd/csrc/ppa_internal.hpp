@@ -242,6 +242,9 @@ struct Cgs2Ws {
 constexpr int CGS_JMAX_ALL = 256;
 constexpr int CGS_JFUSED = 64;   // widest basis of the fused update-projection
 int cgs_blocks(int64_t n);
+// blocks of the Ritz-test inner products and residual norms (more than the
+// Gram-Schmidt kernels': these read many vectors per row with few waves)
+int ritz_blocks(int64_t n);
 void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws);
 // Orthogonalise w against V[:, 0:j] (CGS2).  Writes the unnormalised result to
 // w_out (may equal w), the Hessenberg column (j+1 entries: h, beta) to
