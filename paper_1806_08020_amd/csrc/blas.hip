@@ -722,6 +722,137 @@ __global__ __launch_bounds__(BS) void k_dupdate(const double* __restrict__ V, in
     }
 }
 
+// k_dproj and k_dupdate on row pairs (16-byte loads; even n, even ldv and
+// 16-byte aligned vectors, as for k_proj2).
+__global__ __launch_bounds__(BS) void k_dproj2(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                               int jq, const double* __restrict__ u,
+                                               const double* __restrict__ w,
+                                               double* __restrict__ partial, int nb) {
+    constexpr int CH = CT / 2;
+    constexpr int RP = RPT / 2;
+    __shared__ double red[NW * CT];
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + 2 * threadIdx.x;
+    double2 ur[RP], wr[RP];
+    int64_t rr[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+        const int64_t r = base + (int64_t)i * 2 * BS;
+        rr[i] = r < n ? r : n - 2;
+        ur[i] = (u && r < n) ? *reinterpret_cast<const double2*>(u + rr[i]) : make_double2(0.0, 0.0);
+        wr[i] = (w && r < n) ? *reinterpret_cast<const double2*>(w + rr[i]) : make_double2(0.0, 0.0);
+    }
+    {
+        double sc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < RP; ++i) {
+            sc[0] += ur[i].x * ur[i].x;
+            sc[0] += ur[i].y * ur[i].y;
+            sc[1] += ur[i].x * wr[i].x;
+            sc[1] += ur[i].y * wr[i].y;
+            sc[2] += wr[i].x * wr[i].x;
+            sc[2] += wr[i].y * wr[i].y;
+        }
+        block_reduce_store<3>(sc, 3, red, partial + (int64_t)(2 * jq) * nb + blockIdx.x, nb);
+        __syncthreads();
+    }
+    for (int c0 = 0; c0 < jq; c0 += CH) {
+        double acc[2 * CH];
+#pragma unroll
+        for (int c = 0; c < 2 * CH; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, jq - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RP; ++i) {
+                const double2 v = *reinterpret_cast<const double2*>(col + rr[i]);
+                acc[c] += v.x * ur[i].x;
+                acc[c] += v.y * ur[i].y;
+                acc[CH + c] += v.x * wr[i].x;
+                acc[CH + c] += v.y * wr[i].y;
+            }
+        }
+        const int cnt = min(CH, jq - c0);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < 2 * CH; ++c) {
+            if ((c % CH) < cnt) {
+                const double v = wave_sum(acc[c]);
+                if (lane == 0) red[wv * CT + c] = v;
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < 2 * CH; c += BS) {
+            if ((c % CH) >= cnt) continue;
+            double t = 0.0;
+            for (int q = 0; q < NW; ++q) t += red[q * CT + c];
+            const int col = c < CH ? c0 + c : jq + c0 + (c - CH);
+            partial[(int64_t)col * nb + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_dupdate2(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                                 int jq, const double* __restrict__ coef,
+                                                 const double* __restrict__ u,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ q_out,
+                                                 double* __restrict__ u_out) {
+    constexpr int RP = RPT / 2;
+    __shared__ double as[CGS_JMAX_ALL + 8], gs[CGS_JMAX_ALL + 8];
+    for (int c = threadIdx.x; c < CGS_JMAX_ALL + 8; c += BS) {
+        as[c] = c < jq ? coef[c] : 0.0;
+        gs[c] = c < jq ? coef[CGS_JMAX_ALL + c] : 0.0;
+    }
+    const double inv = coef[2 * CGS_JMAX_ALL], sw = coef[2 * CGS_JMAX_ALL + 1],
+                 gamma = coef[2 * CGS_JMAX_ALL + 2];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * BS * RPT + 2 * threadIdx.x;
+    double2 qa[RP], ug[RP], uv[RP], wv[RP];
+    int64_t rr[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+        const int64_t r = base + (int64_t)i * 2 * BS;
+        rr[i] = r < n ? r : n - 2;
+        uv[i] = u ? *reinterpret_cast<const double2*>(u + rr[i]) : make_double2(0.0, 0.0);
+        wv[i] = w ? *reinterpret_cast<const double2*>(w + rr[i]) : make_double2(0.0, 0.0);
+        qa[i] = make_double2(0.0, 0.0);
+        ug[i] = make_double2(0.0, 0.0);
+    }
+    for (int c0 = 0; c0 < jq; c0 += 8) {
+        double2 v[8][RP];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double* col = V + (int64_t)min(c0 + c, jq - 1) * ldv;
+#pragma unroll
+            for (int i = 0; i < RP; ++i) v[c][i] = *reinterpret_cast<const double2*>(col + rr[i]);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double ac = as[c0 + c], gc = gs[c0 + c];
+#pragma unroll
+            for (int i = 0; i < RP; ++i) {
+                qa[i].x += v[c][i].x * ac;
+                qa[i].y += v[c][i].y * ac;
+                ug[i].x += v[c][i].x * gc;
+                ug[i].y += v[c][i].y * gc;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+        if (base + (int64_t)i * 2 * BS < n) {
+            if (q_out)
+                *reinterpret_cast<double2*>(q_out + rr[i]) =
+                    make_double2((uv[i].x - qa[i].x) * inv, (uv[i].y - qa[i].y) * inv);
+            if (u_out)
+                *reinterpret_cast<double2*>(u_out + rr[i]) =
+                    make_double2(sw * wv[i].x - gamma * uv[i].x - ug[i].x,
+                                 sw * wv[i].y - gamma * uv[i].y - ug[i].y);
+        }
+    }
+}
+
 }  // namespace
 
 int cgs_blocks(int64_t n) {
@@ -850,14 +981,22 @@ void launch_dcgs_step(int kind, int64_t n, int jq, const double* V, int64_t ldv,
                     (kind == DCGS_LAST && u && !w),
                 "delayed Gram-Schmidt: operands do not match the step kind");
     const int nb = ws.nb;
-    hipLaunchKernelGGL(k_dproj, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, u, w, ws.partial, nb);
+    const bool pairs = pairs_ok(n, ldv, {V, u, w, q_out, u_out});
+    if (pairs)
+        hipLaunchKernelGGL(k_dproj2, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, u, w, ws.partial, nb);
+    else
+        hipLaunchKernelGGL(k_dproj, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, u, w, ws.partial, nb);
     PPA_HIP(hipGetLastError());
     reduce_cols(ws.partial, nb, 2 * jq + 3, ws.dred, s);
     hipLaunchKernelGGL(k_dcoef, dim3(1), dim3(BS), 0, s, kind, jq, ws.dred, Hd, ldh, ws.coef, ws.scal,
                        breakdown_tol);
     PPA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_dupdate, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, ws.coef, u, w,
-                       kind == DCGS_FIRST ? nullptr : q_out, kind == DCGS_LAST ? nullptr : u_out);
+    if (pairs)
+        hipLaunchKernelGGL(k_dupdate2, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, ws.coef, u, w,
+                           kind == DCGS_FIRST ? nullptr : q_out, kind == DCGS_LAST ? nullptr : u_out);
+    else
+        hipLaunchKernelGGL(k_dupdate, dim3(nb), dim3(BS), 0, s, V, ldv, n, jq, ws.coef, u, w,
+                           kind == DCGS_FIRST ? nullptr : q_out, kind == DCGS_LAST ? nullptr : u_out);
     PPA_HIP(hipGetLastError());
 }
 
