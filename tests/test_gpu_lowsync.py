@@ -38,13 +38,15 @@ def test_lowsync_laplacian_counters_and_values(lib):
     assert np.all(res <= 1e-8 * A.norm_inf * 1.01)
 
 
-def test_lowsync_trajectory_matches_oracle_and_default(lib):
-    """Convection-diffusion 40x40 (beta*h = 0.6), d = 3, Arnoldi(16,6), the
-    oracle's roots: after 1, 3 and 6 cycles the wanted Ritz values of pi(A),
-    the Rayleigh quotients and the residuals equal the oracle's delayed-form
-    run and the device's default Gram-Schmidt run (the same Arnoldi
-    decomposition in exact arithmetic; restarts included)."""
-    csr = W.convdiff_2d(40, 0.6)
+@pytest.mark.parametrize("side", [40, 39])
+def test_lowsync_trajectory_matches_oracle_and_default(lib, side):
+    """Convection-diffusion 40x40 and 39x39 (beta*h = 0.6; even and odd n,
+    so both the row-pair and the single-row kernels run), d = 3,
+    Arnoldi(16,6), the oracle's roots: after 1, 3 and 6 cycles the wanted
+    Ritz values of pi(A), the Rayleigh quotients and the residuals equal the
+    oracle's delayed-form run and the device's default Gram-Schmidt run (the
+    same Arnoldi decomposition in exact arithmetic; restarts included)."""
+    csr = W.convdiff_2d(side, 0.6)
     b, v0 = W.start_vectors(csr.n, 3)
     roots, _ = O.gmres_poly(O.csr_matvec(csr), b, 3)
     A = lib.Matrix(csr)
