@@ -156,3 +156,18 @@ def test_host_stability_roots_match_oracle(cdll):
     assert np.array_equal(S2.roots(2), O.add_stability_roots(r2)[0])
     S1, added1 = D.stabilized(level=1)
     assert added1 == 0 and np.array_equal(S1.roots(2), r2)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/ppa.h compiles as C99 and as C++ on its own (no HIP or torch
+    types in the boundary)."""
+    import shutil
+    import subprocess
+    for compiler, std, ext in (("gcc", "-std=c99", "c"), ("g++", "-std=c++17", "cpp")):
+        if shutil.which(compiler) is None:
+            pytest.skip(f"{compiler} not available")
+        src = tmp_path / f"use_header.{ext}"
+        src.write_text('#include "ppa.h"\nint main(void) { return ppa_abi_version() == 1 ? 0 : 1; }\n')
+        p = subprocess.run([compiler, std, "-Wall", "-Werror", "-fsyntax-only", "-I",
+                            os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+        assert p.returncode == 0, p.stderr
