@@ -502,9 +502,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         const int nw = R.nw;
         PPA_HIP(hipMemcpyAsync(e.Qd, R.Gw.data(), R.Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
         launch_gemm_tall(n, mc, R.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);
-        for (int cc = 0; cc < R.ycols; ++cc)
-            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, e.Y + (size_t)cc * e.ld, 0.0,
-                              nullptr, 0.0, nullptr, e.AY + (size_t)cc * e.ld, s);
+        launch_spmm_cols(A, e.Y, e.ld, R.ycols, e.AY, s);
         const std::vector<DotSpec> dspec = ritz_dots(R);
         std::vector<double> dv(dspec.size());
         for (size_t off = 0; off < dspec.size(); off += MAX_DOTS) {

@@ -158,6 +158,7 @@ struct Matrix {
     int4* bm_s = nullptr;            // partition into SPMV_CHUNK_S-nonzero blocks
     int64_t nblocks_s = 0;
     int blk64 = 0, blk32 = 0;        // plain kernel block shape per value type: 0 large, 1 small
+    bool long_s = false;             // a row needs a block of its own in the small partition
     double norm_inf = 0.0;
     int device = 0;
     Window win64, win32;
@@ -211,6 +212,12 @@ enum class VecT { F64, F32 };
 // indices, int32 row pointers), each distinct input vector once, the output once.
 size_t fused_spmv_bytes(const Matrix& A, VecT in, VecT out, const void* x, const void* u,
                         const void* z, const void* z2);
+// AY = A Y for the ncols columns of the column-major FP64 block Y (leading
+// dimension ld, shared by AY); each column equals the single-column FP64
+// pass out = A y bit for bit.  Rows that need a block of their own in the
+// small partition send the whole call to the single-column kernel.
+void launch_spmm_cols(const Matrix& A, const double* Y, int64_t ld, int ncols, double* AY,
+                      hipStream_t s);
 size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
                        double beta, const void* u, double gamma, const void* z, double delta,
                        const void* z2, void* o, hipStream_t s);

@@ -592,6 +592,80 @@ __global__ __launch_bounds__(BS) void k_fused_spmv_ring(
         });
 }
 
+// A Y for up to K columns of a column-major block Y (leading dimension ld)
+// in one pass over the matrix, on the small partition (blocks of
+// SPMV_CHUNK_S nonzeros, SPMV_BS_S threads): each nonzero gathers its value
+// from each column, the products are staged per column and every row is
+// summed in column order as in the single-column kernel, so each column of
+// the result equals that kernel's pass (out = A y) bit for bit.  The caller
+// ensures that no row needs a block of its own (rows of at most
+// SPMV_CHUNK_S nonzeros).
+template <int K>
+__global__ __launch_bounds__(SPMV_BS_S) void k_spmm_cols(const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const double* __restrict__ val,
+                                                         const int4* __restrict__ bm, int nblk,
+                                                         const double* __restrict__ Y, int64_t ld,
+                                                         int kc, double* __restrict__ AY) {
+    constexpr int BS = SPMV_BS_S, CH = SPMV_CHUNK_S, PER = CH / BS;
+    __shared__ double prod[K][CH];
+    const int b = xcd_remap(blockIdx.x, nblk);
+    const int4 m = bm[b];
+    const int r0 = m.x, r1 = m.y, p0 = m.z, p1 = m.w;
+    const int tid = threadIdx.x;
+    const int cnt = p1 - p0, last = p1 - 1;
+    if (cnt > 0) {
+        int32_t c[PER];
+        double v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int j = min(p0 + tid + k * BS, last);
+            c[k] = colind[j];
+            v[k] = val[j];
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            if (q < kc) {
+                const double* y = Y + (int64_t)q * ld;
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int i = tid + k * BS;
+                    prod[q][i] = i < cnt ? v[k] * y[c[k]] : 0.0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = r0 + tid; r < r1; r += BS) {
+        RowPre<double> pre;
+        pre.a = rowptr[r];
+        pre.e = rowptr[r + 1];
+        pre.x = pre.z = pre.z2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (q < kc)
+                row_out<CP_KEEP>(pre, prod[q], p0, r, AY + (int64_t)q * ld, 0.0, 1.0, 0.0, 0.0);
+    }
+}
+
+void launch_spmm_cols(const Matrix& A, const double* Y, int64_t ld, int ncols, double* AY,
+                      hipStream_t s) {
+    if (A.nnz == 0 || A.long_s || A.nblocks_s == 0 || ncols <= 1) {
+        for (int c = 0; c < ncols; ++c)
+            launch_fused_spmv(A, VecT::F64, VecT::F64, 0.0, nullptr, 1.0, Y + (size_t)c * ld, 0.0,
+                              nullptr, 0.0, nullptr, AY + (size_t)c * ld, s);
+        return;
+    }
+    constexpr int K = 4;
+    for (int c0 = 0; c0 < ncols; c0 += K) {
+        const int kc = std::min(K, ncols - c0);
+        hipLaunchKernelGGL(k_spmm_cols<K>, dim3((unsigned)A.nblocks_s), dim3(SPMV_BS_S), 0, s, A.rowptr,
+                           A.colind, A.v64, A.bm_s, (int)A.nblocks_s, Y + (size_t)c0 * ld, ld, kc,
+                           AY + (size_t)c0 * ld);
+        PPA_HIP(hipGetLastError());
+    }
+}
+
 template <typename VT>
 constexpr int win_chunk() {
     return sizeof(VT) == 4 ? SPMV_WCHUNK_F32 : SPMV_WCHUNK_F64;
@@ -1153,8 +1227,10 @@ void matrix_setup(Matrix& A, hipStream_t s) {
     PPA_HIP(hipStreamSynchronize(s));
     // the small-block partition (the setup timing may choose it)
     {
-        std::vector<int32_t> bs = partition(rp, n, SPMV_CHUNK_S, SPMV_CHUNK_S, A.align, nullptr);
+        bool lg_s = false;
+        std::vector<int32_t> bs = partition(rp, n, SPMV_CHUNK_S, SPMV_CHUNK_S, A.align, &lg_s);
         A.nblocks_s = (int64_t)bs.size() - 1;
+        A.long_s = lg_s;
         std::vector<int32_t> rs(4 * std::max<int64_t>(A.nblocks_s, 1), 0);
         for (int64_t b = 0; b < A.nblocks_s; ++b) {
             rs[4 * b] = bs[b];
