@@ -592,7 +592,7 @@ __global__ __launch_bounds__(BS) void k_fused_spmv_ring(
         });
 }
 
-// A Y for up to K columns of a column-major block Y (leading dimension ld)
+// A Y for K columns of a column-major block Y (leading dimension ld)
 // in one pass over the matrix, on the small partition (blocks of
 // SPMV_CHUNK_S nonzeros, SPMV_BS_S threads): each nonzero gathers its value
 // from each column, the products are staged per column and every row is
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(SPMV_BS_S) void k_spmm_cols(const int32_t* __restri
                                                          const double* __restrict__ val,
                                                          const int4* __restrict__ bm, int nblk,
                                                          const double* __restrict__ Y, int64_t ld,
-                                                         int kc, double* __restrict__ AY) {
+                                                         double* __restrict__ AY) {
     constexpr int BS = SPMV_BS_S, CH = SPMV_CHUNK_S, PER = CH / BS;
     __shared__ double prod[K][CH];
     const int b = xcd_remap(blockIdx.x, nblk);
@@ -623,17 +623,19 @@ __global__ __launch_bounds__(SPMV_BS_S) void k_spmm_cols(const int32_t* __restri
             c[k] = colind[j];
             v[k] = val[j];
         }
+        // every gather of the K columns is issued before the first is used
+        double g[K][PER];
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            if (q < kc) {
-                const double* y = Y + (int64_t)q * ld;
+        for (int q = 0; q < K; ++q)
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int i = tid + k * BS;
-                    prod[q][i] = i < cnt ? v[k] * y[c[k]] : 0.0;
-                }
+            for (int k = 0; k < PER; ++k) g[q][k] = Y[(int64_t)q * ld + c[k]];
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int i = tid + k * BS;
+                prod[q][i] = i < cnt ? v[k] * g[q][k] : 0.0;
             }
-        }
     }
     __syncthreads();
     for (int r = r0 + tid; r < r1; r += BS) {
@@ -643,8 +645,7 @@ __global__ __launch_bounds__(SPMV_BS_S) void k_spmm_cols(const int32_t* __restri
         pre.x = pre.z = pre.z2 = 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q)
-            if (q < kc)
-                row_out<CP_KEEP>(pre, prod[q], p0, r, AY + (int64_t)q * ld, 0.0, 1.0, 0.0, 0.0);
+            row_out<CP_KEEP>(pre, prod[q], p0, r, AY + (int64_t)q * ld, 0.0, 1.0, 0.0, 0.0);
     }
 }
 
@@ -656,12 +657,18 @@ void launch_spmm_cols(const Matrix& A, const double* Y, int64_t ld, int ncols, d
                               nullptr, 0.0, nullptr, AY + (size_t)c * ld, s);
         return;
     }
-    constexpr int K = 4;
-    for (int c0 = 0; c0 < ncols; c0 += K) {
-        const int kc = std::min(K, ncols - c0);
-        hipLaunchKernelGGL(k_spmm_cols<K>, dim3((unsigned)A.nblocks_s), dim3(SPMV_BS_S), 0, s, A.rowptr,
-                           A.colind, A.v64, A.bm_s, (int)A.nblocks_s, Y + (size_t)c0 * ld, ld, kc,
-                           AY + (size_t)c0 * ld);
+    for (int c0 = 0; c0 < ncols; c0 += 4) {
+        const int kc = std::min(4, ncols - c0);
+        const dim3 g((unsigned)A.nblocks_s), b(SPMV_BS_S);
+        const double* y = Y + (size_t)c0 * ld;
+        double* ay = AY + (size_t)c0 * ld;
+        const int nb = (int)A.nblocks_s;
+        switch (kc) {
+        case 4: hipLaunchKernelGGL(k_spmm_cols<4>, g, b, 0, s, A.rowptr, A.colind, A.v64, A.bm_s, nb, y, ld, ay); break;
+        case 3: hipLaunchKernelGGL(k_spmm_cols<3>, g, b, 0, s, A.rowptr, A.colind, A.v64, A.bm_s, nb, y, ld, ay); break;
+        case 2: hipLaunchKernelGGL(k_spmm_cols<2>, g, b, 0, s, A.rowptr, A.colind, A.v64, A.bm_s, nb, y, ld, ay); break;
+        default: hipLaunchKernelGGL(k_spmm_cols<1>, g, b, 0, s, A.rowptr, A.colind, A.v64, A.bm_s, nb, y, ld, ay); break;
+        }
         PPA_HIP(hipGetLastError());
     }
 }
