@@ -289,8 +289,8 @@ int ppa_fused_spmv(const ppa_matrix* A, int in_f32, int out_f32, double alpha,
                    void* stream);
 
 /* ------------------------------------------------------------------------
- * Classical Gram-Schmidt with one reorthogonalisation pass (section 4: each
- * orthogonalisation step is followed by a pass of reorthogonalisation).
+ * Classical Gram-Schmidt with one reorthogonalisation pass (section 4: every
+ * projection step is repeated once against the same basis).
  *   V_d  double, n x (j) column-major, leading dimension ldv >= n, orthonormal
  *   w_d  double[n] (overwritten with the orthogonalised, unnormalised vector)
  *   h    host double[j+1]: h[0..j-1] = V^T w over both passes, h[j] = ||w_out||

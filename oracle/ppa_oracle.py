@@ -74,16 +74,20 @@ def csr_matvec(csr):
 
 def infnorm(csr) -> float:
     """||A||_inf, the largest absolute row sum (reading of the norm in
-    rtol = ||A|| 1e-8, section 4)."""
-    a = np.abs(np.asarray(csr.vals, dtype=np.float64))
-    rs = np.add.reduceat(a, csr.rowptr[:-1]) if csr.nnz else np.zeros(csr.n)
-    rs[np.diff(csr.rowptr) == 0] = 0.0
-    return float(rs.max()) if csr.n else 0.0
+    rtol = ||A|| 1e-8, section 4).  Each stored entry is added to the sum of
+    the row it belongs to, so empty rows (first, interior or last) sum to 0."""
+    n = int(csr.n)
+    if n == 0:
+        return 0.0
+    rp = np.asarray(csr.rowptr, dtype=np.int64)
+    row_of_entry = np.repeat(np.arange(n), np.diff(rp))
+    a = np.abs(np.asarray(csr.vals, dtype=np.float64)[: rp[-1]])
+    rs = np.bincount(row_of_entry, weights=a, minlength=n)
+    return float(rs.max())
 
 
 # --------------------------------------------------------------------------
-# Gram-Schmidt with one reorthogonalisation pass (section 4: "each
-# orthogonalization step is followed by a pass of reorthogonalization")
+# Classical Gram-Schmidt with one reorthogonalisation pass (section 4)
 # --------------------------------------------------------------------------
 def cgs2(V: np.ndarray, w: np.ndarray, cnt: Counters | None = None):
     """Classical Gram-Schmidt twice against the columns of V.

@@ -67,6 +67,25 @@ def matrices():
 MATS = matrices()
 
 
+@pytest.mark.parametrize("name", list(MATS) + ["holes"])
+def test_norm_inf_matches_oracle(lib, name):
+    """The device's ||A||_inf (ppa_matrix_info, which sets rtol * ||A||) equals
+    the oracle's largest absolute row sum, with empty first, interior and
+    last rows and a row longer than one block."""
+    if name == "holes":
+        rng = np.random.default_rng(3)
+        B = rng.standard_normal((300, 300)) * (rng.random((300, 300)) < 0.05)
+        B[[0, 150, 299], :] = 0.0
+        csr = W.dense_csr(B)
+    else:
+        csr = MATS[name]
+    A = lib.Matrix(csr)
+    ref = O.infnorm(csr)
+    # two sums of the same nonnegative terms in possibly different orders
+    rowlen = max(1, int(np.diff(csr.rowptr).max()))
+    assert abs(A.norm_inf - ref) <= rowlen * EPS64 * ref
+
+
 @pytest.mark.parametrize("name", list(MATS))
 def test_fused_spmv_fp64(lib, name):
     csr = MATS[name]
