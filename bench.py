@@ -5,6 +5,10 @@ One step = one whole solve on the device: GMRES polynomial construction
 (degree d, or d1 x d2 for the double polynomial), then thick-restarted
 Arnoldi(m, k) on pi(A) until the nev wanted pairs meet rtol * ||A||_inf (or
 the cycle cap).  Inputs are seeded synthetic matrices already resident in HBM.
+The default workload is the 3-D convection-diffusion operator on 160^3
+(n = 4,096,000; one FP64 pass moves 424 MB, more than the 256 MB last-level
+cache) with the double polynomial 10 x 20, solved in FP64; the mixed-precision
+solve of the same problem is timed beside it.
 
 Prints one JSON line: `value` is the whole-job pi(A)v throughput (algorithmic
 bytes of every fused SpMV pass of the operator applications in the timed
@@ -231,6 +235,45 @@ def lowsync_report(A, P, bt, vt, cfg, prec, max_cycles):
     return out
 
 
+def cache_resident_report(name, steps, max_cycles):
+    """A second configuration whose fused pass fits the 256 MB last-level
+    cache (the 2-D operator at n = 1e6: 80-88 MB per pass): the same step as
+    the headline (polynomial build plus solve, FP64), timed on its own.  Its
+    kernel bandwidth is served from that cache, so it is no HBM evidence."""
+    import torch
+    from paper_1806_08020_amd import ppa
+    from paper_1806_08020_amd import workloads as W
+    cfg = CONFIGS[name]
+    csr = make_matrix(cfg)
+    b, v0 = W.start_vectors(csr.n, cfg["seed"])
+    A = ppa.Matrix(csr)
+    bt, vt = torch.as_tensor(b, device="cuda"), torch.as_tensor(v0, device="cuda")
+
+    def step():
+        P = ppa.Poly.build(A, cfg["d"], bt)
+        return ppa.eigs(A, P, vt, cfg["m"], cfg["k"], cfg["nev"], rtol=1e-8, max_cycles=max_cycles,
+                        timing=True)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pib = sum(r.spmv_bytes for r in rs)
+    ta = sum(r.t_apply_ms for r in rs) / 1e3
+    npass = sum(r.spmv_passes for r in rs)
+    return {"workload": cfg["desc"], "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
+            "pi_bytes_GBps": round(pib / wall / 1e9, 1),
+            "kernel_GBps": round(pib / ta / 1e9, 1), "kernel_frac_of_hbm_peak": round(pib / ta / 1e9 / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(ta / npass * 1e6, 3), "bytes_per_launch": round(pib / npass),
+            "cache_policy": A.cache_policy("f64"), "nnz_per_block": A.spmv_blocks("f64"),
+            "eigenpairs_per_s": round(sum(r.nconv for r in rs) / wall, 2),
+            "cycles": [r.cycles for r in rs],
+            "note": "last-level-cache resident: one pass (80-88 MB) fits the 256 MB last-level cache, "
+                    "which serves it from one factor to the next; not a measure of HBM bandwidth"}
+
+
 def harmonic_report():
     """Section 4, Example 2: Arnoldi(50,20) for the 15 smallest-magnitude
     eigenvalues, rtol 1e-8, restarted with Ritz vectors and with harmonic
@@ -356,12 +399,12 @@ def served_mix_report(count, closed_only=False):
     return rep
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--max-cycles", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -379,14 +422,19 @@ def main():
                     help="override the SpMV block shape (nonzeros per block) the matrix setup chose")
     ap.add_argument("--table-d0-cycles", type=int, default=1500,
                     help="restart cycles allowed to standard Arnoldi in the Table 8.1 block")
-    ap.add_argument("--precision", default="auto", choices=("auto", "f64", "mixed"),
-                    help="run the workload's solve in this precision instead of its own (profiling)")
+    ap.add_argument("--precision", default="f64", choices=("auto", "f64", "mixed"),
+                    help="precision of the timed solve (auto: the workload's own); the other "
+                         "precision is solved once beside it")
     ap.add_argument("--lowsync", action="store_true",
                     help="headline solve with the delayed-reorthogonalisation Gram-Schmidt")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed solve: no comparison, served mix, stability, "
                          "safeguard or harmonic blocks (for profiler runs)")
-    args = ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def main():
+    args = parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs the solver on one GPU only (no multi-GPU path): --gpus must be 1"}))
         sys.exit(2)
@@ -525,6 +573,8 @@ def main():
                     "non-normal operator the two runs may certify different pseudo-eigenvalues",
         }
     if not args.headline_only:
+        if args.config != "c2":
+            line["c2_cache_resident"] = cache_resident_report("c2", 3, args.max_cycles)
         line["lowsync"] = lowsync_report(A, P, bt, vt, cfg, prec, args.max_cycles)
         line["stability"] = stability_report(P, dbl)
         line["safeguards"] = safeguards_report()

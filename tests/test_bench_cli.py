@@ -30,3 +30,14 @@ def test_configs_build_their_workloads():
     c3 = bench.CONFIGS["c3"]
     assert c3["d"] == (10, 20) and c3["precision"] == "mixed"
     assert bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_default_headline_is_the_3d_operator_in_fp64():
+    # the 424 MB FP64 pass of the 160^3 operator exceeds the 256 MB last-level
+    # cache, so the default line measures HBM; the mixed solve runs beside it
+    import bench
+    a = bench.parse_args([])
+    assert a.config == "c3" and a.precision == "f64" and a.gpus == 1
+    A = bench.make_matrix(bench.CONFIGS[a.config])
+    assert A.n == 160 ** 3 and A.nnz == 28_518_400
+    assert A.nnz * 12 + 4 * (A.n + 1) + 16 * A.n > 256 * 2 ** 20
