@@ -271,6 +271,26 @@ int ppa_poly_apply_workspace_bytes(const ppa_matrix* A, const ppa_poly* p, int p
 int ppa_poly_apply(const ppa_matrix* A, const ppa_poly* p, int precision,
                    const void* v_d, void* y_d, void* ws_d, size_t ws_bytes, void* stream);
 
+/* Size of the static device array behind ppa_poly_apply_noalloc (64 MiB). */
+#define PPA_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* y = pi(A) v as ppa_poly_apply, for callers that cannot allocate device
+ * memory and cannot bring a workspace (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc).  The chain's temporaries
+ * (ppa_poly_apply_workspace_bytes of them) live in a static device array of
+ * PPA_NOALLOC_SCRATCH_BYTES per device, which the library holds until the
+ * process ends; the call allocates nothing.  Same kernels and results as
+ * ppa_poly_apply.  Limits: the workspace must fit the array (FP64: 4 n-vectors
+ * for a single polynomial, 6 for a double one, 7 for a shifted double one;
+ * FP32 half the bytes), else PPA_ERR_WORKSPACE and nothing is launched.
+ * The current device must be the matrix's.  Every call on one device shares
+ * that device's array: calls that overlap on one device (two streams, or two
+ * host threads) race on it and must be serialised by the caller.
+ * Asynchronous on `stream`; the first call on a device looks the array's
+ * device address up (hipGetSymbolAddress). */
+int ppa_poly_apply_noalloc(const ppa_matrix* A, const ppa_poly* p, int precision,
+                           const void* v_d, void* y_d, void* stream);
+
 /* Algorithmic HBM bytes of one ppa_poly_apply in `precision`, summed over its
  * fused passes: the CSR arrays once per pass (values, int32 column indices,
  * int32 row pointers), each distinct input vector once and the output once.

@@ -3,6 +3,7 @@
 // for ppa_last_error() (thread-local).
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 #include "ppa_internal.hpp"
 
@@ -583,3 +584,69 @@ int ppa_leja_order(int n, double* re, double* im) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free apply
+// The polynomial chain's temporaries of ppa_poly_apply_noalloc live in one
+// file-scope device array (each device that runs the call holds its own copy
+// until the process ends).  Host code never passes the array's name to a
+// kernel or a copy: it is only a host-side stand-in.  The device address is
+// looked up once per device, with that device current, and cached.
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[PPA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_on_current_device() {
+    int dev = 0;
+    PPA_HIP(hipGetDevice(&dev));
+    PPA_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        PPA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        PPA_REQUIRE(ptr != nullptr, "no device address for the static scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int ppa_poly_apply_noalloc(const ppa_matrix* h, const ppa_poly* ph, int precision,
+                                      const void* v_d, void* y_d, void* stream) {
+    return guarded([&] {
+        PPA_REQUIRE(h && ph && v_d && y_d, "matrix, poly, v and y are required");
+        PPA_REQUIRE(v_d != y_d, "v and y must not alias");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be F64 or F32");
+        const Matrix& A = *reinterpret_cast<const Matrix*>(h);
+        const Poly& p = *reinterpret_cast<const Poly*>(ph);
+        const VecT t = precision == PPA_F64 ? VecT::F64 : VecT::F32;
+        // size check first, on the host: nothing is launched for a request
+        // that does not fit
+        {
+            Carver dry(nullptr, 0);
+            ApplyWs probe;
+            carve_apply(dry, A.n, p, t, probe);
+            if (dry.bytes() > (size_t)PPA_NOALLOC_SCRATCH_BYTES)
+                fail(PPA_ERR_WORKSPACE,
+                     "ppa_poly_apply_noalloc: needs %zu bytes of scratch, the static array holds %zu "
+                     "(use ppa_poly_apply with a workspace)",
+                     dry.bytes(), (size_t)PPA_NOALLOC_SCRATCH_BYTES);
+        }
+        int dev = 0;
+        PPA_HIP(hipGetDevice(&dev));
+        PPA_REQUIRE(dev == A.device, "the current device (%d) is not the matrix's (%d)", dev, A.device);
+        void* base = scratch_on_current_device();
+        Carver c(base, PPA_NOALLOC_SCRATCH_BYTES);
+        ApplyWs aw;
+        carve_apply(c, A.n, p, t, aw);
+        c.check();
+        // every temporary of the chain is written by a pass before any pass
+        // reads it, so the previous call's contents need no clearing
+        apply_poly(A, p, t, v_d, t, y_d, t, aw, (hipStream_t)stream);
+        return PPA_OK;
+    });
+}

@@ -96,6 +96,7 @@ def _load():
         "ppa_poly_apply_workspace_bytes": (i, [vp, vp, i, P(sz)]),
         "ppa_poly_apply": (i, [vp, vp, i, vp, vp, vp, sz, vp]),
         "ppa_poly_apply_bytes": (i, [vp, vp, i, P(d)]),
+        "ppa_poly_apply_noalloc": (i, [vp, vp, i, vp, vp, vp]),
         "ppa_fused_spmv": (i, [vp, i, i, d, vp, d, vp, d, vp, d, vp, vp, vp]),
         "ppa_cgs2_workspace_bytes": (i, [i64, i, P(sz)]),
         "ppa_cgs2": (i, [i64, i, vp, i64, vp, P(d), P(d), vp, sz, vp]),
@@ -356,6 +357,21 @@ def apply(A: Matrix, p: Poly, v: torch.Tensor, precision: str = "f64", out=None,
     if ws is None:
         ws = apply_workspace(A, p, precision)
     _check(_lib.ppa_poly_apply(A.h, p.h, prec, _ptr(v), _ptr(y), _ptr(ws), ws.numel(), _stream()))
+    return y
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def apply_noalloc(A: Matrix, p: Poly, v: torch.Tensor, precision: str = "f64", out=None):
+    """y = pi(A) v through ppa_poly_apply_noalloc: the chain's temporaries live
+    in the library's static per-device scratch array (no workspace)."""
+    prec = _PREC[precision]
+    dt = torch.float64 if prec == PPA_F64 else torch.float32
+    if v.dtype != dt or not v.is_cuda or v.numel() != A.n:
+        raise ValueError("v must be a contiguous device vector of length n and matching dtype")
+    y = torch.empty_like(v) if out is None else out
+    _check(_lib.ppa_poly_apply_noalloc(A.h, p.h, prec, _ptr(v), _ptr(y), _stream()))
     return y
 
 
