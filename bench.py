@@ -36,14 +36,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # the factors the same counters give for a plain 2 GiB device copy (FETCH_SIZE
 # reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config and
 # by the hash of the plain kernel's source (spmv.hip up to the windowed
-# variant) the counters were taken on, by the cache policy and by the block
-# shape (nonzeros per block): any change of that kernel makes the entry stale
-# and the field null.
+# variant) the counters were taken on, by the cache policy, by the block
+# shape (nonzeros per block) and by the use of column runs: any change of that
+# kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
-    ("c2", "9f058091bdec7e59", "keep", 256): {"fetch_kib": 36809.45, "write_kib": 7812.65,
-                                             "fetch_factor": 2.0, "write_factor": 1.0},
-    ("c2", "9f058091bdec7e59", "keep", 2048): {"fetch_kib": 36548.35, "write_kib": 7817.07,
-                                              "fetch_factor": 2.0, "write_factor": 1.0},
+    ("c2", "9f058091bdec7e59", "keep", 256, False): {"fetch_kib": 36809.45, "write_kib": 7812.65,
+                                                    "fetch_factor": 2.0, "write_factor": 1.0},
+    ("c2", "9f058091bdec7e59", "keep", 2048, False): {"fetch_kib": 36548.35, "write_kib": 7817.07,
+                                                     "fetch_factor": 2.0, "write_factor": 1.0},
 }
 
 CONFIGS = {
@@ -268,6 +268,7 @@ def cache_resident_report(name, steps, max_cycles):
             "kernel_GBps": round(pib / ta / 1e9, 1), "kernel_frac_of_hbm_peak": round(pib / ta / 1e9 / HBM_PEAK_GBS, 4),
             "avg_launch_us": round(ta / npass * 1e6, 3), "bytes_per_launch": round(pib / npass),
             "cache_policy": A.cache_policy("f64"), "nnz_per_block": A.spmv_blocks("f64"),
+            "column_runs": A.spmv_runs("f64")[0],
             "eigenpairs_per_s": round(sum(r.nconv for r in rs) / wall, 2),
             "cycles": [r.cycles for r in rs],
             "note": "last-level-cache resident: one pass (80-88 MB) fits the 256 MB last-level cache, "
@@ -418,6 +419,8 @@ def parse_args(argv=None):
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--cache-policy", default="auto", choices=("auto", "stream", "keep", "keep_ntst"),
                     help="override the SpMV cache policy the matrix setup chose (for counter runs)")
+    ap.add_argument("--runs", default="auto", choices=("auto", "on", "off"),
+                    help="override the use of column runs the matrix setup chose (on: built and forced)")
     ap.add_argument("--spmv-blocks", default="auto", choices=("auto", "2048", "256"),
                     help="override the SpMV block shape (nonzeros per block) the matrix setup chose")
     ap.add_argument("--table-d0-cycles", type=int, default=1500,
@@ -453,7 +456,11 @@ def main():
     csr = make_matrix(cfg)
     b, v0 = W.start_vectors(csr.n, cfg["seed"])
     prec = cfg["precision"] if args.precision == "auto" else args.precision
-    A = ppa.Matrix(csr, want_f32=(prec != "f64"))
+    A = ppa.Matrix(csr, want_f32=(prec != "f64"), window="runs" if args.runs == "on" else "auto")
+    if args.runs == "off":
+        for pk in (("f64", "f32") if prec != "f64" else ("f64",)):
+            if A.spmv_runs(pk)[0]:
+                A.set_spmv_runs(False, pk)
     if args.cache_policy != "auto":
         A.set_cache_policy(args.cache_policy, "f32" if prec == "mixed" else "f64")
     if args.spmv_blocks != "auto":
@@ -500,7 +507,8 @@ def main():
     khash = hashlib.sha256(ksrc[:ksrc.index("// Windowed variant:")].encode()).hexdigest()[:16]
     policy = A.cache_policy("f32" if prec == "mixed" else "f64")
     blocks = A.spmv_blocks("f32" if prec == "mixed" else "f64")
-    tr = MEASURED_TRAFFIC.get((args.config, khash, policy, blocks))
+    runs_on, runs_blocks = A.spmv_runs("f32" if prec == "mixed" else "f64")
+    tr = MEASURED_TRAFFIC.get((args.config, khash, policy, blocks, runs_on))
     traffic = (round(1024 * (tr["fetch_kib"] * tr["fetch_factor"] + tr["write_kib"] * tr["write_factor"]))
                if tr else None)
     line = {
@@ -535,6 +543,7 @@ def main():
         "roofline": {"kernel": "k_fused_spmv", "bound": "hbm",
                      "spmv_variant": A.spmv_variant("f32" if prec == "mixed" else "f64"),
                      "cache_policy": policy, "nnz_per_block": blocks,
+                     "column_runs": runs_on, "blocks_with_runs": runs_blocks, "blocks": A.nblocks,
                      "achieved": round(kern_gbs, 1) if kern_gbs else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4) if kern_gbs else None,
                      "traffic": traffic, "bytes_per_launch": round(pi_bytes / max(passes, 1)),

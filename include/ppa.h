@@ -97,6 +97,9 @@ const char* ppa_last_error(void);
                                        policy, large blocks, no staged variant
                                        unless forced (for matrices used briefly,
                                        where the timing would not pay)           */
+#define PPA_MATRIX_RUNS_FORCE 32    /* build the column runs of the plain kernel's
+                                       large blocks and use them (both value
+                                       types), see ppa_matrix_spmv_runs          */
 int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
                       const double* val64_d, const float* val32_d, int flags,
                       void* stream, ppa_matrix** out);
@@ -142,6 +145,25 @@ int ppa_matrix_set_cache_policy(ppa_matrix* A, int precision, int policy);
  * 3% gain; the setter overrides (PPA_ERR_INVALID for another value). */
 int ppa_matrix_spmv_blocks(const ppa_matrix* A, int precision, int* nnz_per_block);
 int ppa_matrix_set_spmv_blocks(ppa_matrix* A, int precision, int nnz_per_block);
+
+/* Column runs of the plain kernel (large blocks).  The columns one row block
+ * gathers form a few contiguous runs for stencil and band matrices (a 3-D
+ * 7-point stencil: three runs, the planes below and above and the rows
+ * around the block).  With runs on, each block copies its runs of the
+ * gathered vector into LDS with 16-byte loads issued together with the
+ * matrix stream, so no gather waits for a column index to arrive from
+ * memory; blocks with more than 7 runs, or more than 10 KB of them in the
+ * value type, gather from memory as without.  Results are bitwise those of
+ * the plain kernel.  The runs are built at creation by PPA_MATRIX_RUNS_FORCE
+ * or by the creation timing on large matrices (which then times them with
+ * the three cache policies and keeps them only for a 3% gain).
+ * *on receives 1 when the plain kernel of `precision` uses them.  The setter
+ * turns them on (1; the large block shape is then used) or off (0);
+ * PPA_ERR_INVALID when they were not built.  It must not race with launches
+ * that use A.  *blocks_with_runs (may be NULL) receives how many large blocks
+ * have runs that fit the LDS budget of that value type. */
+int ppa_matrix_spmv_runs(const ppa_matrix* A, int precision, int* on, int64_t* blocks_with_runs);
+int ppa_matrix_set_spmv_runs(ppa_matrix* A, int precision, int on);
 
 /* ------------------------------------------------------------------------
  * Polynomial pi in factored form, eq. (2.1): pi(z) = prod_i (1 - z/theta_i),

@@ -80,9 +80,13 @@ int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_
             }
             PPA_REQUIRE(!((flags & PPA_MATRIX_WINDOW_FORCE) && (flags & PPA_MATRIX_RING_FORCE)),
                         "PPA_MATRIX_WINDOW_FORCE and PPA_MATRIX_RING_FORCE exclude each other");
+            PPA_REQUIRE(!((flags & PPA_MATRIX_RUNS_FORCE) &&
+                          (flags & (PPA_MATRIX_WINDOW_FORCE | PPA_MATRIX_RING_FORCE | PPA_MATRIX_WINDOW_OFF))),
+                        "PPA_MATRIX_RUNS_FORCE excludes the other SpMV variant flags");
             const int wmode = (flags & PPA_MATRIX_WINDOW_OFF)     ? -1
                               : (flags & PPA_MATRIX_WINDOW_FORCE) ? 1
                               : (flags & PPA_MATRIX_RING_FORCE)   ? 2
+                              : (flags & PPA_MATRIX_RUNS_FORCE)   ? 3
                                                                   : 0;
             matrix_tune(*A, wmode, (flags & PPA_MATRIX_NO_TUNE) == 0, s);
             A->rp_host.clear();
@@ -175,6 +179,33 @@ int ppa_matrix_set_spmv_blocks(ppa_matrix* h, int precision, int nnz_per_block) 
         Matrix* A = reinterpret_cast<Matrix*>(h);
         PPA_REQUIRE(precision == PPA_F64 || A->v32, "the matrix has no FP32 values");
         (precision == PPA_F64 ? A->blk64 : A->blk32) = nnz_per_block == SPMV_CHUNK_S ? 1 : 0;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_spmv_runs(const ppa_matrix* h, int precision, int* on, int64_t* blocks_with_runs) {
+    return guarded([&] {
+        PPA_REQUIRE(h && on, "matrix and on are required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        const Matrix* A = reinterpret_cast<const Matrix*>(h);
+        const bool f64 = precision == PPA_F64;
+        *on = (A->runs.rec && (f64 ? A->runs.on64 : A->runs.on32)) ? 1 : 0;
+        if (blocks_with_runs) *blocks_with_runs = A->runs.rec ? (f64 ? A->runs.nwin64 : A->runs.nwin32) : 0;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_set_spmv_runs(ppa_matrix* h, int precision, int on) {
+    return guarded([&] {
+        PPA_REQUIRE(h, "matrix is required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        PPA_REQUIRE(on == 0 || on == 1, "on must be 0 or 1");
+        Matrix* A = reinterpret_cast<Matrix*>(h);
+        PPA_REQUIRE(precision == PPA_F64 || A->v32, "the matrix has no FP32 values");
+        PPA_REQUIRE(on == 0 || A->runs.rec, "no column runs were built for this matrix");
+        const bool f64 = precision == PPA_F64;
+        (f64 ? A->runs.on64 : A->runs.on32) = on == 1;
+        if (on) (f64 ? A->blk64 : A->blk32) = 0;
         return PPA_OK;
     });
 }

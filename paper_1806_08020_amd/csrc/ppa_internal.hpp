@@ -136,6 +136,42 @@ struct Ring {
     size_t lds_bytes = 0;
 };
 
+// Column-run windows of the plain kernel's large blocks.  The columns a block
+// gathers form a few contiguous runs for stencil and band matrices (a 3-D
+// 7-point stencil: the planes below and above and the rows around it).  Per
+// block the setup stores the runs (sorted, disjoint, starts rounded down and
+// ends up to multiples of 4 entries, gaps of at most SPMV_RUNS_GAP entries
+// bridged) as 16 ints:
+//   [0] number of runs (0: the block gathers from global memory)
+//   [1] LDS entries of all runs
+//   [2 + k] first column of run k (k < SPMV_RUNS_MAX; unused: INT32_MAX)
+//   [2 + SPMV_RUNS_MAX + k - 1] LDS offset of run k, k >= 1 (unused: INT32_MAX)
+// The block copies its runs of u into LDS with 16-byte loads issued together
+// with its matrix stream (they do not wait for the column indices), then
+// reads every gathered entry from LDS.  A block whose runs exceed
+// SPMV_RUNS_LDS bytes in the value type gathers from global memory.
+#ifndef PPA_SPMV_RUNS_MAX
+#define PPA_SPMV_RUNS_MAX 7
+#endif
+#ifndef PPA_SPMV_RUNS_LDS
+#define PPA_SPMV_RUNS_LDS 10240
+#endif
+#ifndef PPA_SPMV_RUNS_GAP
+#define PPA_SPMV_RUNS_GAP 16
+#endif
+constexpr int SPMV_RUNS_MAX = PPA_SPMV_RUNS_MAX;
+constexpr int SPMV_RUNS_LDS = PPA_SPMV_RUNS_LDS;
+constexpr int SPMV_RUNS_GAP = PPA_SPMV_RUNS_GAP;
+constexpr int SPMV_RUNS_REC = 16;
+static_assert(2 + 2 * SPMV_RUNS_MAX - 1 <= SPMV_RUNS_REC, "run record holds 16 ints");
+
+struct Runs {
+    int32_t* rec = nullptr;          // device, SPMV_RUNS_REC ints per large block
+    int64_t nblocks = 0;
+    int64_t nwin64 = 0, nwin32 = 0;  // blocks whose runs fit the LDS budget per value type
+    bool on64 = false, on32 = false; // the plain large-block kernel uses them
+};
+
 // The windowed and sliding-window variants are timed at matrix creation only
 // when the plain kernel's tuned pass runs below this rate (GB/s; half the
 // MI355X HBM peak).
@@ -163,6 +199,7 @@ struct Matrix {
     int device = 0;
     Window win64, win32;
     Ring ring64, ring32;
+    Runs runs;
     std::vector<int32_t> rp_host;    // host copy of rowptr (setup only)
 };
 

@@ -33,8 +33,10 @@
 #include "ppa_internal.hpp"
 
 #include <algorithm>
-#include <type_traits>
+#include <climits>
 #include <cmath>
+#include <thread>
+#include <type_traits>
 
 // Nonzeros per lane in one load of the main kernel: FP64 values one at a
 // time, FP32 values (and their indices) as 16-byte groups of four.
@@ -215,25 +217,89 @@ __device__ __forceinline__ Grp<G, T> load_grp(const T* __restrict__ p, int idx, 
     return r;
 }
 
+// Column runs of one large block (see Runs): uniform values, read from the
+// block's 64-byte record.
+struct RunRec {
+    int nruns, wlen;
+    int st[SPMV_RUNS_MAX];   // first column of run k
+    int of[SPMV_RUNS_MAX];   // LDS offset of run k (of[0] = 0)
+};
+
+__device__ __forceinline__ RunRec load_runs(const int32_t* __restrict__ rr, int b) {
+    const int4* q = reinterpret_cast<const int4*>(rr) + (SPMV_RUNS_REC / 4) * b;
+    int t[SPMV_RUNS_REC];
+#pragma unroll
+    for (int i = 0; i < SPMV_RUNS_REC / 4; ++i) {
+        const int4 v = q[i];
+        t[4 * i] = v.x;
+        t[4 * i + 1] = v.y;
+        t[4 * i + 2] = v.z;
+        t[4 * i + 3] = v.w;
+    }
+    RunRec r;
+    r.nruns = t[0];
+    r.wlen = t[1];
+#pragma unroll
+    for (int k = 0; k < SPMV_RUNS_MAX; ++k) r.st[k] = t[2 + k];
+    r.of[0] = 0;
+#pragma unroll
+    for (int k = 1; k < SPMV_RUNS_MAX; ++k) r.of[k] = t[2 + SPMV_RUNS_MAX + k - 1];
+    return r;
+}
+
+// LDS position of column c (clamped into the window: masked lanes may hold
+// columns of a neighbouring block).  Unused runs start at INT32_MAX.
+__device__ __forceinline__ int run_pos(const RunRec& R, int c) {
+    int lp = c - R.st[0];
+#pragma unroll
+    for (int k = 1; k < SPMV_RUNS_MAX; ++k)
+        if (c >= R.st[k]) lp = c - R.st[k] + R.of[k];
+    return min(max(lp, 0), R.wlen - 1);
+}
+
+// Column held at LDS position pos (pos < wlen).  Unused offsets are INT32_MAX.
+__device__ __forceinline__ int run_col(const RunRec& R, int pos) {
+    int g = pos + R.st[0];
+#pragma unroll
+    for (int k = 1; k < SPMV_RUNS_MAX; ++k)
+        if (pos >= R.of[k]) g = pos - R.of[k] + R.st[k];
+    return g;
+}
+
 // Main fused kernel.  Each thread reads column indices and values as groups
 // of G consecutive nonzeros (16-byte loads for G = 4 and 4-byte indices);
 // groups start at the block's first nonzero rounded down to a multiple of G
 // (the partition guarantees that this aligned range holds at most CH_
-// entries, the block's nonzero budget, with BS_ threads).  Positions outside the block are masked to zero, the
-// products land in LDS at their aligned position and each thread sums whole
-// rows from an offset view.  Every load of the block is issued before the
-// first gathered value is used.
-template <typename VT, typename IT, typename OT, int G, bool EPI, int CP, int BS_, int CH_>
+// entries, the block's nonzero budget, with BS_ threads).  Positions outside
+// the block are masked to zero, the products land in LDS at their aligned
+// position and each thread sums whole rows from an offset view.  Every load
+// of the block is issued before the first gathered value is used.
+//
+// RUNS: the block's column runs of u (record rr) are copied into LDS with
+// 16-byte loads issued right after the matrix stream, and the gathers read
+// LDS; a block without a fitting record gathers from global memory.  The
+// products and sums are the same either way, so the result is bitwise that
+// of the plain form.
+template <typename VT, typename IT, typename OT, int G, bool EPI, int CP, int BS_, int CH_,
+          bool RUNS>
 __global__ __launch_bounds__(BS_) void k_fused_spmv(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-    const VT* __restrict__ val, const int4* __restrict__ bm, int nblk, int nnz,
-    const IT* __restrict__ x, const IT* __restrict__ u, const IT* __restrict__ z,
-    const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta, VT gamma, VT delta) {
+    const VT* __restrict__ val, const int4* __restrict__ bm, const int32_t* __restrict__ rr,
+    int nblk, int nnz, int n, const IT* __restrict__ x, const IT* __restrict__ u,
+    const IT* __restrict__ z, const IT* __restrict__ z2, OT* __restrict__ out, VT alpha, VT beta,
+    VT gamma, VT delta) {
     constexpr int PER = CH_ / BS_;
     static_assert(PER * BS_ == CH_, "chunk must be a multiple of the block size");
     constexpr int NG = (PER + G - 1) / G;      // groups per thread (the last may be idle)
-    // products at their aligned positions; the long-row path reuses it for its partials
-    __shared__ __align__(16) VT prod_ext[NG * G * BS_];
+    constexpr int NP = NG * G * BS_;           // product slots
+    constexpr int WMAX = RUNS ? SPMV_RUNS_LDS / (int)sizeof(VT) : 0;
+    constexpr int VW = 16 / (int)sizeof(IT);   // window entries per 16-byte load
+    constexpr int WQ = RUNS ? (WMAX / VW + BS_ - 1) / BS_ : 1;   // window loads per thread
+    // products at their aligned positions (the long-row path reuses them for
+    // its partials), then the run window
+    __shared__ __align__(16) VT lds[NP + WMAX];
+    VT* prod_ext = lds;
+    VT* win = lds + NP;
     const int b = xcd_remap(blockIdx.x, nblk);
     const int4 m = bm[b];   // rows [r0, r1), nonzeros [p0, p1): one 16-byte load
     const int r0 = m.x, r1 = m.y, p0 = m.z, p1 = m.w;
@@ -245,6 +311,47 @@ __global__ __launch_bounds__(BS_) void k_fused_spmv(
                                       beta, gamma, delta, prod_ext);
         return;
     }
+    RunRec R{};
+    bool use_win = false;
+    if constexpr (RUNS) {
+        R = load_runs(rr, b);
+        use_win = R.nruns > 0 && R.wlen <= WMAX && R.wlen > 0 && p1 > p0;
+    }
+    typedef IT ivec __attribute__((ext_vector_type(VW)));
+    ivec wv[WQ];
+    // window copy: 16-byte vectors of u, issued before the row operands; the
+    // vector index is clamped into the window (masked at the LDS store) and
+    // a vector that would pass the end of u is read element by element
+    auto load_window = [&]() {
+        if constexpr (RUNS) {
+            const int nvec = R.wlen / VW;
+#pragma unroll
+            for (int k = 0; k < WQ; ++k) {
+                const int pos = VW * min(tid + k * BS_, nvec - 1);
+                const int g = run_col(R, pos);
+                if (g + VW <= n) {
+                    wv[k] = *reinterpret_cast<const ivec*>(u + g);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) wv[k][j] = u[min(g + j, n - 1)];
+                }
+            }
+        }
+    };
+    auto store_window = [&]() {
+        if constexpr (RUNS) {
+            const int nvec = R.wlen / VW;
+#pragma unroll
+            for (int k = 0; k < WQ; ++k) {
+                const int q = tid + k * BS_;
+                if (q < nvec) {
+#pragma unroll
+                    for (int j = 0; j < VW; ++j) win[VW * q + j] = (VT)wv[k][j];
+                }
+            }
+            __syncthreads();
+        }
+    };
     const int ra = r0 + tid, rb = r0 + tid + BS_;
     RowPre<VT> qa, qb;
     if constexpr (G == 1) {
@@ -260,13 +367,20 @@ __global__ __launch_bounds__(BS_) void k_fused_spmv(
                 v[k] = stream_load<CP>(val + j);
             }
         }
+        if (use_win) load_window();
         // the thread's first two rows (clamped into the block; masked at use)
         qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
         qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), x, z, z2);
+        if (use_win) store_window();
         if (cnt > 0) {
             VT g[PER];
+            if (use_win) {
 #pragma unroll
-            for (int k = 0; k < PER; ++k) g[k] = (VT)u[c[k]];
+                for (int k = 0; k < PER; ++k) g[k] = win[run_pos(R, c[k])];
+            } else {
+#pragma unroll
+                for (int k = 0; k < PER; ++k) g[k] = (VT)u[c[k]];
+            }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int i = tid + k * BS_;
@@ -286,14 +400,23 @@ __global__ __launch_bounds__(BS_) void k_fused_spmv(
                 v[k] = load_grp<G, CP>(val, idx, full, nnz - 1);
             }
         }
+        if (use_win) load_window();
         qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
         qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), x, z, z2);
+        if (use_win) store_window();
         if (p1 > p0) {
             VT g[NG][G];
+            if (use_win) {
 #pragma unroll
-            for (int k = 0; k < NG; ++k)
+                for (int k = 0; k < NG; ++k)
 #pragma unroll
-                for (int j = 0; j < G; ++j) g[k][j] = (VT)u[c[k].v[j]];
+                    for (int j = 0; j < G; ++j) g[k][j] = win[run_pos(R, c[k].v[j])];
+            } else {
+#pragma unroll
+                for (int k = 0; k < NG; ++k)
+#pragma unroll
+                    for (int j = 0; j < G; ++j) g[k][j] = (VT)u[c[k].v[j]];
+            }
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
                 const int pos = G * (tid + k * BS_);
@@ -737,25 +860,36 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, const Rin
         const bool small = (sizeof(VT) == 8 ? A.blk64 : A.blk32) == 1;
         const int4* bm = small ? A.bm_s : A.bm;
         const int64_t nblk = small ? A.nblocks_s : A.nblocks;
+        // column-run windows: large blocks only, u 16-byte aligned
+        const bool runs = !small && A.runs.rec != nullptr &&
+                          (sizeof(VT) == 8 ? A.runs.on64 : A.runs.on32) &&
+                          reinterpret_cast<uintptr_t>(u) % 16 == 0;
         auto go = [&](auto kern, int bs) {
             hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(bs), 0, s, A.rowptr, A.colind, val,
-                               bm, (int)nblk, (int)A.nnz, (const IT*)x, (const IT*)u, (const IT*)z,
-                               (const IT*)z2, (OT*)o, (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
+                               bm, (const int32_t*)A.runs.rec, (int)nblk, (int)A.nnz, (int)A.n,
+                               (const IT*)x, (const IT*)u, (const IT*)z, (const IT*)z2, (OT*)o,
+                               (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
         };
-        auto shape = [&](auto cp, auto bsc, auto chc) {
+        auto shape = [&](auto cp, auto bsc, auto chc, auto rnc) {
             constexpr int P = decltype(cp)::value, B = decltype(bsc)::value, H = decltype(chc)::value;
+            constexpr bool RN = decltype(rnc)::value;
             if (grp)
-                epi ? go(k_fused_spmv<VT, IT, OT, G, true, P, B, H>, B)
-                    : go(k_fused_spmv<VT, IT, OT, G, false, P, B, H>, B);
+                epi ? go(k_fused_spmv<VT, IT, OT, G, true, P, B, H, RN>, B)
+                    : go(k_fused_spmv<VT, IT, OT, G, false, P, B, H, RN>, B);
             else
-                epi ? go(k_fused_spmv<VT, IT, OT, 1, true, P, B, H>, B)
-                    : go(k_fused_spmv<VT, IT, OT, 1, false, P, B, H>, B);
+                epi ? go(k_fused_spmv<VT, IT, OT, 1, true, P, B, H, RN>, B)
+                    : go(k_fused_spmv<VT, IT, OT, 1, false, P, B, H, RN>, B);
         };
         auto pick = [&](auto cp) {
             if (small)
-                shape(cp, std::integral_constant<int, SPMV_BS_S>(), std::integral_constant<int, SPMV_CHUNK_S>());
+                shape(cp, std::integral_constant<int, SPMV_BS_S>(), std::integral_constant<int, SPMV_CHUNK_S>(),
+                      std::false_type());
+            else if (runs)
+                shape(cp, std::integral_constant<int, SPMV_BS>(), std::integral_constant<int, SPMV_CHUNK>(),
+                      std::true_type());
             else
-                shape(cp, std::integral_constant<int, SPMV_BS>(), std::integral_constant<int, SPMV_CHUNK>());
+                shape(cp, std::integral_constant<int, SPMV_BS>(), std::integral_constant<int, SPMV_CHUNK>(),
+                      std::false_type());
         };
         const int cp = sizeof(VT) == 8 ? A.cp64 : A.cp32;
         if (cp == CP_KEEP)
@@ -973,6 +1107,101 @@ static std::vector<int32_t> partition(const std::vector<int32_t>& rp, int64_t n,
     }
     if (has_long) *has_long = lg;
     return blk;
+}
+
+// Column runs of every large block (the record layout is described with
+// Runs).  The column indices are copied to the host once; the blocks are
+// split over host threads.  A block's columns are sorted, joined into runs
+// (gaps of at most SPMV_RUNS_GAP entries bridged), the runs widened to
+// multiples of 4 entries (16-byte loads of FP32 or FP64 vectors) and joined
+// again where they touch.  Blocks with more runs than SPMV_RUNS_MAX, runs
+// larger than the FP32 window, or a long row keep no record.
+static void build_runs(Matrix& A, hipStream_t s) {
+    if (A.runs.rec || A.nblocks == 0 || A.nnz == 0) return;
+    const int64_t nb = A.nblocks;
+    std::vector<int4> bm(nb);
+    std::vector<int32_t> ci(A.nnz);
+    PPA_HIP(hipMemcpyAsync(bm.data(), A.bm, nb * sizeof(int4), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipMemcpyAsync(ci.data(), A.colind, A.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> rec((size_t)nb * SPMV_RUNS_REC, 0);
+    const int lim32 = SPMV_RUNS_LDS / (int)sizeof(float);
+    const int lim64 = SPMV_RUNS_LDS / (int)sizeof(double);
+    auto one = [&](int64_t b, std::vector<int32_t>& t, std::vector<int64_t>& rs) {
+        int32_t* r = &rec[(size_t)b * SPMV_RUNS_REC];
+        r[0] = r[1] = 0;
+        for (int k = 0; k < SPMV_RUNS_MAX; ++k) r[2 + k] = INT32_MAX;
+        for (int k = 1; k < SPMV_RUNS_MAX; ++k) r[2 + SPMV_RUNS_MAX + k - 1] = INT32_MAX;
+        const int p0 = bm[b].z, p1 = bm[b].w;
+        if (p1 <= p0 || p1 - p0 > SPMV_CHUNK) return;
+        t.assign(ci.begin() + p0, ci.begin() + p1);
+        std::sort(t.begin(), t.end());
+        // runs [start, end) of the sorted columns, then aligned to 4 entries
+        rs.clear();
+        int64_t st = t[0], en = (int64_t)t[0] + 1;
+        for (size_t i = 1; i < t.size(); ++i) {
+            if (t[i] <= en + SPMV_RUNS_GAP) {
+                en = std::max<int64_t>(en, (int64_t)t[i] + 1);
+            } else {
+                rs.push_back(st);
+                rs.push_back(en);
+                st = t[i];
+                en = (int64_t)t[i] + 1;
+            }
+        }
+        rs.push_back(st);
+        rs.push_back(en);
+        std::vector<int64_t> al;
+        al.reserve(rs.size());
+        for (size_t i = 0; i < rs.size(); i += 2) {
+            const int64_t a = rs[i] & ~int64_t(3), e = (rs[i + 1] + 3) & ~int64_t(3);
+            if (!al.empty() && a <= al.back())
+                al.back() = std::max(al.back(), e);
+            else {
+                al.push_back(a);
+                al.push_back(e);
+            }
+        }
+        const int nr = (int)(al.size() / 2);
+        if (nr > SPMV_RUNS_MAX) return;
+        int64_t off = 0;
+        for (int k = 0; k < nr; ++k) {
+            r[2 + k] = (int32_t)al[2 * k];
+            if (k > 0) r[2 + SPMV_RUNS_MAX + k - 1] = (int32_t)off;
+            off += al[2 * k + 1] - al[2 * k];
+        }
+        if (off > lim32) {
+            for (int k = 0; k < SPMV_RUNS_MAX; ++k) r[2 + k] = INT32_MAX;
+            for (int k = 1; k < SPMV_RUNS_MAX; ++k) r[2 + SPMV_RUNS_MAX + k - 1] = INT32_MAX;
+            return;
+        }
+        r[0] = nr;
+        r[1] = (int32_t)off;
+    };
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(
+                                                 std::min(16u, std::max(1u, std::thread::hardware_concurrency())),
+                                                 (nb + 255) / 256));
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; ++w)
+        th.emplace_back([&, w]() {
+            std::vector<int32_t> t;
+            std::vector<int64_t> rs;
+            for (int64_t b = w; b < nb; b += nt) one(b, t, rs);
+        });
+    for (auto& x : th) x.join();
+    int64_t n64 = 0, n32 = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t* r = &rec[(size_t)b * SPMV_RUNS_REC];
+        n32 += r[0] > 0;
+        n64 += r[0] > 0 && r[1] <= lim64;
+    }
+    A.runs.nblocks = nb;
+    A.runs.nwin64 = n64;
+    A.runs.nwin32 = n32;
+    if (n32 == 0) return;   // no block has usable runs: no record array
+    PPA_HIP(hipMalloc(&A.runs.rec, rec.size() * sizeof(int32_t)));
+    PPA_HIP(hipMemcpyAsync(A.runs.rec, rec.data(), rec.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PPA_HIP(hipStreamSynchronize(s));
 }
 
 // Allow every windowed kernel instance of one value type to use `bytes` of
@@ -1314,18 +1543,26 @@ void matrix_tune(Matrix& A, int mode, bool timing, hipStream_t s) {
         } else if (mode == 2) {
             A.ring64.on = A.ring64.rm != nullptr;
             A.ring32.on = A.ring32.rm != nullptr;
+        } else if (mode == 3) {
+            // column runs with the large blocks
+            A.runs.on64 = A.runs.on32 = A.runs.rec != nullptr;
+            if (A.runs.rec) A.blk64 = A.blk32 = 0;
         }
     };
     if (!timing || A.nnz == 0 || A.n < 200000 || A.nnz < 1000000) {
         // small matrices, or no timing asked for: the size rule's choice, and
         // a forced staged variant if it fits
         if (mode >= 1 && A.nnz > 0) {
-            build_all(mode == 1, mode == 2);
+            if (mode == 3)
+                build_runs(A, s);
+            else
+                build_all(mode == 1, mode == 2);
             force();
         }
         return;
     }
-    if (mode >= 0) build_all(mode <= 1, mode == 0 || mode == 2);
+    if (mode == 0 || mode == 3) build_runs(A, s);
+    if (mode >= 0 && mode <= 2) build_all(mode <= 1, mode == 0 || mode == 2);
     double* u = nullptr;
     double* y = nullptr;
     // u: the FP64 test vector; y: output (FP64) or, for FP32, an FP32 copy of
@@ -1348,21 +1585,28 @@ void matrix_tune(Matrix& A, int mode, bool timing, hipStream_t s) {
         W.on = false;
         R.on = false;
         const int cp0 = cp;
-        // candidates: cache policy c (0..2) with block shape b (0 large, 1 small)
-        float tc[6] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+        // candidates: cache policy c % 3 with the large blocks (c < 3), the
+        // small blocks (3 <= c < 6) or the large blocks with column runs
+        // (6 <= c < 9, when the setup found runs for at least half the blocks)
+        bool& rn = f32 ? A.runs.on32 : A.runs.on64;
+        const int64_t nwin = f32 ? A.runs.nwin32 : A.runs.nwin64;
+        const int ncand = (A.runs.rec && 2 * nwin >= A.runs.nblocks) ? 9 : 6;
+        float tc[9] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
         for (int trial = 0; trial < 4; ++trial)
-            for (int c = 0; c < 6; ++c) {
+            for (int c = 0; c < ncand; ++c) {
                 cp = c % 3;
-                blk = c / 3;
+                blk = c / 3 == 1 ? 1 : 0;
+                rn = c >= 6;
                 const float t = time_passes(A, f32, uu, yy, 8, s);
                 if (trial > 0) tc[c] = std::min(tc[c], t);
             }
         // the size rule's policy with large blocks stays unless another
         // candidate is clearly faster
-        const int c_best = (int)(std::min_element(tc, tc + 6) - tc);
+        const int c_best = (int)(std::min_element(tc, tc + ncand) - tc);
         const int c_keep = tc[c_best] < 0.97f * tc[cp0] ? c_best : cp0;
         cp = c_keep % 3;
-        blk = c_keep / 3;
+        blk = c_keep / 3 == 1 ? 1 : 0;
+        rn = c_keep >= 6;
         W.on = won;
         if (mode != 0 || (!W.bm && !R.rm)) continue;
         // the staged variants exist for gather-bound matrices: when the plain
@@ -1406,6 +1650,8 @@ void matrix_tune(Matrix& A, int mode, bool timing, hipStream_t s) {
 }
 
 void matrix_release(Matrix& A) {
+    if (A.runs.rec) (void)hipFree(A.runs.rec);
+    A.runs.rec = nullptr;
     if (A.bm) (void)hipFree(A.bm);
     if (A.bm_s) (void)hipFree(A.bm_s);
     A.bm_s = nullptr;

@@ -25,6 +25,7 @@ PPA_ERR_INVALID, PPA_ERR_HIP, PPA_ERR_WORKSPACE, PPA_ERR_NONFINITE = -1, -2, -3,
 PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
 PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF, PPA_MATRIX_RING_FORCE = 1, 2, 4, 8
 PPA_MATRIX_NO_TUNE = 16
+PPA_MATRIX_RUNS_FORCE = 32
 _PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
 
 vp = C.c_void_p
@@ -80,6 +81,8 @@ def _load():
         "ppa_matrix_set_cache_policy": (i, [vp, i, i]),
         "ppa_matrix_spmv_blocks": (i, [vp, i, P(i)]),
         "ppa_matrix_set_spmv_blocks": (i, [vp, i, i]),
+        "ppa_matrix_spmv_runs": (i, [vp, i, P(i), P(i64)]),
+        "ppa_matrix_set_spmv_runs": (i, [vp, i, i]),
         "ppa_poly_from_roots": (i, [i, P(d), P(d), i, P(d), P(d), P(vp)]),
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
@@ -164,7 +167,8 @@ class Matrix:
     def __init__(self, csr, want_f32: bool = False, window: str = "auto", tune: bool = True):
         """window: "auto" (time the SpMV variants on large matrices),
         "force" (LDS-windowed whenever it fits), "ring" (sliding window
-        whenever it fits) or "off" (plain kernel only).  tune=False skips the
+        whenever it fits), "runs" (plain kernel with column runs staged in
+        LDS) or "off" (plain kernel only, global gathers).  tune=False skips the
         timing at creation (size-rule cache policy, large blocks)."""
         dev = torch.device("cuda")
         self.n = int(csr.n)
@@ -177,7 +181,7 @@ class Matrix:
         self.vals32 = self.vals.float() if want_f32 else None
         h = vp()
         flags = {"auto": 0, "force": PPA_MATRIX_WINDOW_FORCE, "ring": PPA_MATRIX_RING_FORCE,
-                 "off": PPA_MATRIX_WINDOW_OFF}[window]
+                 "off": PPA_MATRIX_WINDOW_OFF, "runs": PPA_MATRIX_RUNS_FORCE}[window]
         if not tune:
             flags |= PPA_MATRIX_NO_TUNE
         _check(_lib.ppa_matrix_create(self.n, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.vals),
@@ -224,6 +228,16 @@ class Matrix:
 
     def set_spmv_blocks(self, nnz_per_block: int, precision: str = "f64") -> None:
         _check(_lib.ppa_matrix_set_spmv_blocks(self.h, _PREC[precision], int(nnz_per_block)))
+
+    def spmv_runs(self, precision: str = "f64"):
+        """(on, blocks with runs): whether the plain kernel stages column
+        runs in LDS, and how many large blocks have runs within budget."""
+        on, nb = C.c_int(), C.c_int64()
+        _check(_lib.ppa_matrix_spmv_runs(self.h, _PREC[precision], C.byref(on), C.byref(nb)))
+        return bool(on.value), nb.value
+
+    def set_spmv_runs(self, on: bool, precision: str = "f64") -> None:
+        _check(_lib.ppa_matrix_set_spmv_runs(self.h, _PREC[precision], int(bool(on))))
 
     def __del__(self):
         h = getattr(self, "h", None)
