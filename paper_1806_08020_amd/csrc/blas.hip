@@ -923,6 +923,15 @@ static void reduce_cols(const double* partial, int nb, int ncols, double* out, h
     PPA_HIP(hipGetLastError());
 }
 
+void launch_gram(int64_t n, int j, const double* V, int64_t ldv, const double* W, int ncols,
+                 double* G_d, Cgs2Ws& ws, hipStream_t s) {
+    PPA_REQUIRE(j >= 1 && j <= CGS_JMAX_ALL - 1 && ncols >= 1, "gram: sizes out of range");
+    for (int c = 0; c < ncols; ++c) {
+        proj(n, j, V, ldv, W + (size_t)c * ldv, ws.partial, ws.nb, 0, s);
+        reduce_cols(ws.partial, ws.nb, j, G_d + (size_t)c * j, s);
+    }
+}
+
 void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* w_out,
                  double* Hcol_d, double* v_next, double breakdown_tol, Cgs2Ws& ws,
                  hipStream_t s) {

@@ -416,6 +416,53 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
     RitzOut last;
     RitzPlan lastw;
     std::vector<cplx> lastnu;
+    // Ritz test of the pairs planned in R (Y = V_vcols Gw): Y and A Y on the
+    // device, Rayleigh quotients mu = y* A y and residual norms ||A y - mu y||
+    // for unit y
+    auto ritz_test = [&](const RitzPlan& R, int vcols) {
+        PPA_HIP(hipMemcpyAsync(e.Qd, R.Gw.data(), R.Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_gemm_tall(n, vcols, R.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);
+        launch_spmm_cols(A, e.Y, e.ld, R.ycols, e.AY, s);
+        const std::vector<DotSpec> dspec = ritz_dots(R);
+        std::vector<double> dv(dspec.size());
+        for (size_t off = 0; off < dspec.size(); off += MAX_DOTS) {
+            DotList L{};
+            L.count = (int)std::min<size_t>(MAX_DOTS, dspec.size() - off);
+            for (int t = 0; t < L.count; ++t) {
+                const DotSpec& q = dspec[off + t];
+                L.a[t] = e.Y + (size_t)q.a * e.ld;
+                L.b[t] = (q.kind == 1 ? e.Y : e.AY) + (size_t)q.b * e.ld;
+            }
+            launch_dots(n, L, e.dpart, ritz_blocks(n), e.dout, s);
+            PPA_HIP(hipMemcpyAsync(dv.data() + off, e.dout, L.count * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        PPA_HIP(hipStreamSynchronize(s));
+        RitzOut Rr;
+        ritz_mu(R, dv, Rr.mu, Rr.ynorm);
+        mvps += ritz_mvps(R);
+        // residual norms ||A y - mu y|| / ||y||
+        {
+            const std::vector<ComboSpec> cs = ritz_combos(R, Rr.mu);
+            const int nl = (int)cs.size();
+            std::vector<double> rn(nl);
+            for (int done = 0; done < nl;) {
+                ComboList P{};
+                P.count = std::min(MAX_COMBOS, nl - done);
+                for (int q = 0; q < P.count; ++q)
+                    for (int t = 0; t < 3; ++t) {
+                        const ComboSpec& c = cs[done + q];
+                        P.v[q][t] = t < c.nterms ? (c.kind[t] == 0 ? e.AY : e.Y) + (size_t)c.col[t] * e.ld : nullptr;
+                        P.c[q][t] = t < c.nterms ? c.c[t] : 0.0;
+                    }
+                launch_combo_norms(n, P, e.dpart, ritz_blocks(n), e.dout, s);
+                PPA_HIP(hipMemcpyAsync(rn.data() + done, e.dout, P.count * sizeof(double), hipMemcpyDeviceToHost, s));
+                done += P.count;
+            }
+            PPA_HIP(hipStreamSynchronize(s));
+            ritz_resid(R, cs, rn, Rr.ynorm, Rr.res);
+        }
+        return Rr;
+    };
     bool converged = false, broke = false;
     int cycle = 0;
     for (cycle = 1; cycle <= o.max_cycles; ++cycle) {
@@ -500,47 +547,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
         RitzPlan R = plan_ritz(Hm, mc, nev, target, harmonic && mc == m,
                                mc == m ? H[m + (size_t)(m - 1) * (m + 1)] : 0.0);
         const int nw = R.nw;
-        PPA_HIP(hipMemcpyAsync(e.Qd, R.Gw.data(), R.Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_gemm_tall(n, mc, R.ycols, e.V, e.ld, e.Qd, e.Y, e.ld, s);
-        launch_spmm_cols(A, e.Y, e.ld, R.ycols, e.AY, s);
-        const std::vector<DotSpec> dspec = ritz_dots(R);
-        std::vector<double> dv(dspec.size());
-        for (size_t off = 0; off < dspec.size(); off += MAX_DOTS) {
-            DotList L{};
-            L.count = (int)std::min<size_t>(MAX_DOTS, dspec.size() - off);
-            for (int t = 0; t < L.count; ++t) {
-                const DotSpec& q = dspec[off + t];
-                L.a[t] = e.Y + (size_t)q.a * e.ld;
-                L.b[t] = (q.kind == 1 ? e.Y : e.AY) + (size_t)q.b * e.ld;
-            }
-            launch_dots(n, L, e.dpart, ritz_blocks(n), e.dout, s);
-            PPA_HIP(hipMemcpyAsync(dv.data() + off, e.dout, L.count * sizeof(double), hipMemcpyDeviceToHost, s));
-        }
-        PPA_HIP(hipStreamSynchronize(s));
-        RitzOut Rr;
-        ritz_mu(R, dv, Rr.mu, Rr.ynorm);
-        mvps += ritz_mvps(R);
-        // residual norms ||A y - mu y|| / ||y||
-        {
-            const std::vector<ComboSpec> cs = ritz_combos(R, Rr.mu);
-            const int nl = (int)cs.size();
-            std::vector<double> rn(nl);
-            for (int done = 0; done < nl;) {
-                ComboList P{};
-                P.count = std::min(MAX_COMBOS, nl - done);
-                for (int q = 0; q < P.count; ++q)
-                    for (int t = 0; t < 3; ++t) {
-                        const ComboSpec& c = cs[done + q];
-                        P.v[q][t] = t < c.nterms ? (c.kind[t] == 0 ? e.AY : e.Y) + (size_t)c.col[t] * e.ld : nullptr;
-                        P.c[q][t] = t < c.nterms ? c.c[t] : 0.0;
-                    }
-                launch_combo_norms(n, P, e.dpart, ritz_blocks(n), e.dout, s);
-                PPA_HIP(hipMemcpyAsync(rn.data() + done, e.dout, P.count * sizeof(double), hipMemcpyDeviceToHost, s));
-                done += P.count;
-            }
-            PPA_HIP(hipStreamSynchronize(s));
-            ritz_resid(R, cs, rn, Rr.ynorm, Rr.res);
-        }
+        RitzOut Rr = ritz_test(R, mc);
         double mx = 0.0;
         for (int i = 0; i < nw; ++i) mx = std::max(mx, Rr.res[i]);
         hist.push_back(mx);
@@ -562,14 +569,43 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
             const bool stall = hc >= 3 && hist[hc - 1] > 0.5 * hist[hc - 3] && mx <= 1e3 * floor_abs;
             if (floor || stall) {
                 fp32 = false;
-                std::vector<double> coef(R.ycols, 0.0);
-                for (int i = 0; i < nw; ++i) {
-                    if (R.dup[i]) continue;
-                    coef[R.cre[i]] += 1.0 / Rr.ynorm[i];
-                    if (R.cim[i] >= 0) coef[R.cim[i]] += 1.0 / Rr.ynorm[i];
+                // closing FP64 Rayleigh-Ritz with A itself on the FP32-built
+                // basis V_{m+1} (FP64 storage, orthonormal to FP64 rounding):
+                // K = V^T A V, its Ritz pairs nearest the target, tested on A
+                // as every cycle's pairs are.  When they all meet rtol the
+                // solve ends here; otherwise the FP64 cycles restart from the
+                // sum of these unit Ritz vectors.  Costs m + 1 products with A
+                // and (m + 1)^2 inner products, against m factors of pi per cycle.
+                const int J = mc + 1;
+                launch_spmm_cols(A, e.V, e.ld, J, e.V2, s);
+                launch_gram(n, J, e.V, e.ld, e.V2, J, e.Qd, e.cw, s);
+                std::vector<double> K((size_t)J * J);
+                PPA_HIP(hipMemcpyAsync(K.data(), e.Qd, K.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+                PPA_HIP(hipStreamSynchronize(s));
+                for (double x : K)
+                    if (!std::isfinite(x)) fail(PPA_ERR_NONFINITE, "closing Rayleigh-Ritz: non-finite projection");
+                mvps += J;
+                dots += (int64_t)J * J;
+                const RitzPlan R2 = plan_ritz(K, J, nev, p ? p->shift : 0.0);
+                const RitzOut Rr2 = ritz_test(R2, J);
+                double mx2 = 0.0;
+                for (int i = 0; i < R2.nw; ++i) mx2 = std::max(mx2, Rr2.res[i]);
+                hist.back() = std::min(mx, mx2);
+                if (R2.nw == nev && mx2 <= rtol_abs) {
+                    last = Rr2;
+                    lastw = R2;
+                    lastnu.assign(R2.nu.begin(), R2.nu.begin() + R2.nw);
+                    converged = true;
+                    break;
+                }
+                std::vector<double> coef(R2.ycols, 0.0);
+                for (int i = 0; i < R2.nw; ++i) {
+                    if (R2.dup[i]) continue;
+                    coef[R2.cre[i]] += 1.0 / Rr2.ynorm[i];
+                    if (R2.cim[i] >= 0) coef[R2.cim[i]] += 1.0 / Rr2.ynorm[i];
                 }
                 PPA_HIP(hipMemcpyAsync(e.Qd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
-                launch_gemm_tall(n, R.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
+                launch_gemm_tall(n, R2.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
                 launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
                 set_unit(n, e.V2, e.V, e.dpart, nb, e.dout, s);
                 j0 = 0;

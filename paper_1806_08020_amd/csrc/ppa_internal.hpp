@@ -294,6 +294,11 @@ void carve_cgs2(Carver& c, int64_t n, Cgs2Ws& ws);
 // w_out (may equal w), the Hessenberg column (j+1 entries: h, beta) to
 // Hcol_d (device), and 1/beta (0 on breakdown) to ws.scal[2].  If v_next is
 // non-null it receives w_out * (1/beta).
+// G = V^T W: j x ncols, column-major on the device (V and W share the
+// leading dimension ldv); one projection pass over V per column of W, the
+// same two-stage reduction as the Gram-Schmidt kernels.
+void launch_gram(int64_t n, int j, const double* V, int64_t ldv, const double* W, int ncols,
+                 double* G_d, Cgs2Ws& ws, hipStream_t s);
 void launch_cgs2(int64_t n, int j, const double* V, int64_t ldv, const double* w, double* w_out,
                  double* Hcol_d, double* v_next, double breakdown_tol, Cgs2Ws& ws,
                  hipStream_t s);

@@ -243,4 +243,19 @@ def summarize(done: list[Completion], wall: float) -> dict:
         "wall_s": wall,
         "batch_requests": sum(1 for c in done if c.path == "batch"),
         "stream_requests": sum(1 for c in done if c.path == "stream"),
+        "by_path": {path: _path_summary([c for c in done if c.path == path])
+                    for path in ("batch", "stream")},
     }
+
+
+def _path_summary(done: list[Completion]) -> dict:
+    """Latency and work of the requests one path served (the batched engine
+    runs FP64 only; a mixed-precision run applies to the stream path)."""
+    if not done:
+        return {"requests": 0}
+    lat = np.array([c.latency for c in done])
+    ok = [c for c in done if c.result is not None]
+    return {"requests": len(done), "converged": sum(1 for c in ok if c.result.converged),
+            "eigenpairs": int(sum(c.result.nconv for c in ok)),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_n": float(np.mean([c.n for c in done]))}

@@ -23,6 +23,76 @@ def lap_closed(nx, ny):
     return np.sort((4 - 2 * np.cos(i * np.pi / (nx + 1)) - 2 * np.cos(j * np.pi / (ny + 1))).ravel())
 
 
+def convdiff_closed(N, bh):
+    """Eigenvalues of the h^2-scaled 2-D operator -u_xx - u_yy + beta u_x on
+    an N x N grid, lambda_ij = 4 - 2 sqrt(1 - b^2) cos(i pi/(N+1)) - 2 cos(j pi/(N+1))
+    with b = beta h / 2, and the condition number of each: the x factor is
+    D S D^-1 with S symmetric and D = diag(rho^k), rho = sqrt((1+b)/(1-b)),
+    so its eigenvectors are D q_i (right) and D^-1 q_i (left) with q_i the
+    sine vectors, kappa_i = ||D q_i|| ||D^-1 q_i|| / ||q_i||^2; the y factor
+    is symmetric."""
+    b = 0.5 * bh
+    k = np.arange(1, N + 1)
+    th = k * np.pi / (N + 1)
+    rho = np.sqrt((1 + b) / (1 - b))
+    D = rho ** k
+    kap = np.empty(N)
+    for i in range(1, N + 1):
+        q = np.sin(i * th)
+        kap[i - 1] = np.linalg.norm(D * q) * np.linalg.norm(q / D) / (q @ q)
+    lam = 4 - 2 * np.sqrt(1 - b * b) * np.cos(th)[:, None] - 2 * np.cos(th)[None, :]
+    kk = np.repeat(kap[:, None], N, axis=1)
+    o = np.argsort(lam.ravel())
+    return lam.ravel()[o], kk.ravel()[o]
+
+
+# eigenvalues and condition numbers of each request's operator
+CLOSED = {}
+
+
+def closed_for(i):
+    if i not in CLOSED:
+        if i == 0:
+            lam = lap_closed(30, 31)
+            CLOSED[i] = (lam, np.ones_like(lam), True)
+        elif i == 3:
+            lam = lap_closed(64, 64)
+            CLOSED[i] = (lam, np.ones_like(lam), True)
+        else:
+            N, bh = {1: (40, 0.3), 2: (24, 0.7), 4: (50, 0.1)}[i]
+            lam, kap = convdiff_closed(N, bh)
+            CLOSED[i] = (lam, kap, False)
+    return CLOSED[i]
+
+
+def check_eigenvalues(i, res, anorm):
+    """Each returned eigenvalue lies within its certified distance of a
+    closed-form eigenvalue, and no simple eigenvalue is claimed twice.  A unit
+    vector with residual r is within r^2 / gap of an eigenvalue of a
+    symmetric matrix (gap: distance to the next distinct eigenvalue), and
+    within kappa * r of a nonsymmetric one to first order (asserted with a
+    factor 2), up to the rounding of y* A y and of the closed form, a few
+    units of eps * ||A|| (1e-14 ||A|| allowed)."""
+    lam, kap, sym = closed_for(i)
+    claimed = {}
+    for mu, r in zip(res.mu, res.resid):
+        assert r <= 1e-8 * anorm
+        t = int(np.argmin(np.abs(lam - mu.real)))
+        if sym:
+            distinct = np.unique(np.round(lam, 12))
+            u = int(np.argmin(np.abs(distinct - lam[t])))
+            gap = np.min(np.abs(np.delete(distinct, u) - distinct[u]))
+            bound = r * r / gap + 1e-14 * anorm
+            mult = int(np.sum(np.abs(lam - lam[t]) <= 1e-12))
+        else:
+            bound = 2.0 * kap[t] * r + 1e-14 * anorm
+            mult = 1
+        assert abs(mu - lam[t]) <= bound, (i, mu, lam[t], bound)
+        key = round(float(lam[t]), 12)
+        claimed[key] = claimed.get(key, 0) + 1
+        assert claimed[key] <= mult, (i, key)
+
+
 def make_req(csr, seed, d, m, k, nev):
     b, v0 = W.start_vectors(csr.n, seed)
     return dict(csr=csr, b=b, v0=v0, d=d, m=m, k=k, nev=nev)
@@ -90,13 +160,23 @@ def test_batch_alone_equals_mix(lib):
         g = got[i]
         assert np.array_equal(a.mu, g.mu) and np.array_equal(a.resid, g.resid), i
         assert (a.cycles, a.mvps, a.dots, a.nconv) == (g.cycles, g.mvps, g.dots, g.nconv)
-        # and each one agrees with the oracle's converged eigenvalues
+        # every eigenvalue within its certified distance of the closed form,
+        # and of the oracle's: both runs converge to rtol, so the two lie
+        # within the sum of their bounds of the same eigenvalue
         rq = REQS[i]
+        anorm = O.infnorm(rq["csr"])
+        assert a.converged, i
+        check_eigenvalues(i, a, anorm)
         ores, _ = O.pp_eigs(rq["csr"], rq["b"], rq["v0"], m=rq["m"], k=rq["k"], nev=rq["nev"],
                             d=rq["d"], rtol=1e-8, max_cycles=40)
-        if ores.converged and a.converged:
-            anorm = O.infnorm(rq["csr"])
-            assert np.all(a.resid <= 1e-8 * anorm)
+        assert ores.converged, i
+        check_eigenvalues(i, ores, anorm)
+        lam, kap, sym = closed_for(i)
+        for mu, r in zip(a.mu, a.resid):
+            t = int(np.argmin(np.abs(ores.mu - mu)))
+            tl = int(np.argmin(np.abs(lam - mu.real)))
+            tol = (2e-10 * abs(mu) if sym else 2.0 * kap[tl] * (r + ores.resid[t])) + 2e-14 * anorm
+            assert abs(mu - ores.mu[t]) <= tol, (i, mu, ores.mu[t], tol)
 
 
 def test_batch_full_engine_reports_busy(lib):
