@@ -34,16 +34,19 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # HBM traffic of the fused SpMV kernel per launch, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this benchmark, scaled by
 # the factors the same counters give for a plain 2 GiB device copy (FETCH_SIZE
-# reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config and
+# reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config, pass
+# precision and
 # by the hash of the plain kernel's source (spmv.hip up to the windowed
 # variant) the counters were taken on, by the cache policy, by the block
 # shape (nonzeros per block) and by the use of column runs: any change of that
 # kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
-    ("c2", "9f058091bdec7e59", "keep", 256, False): {"fetch_kib": 36809.45, "write_kib": 7812.65,
-                                                    "fetch_factor": 2.0, "write_factor": 1.0},
-    ("c2", "9f058091bdec7e59", "keep", 2048, False): {"fetch_kib": 36548.35, "write_kib": 7817.07,
-                                                     "fetch_factor": 2.0, "write_factor": 1.0},
+    # 3-D 160^3, FP64, non-temporal loads, 2048 nonzeros per block, column runs:
+    # the solve's mix of the plain pass (22206 launches: 196394.47 KiB fetched,
+    # 32005.16 KiB written per dispatch) and the tau-epilogue pass (2460
+    # launches: 219220.71 / 32018.55 KiB), weighted by launch count
+    ("c3", "f64", "b454f77359cab70d", "stream", 2048, True): {
+        "fetch_kib": 198670.99, "write_kib": 32006.50, "fetch_factor": 2.0, "write_factor": 1.0},
 }
 
 CONFIGS = {
@@ -536,8 +539,9 @@ def parse_args(argv=None):
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--cache-policy", default="auto", choices=("auto", "stream", "keep", "keep_ntst"),
                     help="override the SpMV cache policy the matrix setup chose (for counter runs)")
-    ap.add_argument("--runs", default="auto", choices=("auto", "on", "off"),
-                    help="override the use of column runs the matrix setup chose (on: built and forced)")
+    ap.add_argument("--spmv-variant", default="auto", choices=("auto", "plain", "runs", "window", "ring"),
+                    help="SpMV kernel instead of the setup's timed choice: plain (global gathers), "
+                         "runs (column runs in LDS), window (per-block LDS window), ring (sliding window)")
     ap.add_argument("--spmv-blocks", default="auto", choices=("auto", "2048", "256"),
                     help="override the SpMV block shape (nonzeros per block) the matrix setup chose")
     ap.add_argument("--table-d0-cycles", type=int, default=1500,
@@ -576,11 +580,9 @@ def main():
     csr = make_matrix(cfg)
     b, v0 = W.start_vectors(csr.n, cfg["seed"])
     prec = cfg["precision"] if args.precision == "auto" else args.precision
-    A = ppa.Matrix(csr, want_f32=(prec != "f64"), window="runs" if args.runs == "on" else "auto")
-    if args.runs == "off":
-        for pk in (("f64", "f32") if prec != "f64" else ("f64",)):
-            if A.spmv_runs(pk)[0]:
-                A.set_spmv_runs(False, pk)
+    A = ppa.Matrix(csr, want_f32=(prec != "f64"),
+                   window={"auto": "auto", "plain": "off", "runs": "runs", "window": "force",
+                           "ring": "ring"}[args.spmv_variant])
     if args.cache_policy != "auto":
         A.set_cache_policy(args.cache_policy, "f32" if prec == "mixed" else "f64")
     if args.spmv_blocks != "auto":
@@ -647,7 +649,7 @@ def main():
     policy = A.cache_policy("f32" if prec == "mixed" else "f64")
     blocks = A.spmv_blocks("f32" if prec == "mixed" else "f64")
     runs_on, runs_blocks = A.spmv_runs("f32" if prec == "mixed" else "f64")
-    tr = MEASURED_TRAFFIC.get((args.config, khash, policy, blocks, runs_on))
+    tr = MEASURED_TRAFFIC.get((args.config, "f64" if prec == "f64" else "f32", khash, policy, blocks, runs_on))
     traffic = (round(1024 * (tr["fetch_kib"] * tr["fetch_factor"] + tr["write_kib"] * tr["write_factor"]))
                if tr else None)
     line = {
