@@ -188,7 +188,9 @@ bool schur(Mat& H, Mat* Z, std::vector<cplx>& w) {
             continue;
         }
         if (total >= itmax) return false;
-        double s, t;
+        // the shift pair: a complex pair re +- i im (im > 0), or one real
+        // shift re used twice (im = 0)
+        double re, im;
         if (its > 0 && its % 10 == 0) {
             // exceptional shifts (a conjugate pair) from the trailing or, every
             // other time, the leading corner of the active window
@@ -196,19 +198,37 @@ bool schur(Mat& H, Mat* Z, std::vector<cplx>& w) {
             const double ex = top ? std::fabs(H(l + 1, l)) + std::fabs(H(l + 2, l + 1))
                                   : std::fabs(H(hi, hi - 1)) + std::fabs(H(hi - 1, hi - 2));
             const double base = top ? H(l, l) : H(hi, hi);
-            const double re = base + 0.75 * ex, im = 0.66 * ex;
-            s = 2.0 * re;
-            t = re * re + im * im;
+            re = base + 0.75 * ex;
+            im = 0.66 * ex;
         } else {
-            s = H(hi - 1, hi - 1) + H(hi, hi);
-            t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
+            // eigenvalues of the trailing 2 x 2 block; two real ones are
+            // replaced by the one nearer H(hi, hi), taken twice
+            const double a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+            const double pp = 0.5 * (a - d), disc = pp * pp + b * c;
+            const double mid = 0.5 * (a + d);
+            if (disc >= 0.0) {
+                const double sq = std::sqrt(disc);
+                const double r1 = mid + sq, r2 = mid - sq;
+                re = std::fabs(r1 - d) <= std::fabs(r2 - d) ? r1 : r2;
+                im = 0.0;
+            } else {
+                re = mid;
+                im = std::sqrt(-disc);
+            }
         }
         ++its;
         ++total;
-        // first column of H^2 - s H + t I restricted to rows l, l+1, l+2
-        double x = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
-        double y = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
-        double z = H(l + 1, l) * H(l + 2, l + 1);
+        // first column of (H - sigma1)(H - sigma2) restricted to rows l, l+1,
+        // l+2, formed from the differences H(l, l) - re (no cancellation when
+        // the shifts are close to H(l, l), as for a multiple eigenvalue) and
+        // scaled by sc: only its direction matters
+        const double h21 = H(l + 1, l);
+        double sc = std::fabs(H(l, l) - re) + im + std::fabs(h21);
+        if (sc == 0.0) sc = 1.0;
+        const double h21s = h21 / sc, d11 = H(l, l) - re;
+        double x = h21s * H(l, l + 1) + d11 * (d11 / sc) + im * (im / sc);
+        double y = h21s * (d11 + (H(l + 1, l + 1) - re));
+        double z = h21s * H(l + 2, l + 1);
         for (int k = l; k <= hi - 2; ++k) {
             const double xv[3] = {x, y, z};
             double alpha;

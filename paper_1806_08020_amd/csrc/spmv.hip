@@ -635,17 +635,28 @@ __global__ __launch_bounds__(BS) void k_fused_spmv_ring(
             S.z2 = z2s[r];
         }
     };
+    // a lane's G products are stored with one G-wide LDS write (G = 4 FP32:
+    // 16 bytes); scalar stores at a lane stride of G would hit the same banks
+    // G times over
     auto gather = [&](const Slot& C, VT* prod) {
         const int base = C.p0 & ~(G - 1);
         if (C.p1 > C.p0) {
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
                 const int pos = G * (tid + k * BS);
+                typedef VT pvec __attribute__((ext_vector_type(G)));
+                pvec pr;
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
                     const int e = base + pos + j;
                     const VT w = ring[ring_pos<RW>(C.c[k].v[j])];
-                    prod[pos + j] = (e >= C.p0 && e < C.p1) ? C.v[k].v[j] * w : (VT)0;
+                    pr[j] = (e >= C.p0 && e < C.p1) ? C.v[k].v[j] * w : (VT)0;
+                }
+                if constexpr (G * sizeof(VT) == 16) {
+                    *reinterpret_cast<pvec*>(prod + pos) = pr;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < G; ++j) prod[pos + j] = pr[j];
                 }
             }
         }

@@ -77,6 +77,32 @@ def test_host_dense_eig_symmetric_and_repeated(cdll):
         sorted([(2, 0), (0, 1), (0, -1), (-5, 0)])
 
 
+def test_host_dense_eig_several_triple_eigenvalues(cdll):
+    """Non-normal matrices with several exactly triple eigenvalues (as a
+    3-D operator with the same convection on every axis gives pi(A)): the
+    shifted QR must reach the Schur form.  The first column of the
+    double-shift product is formed from differences H(l, l) - shift; formed
+    as H^2 - sH + tI it cancels to rounding noise once the shifts sit on a
+    multiple eigenvalue, and the iteration then stalls (this family stalled
+    in 74 of 200 draws)."""
+    from paper_1806_08020_amd import ppa
+    n = 40
+    for seed in range(60):
+        rng = np.random.default_rng([40, seed])
+        k = 4 + 2 * (seed % 3)
+        d = np.concatenate([np.repeat(rng.uniform(0.02, 0.3, k), 3), rng.uniform(-0.003, 0.01, n - 3 * k)])
+        X = np.eye(n) + (0.1 + 0.1 * (seed % 3)) * rng.standard_normal((n, n))
+        a = X @ np.diag(d) @ np.linalg.inv(X)
+        w, V = ppa.dense_eig(a)
+        # a triple eigenvalue perturbed at rounding level moves by about
+        # cond(X) * eps * ||a||, first order (non-defective)
+        tol = 1e-9 * np.linalg.cond(X)
+        assert np.max(np.abs(np.sort(w.real) - np.sort(d))) <= tol, seed
+        assert np.max(np.abs(w.imag)) <= tol
+        R = a @ V - V * w
+        assert np.linalg.norm(R) <= 1e-9 * np.linalg.norm(a) * n
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_host_leja_matches_oracle(cdll, seed):
     import oracle as O

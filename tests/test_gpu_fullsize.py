@@ -176,3 +176,53 @@ def test_cd2_full_harmonic_properties(lib, cd2):
     res = host_residuals(cd2, r.mu, X)
     assert np.all(res <= 1e-8 * A.norm_inf * 1.001)
     assert np.allclose(res, r.resid, rtol=1e-6, atol=1e-14 * A.norm_inf)
+
+
+def _closed_3d(N, bh, M=14):
+    """Eigenvalues of the h^2-scaled 3-D operator -Lap u + beta (u_x + u_y +
+    u_z) on N^3 (the same factor on each axis: eigenvalues of permuted index
+    triples coincide exactly), lambda = 6 - 2 sqrt(1 - b^2) sum cos(i pi/(N+1)),
+    b = beta h / 2, for the smallest indices (i, j, k < M), with each one's
+    condition number: the product of the 1-D factors' ||D q_i|| ||D^-1 q_i|| /
+    ||q_i||^2, D = diag(rho^k), rho = sqrt((1+b)/(1-b))."""
+    b = 0.5 * bh
+    k = np.arange(1, N + 1)
+    th = k * np.pi / (N + 1)
+    D = np.sqrt((1 + b) / (1 - b)) ** k
+    kap = np.array([np.linalg.norm(D * np.sin(i * th)) * np.linalg.norm(np.sin(i * th) / D)
+                    / (np.sin(i * th) @ np.sin(i * th)) for i in range(1, M + 1)])
+    f = -2 * np.sqrt(1 - b * b) * np.cos(th[:M])
+    I, J, K = np.meshgrid(np.arange(M), np.arange(M), np.arange(M), indexing="ij")
+    lam = (6 + f[I] + f[J] + f[K]).ravel()
+    kk = (kap[I] * kap[J] * kap[K]).ravel()
+    o = np.argsort(lam)
+    return lam[o], kk[o]
+
+
+@pytest.mark.parametrize("bh", [0.02, 0.05])
+def test_c3_grid_closed_form_eigenvalues(lib, bh):
+    """The headline's grid (160^3), solve and polynomial (double 10 x 20,
+    Arnoldi(40,20), nev = 15, FP64) with a convection weak enough that the
+    closed form pins every eigenvalue: each returned value lies within
+    2 kappa r of a closed-form eigenvalue (first order for a diagonalizable
+    matrix, r its residual), and no eigenvalue is claimed more often than its
+    multiplicity (1, 3 or 6 on this grid)."""
+    csr = W.convdiff_3d(160, bh)
+    b, v0 = W.start_vectors(csr.n, 3)
+    A = lib.Matrix(csr)
+    P = lib.Poly.build_double(A, 10, 20, dev(b))
+    r = lib.eigs(A, P, dev(v0), 40, 20, 15, rtol=1e-8, max_cycles=12)
+    print(f"160^3 beta*h={bh}: cycles {r.cycles}, converged {r.converged}", flush=True)
+    assert r.converged and r.nconv == 15
+    lam, kap = _closed_3d(160, bh)
+    claimed = {}
+    for mu, res in zip(r.mu, r.resid):
+        assert res <= 1e-8 * A.norm_inf
+        t = int(np.argmin(np.abs(lam - mu.real)))
+        assert abs(mu - lam[t]) <= 2.0 * kap[t] * res + 1e-14 * A.norm_inf, (mu, lam[t])
+        mult = int(np.sum(np.abs(lam - lam[t]) <= 1e-13))
+        key = round(float(lam[t]), 12)
+        claimed[key] = claimed.get(key, 0) + 1
+        assert claimed[key] <= mult
+    # the smallest eigenvalue is simple and always among those returned
+    assert np.min(np.abs(r.mu - lam[0])) <= 2.0 * kap[0] * r.max_resid + 1e-14 * A.norm_inf
