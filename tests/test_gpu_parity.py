@@ -351,9 +351,14 @@ def test_eigs_config1_laplacian(lib):
     gd = np.unique(np.round(r.mu.real, 9))
     od = np.unique(np.round(ores.mu.real, 9))
     assert np.array_equal(gd, od)
-    if r.cycles == ores.cycles:
-        assert (r.mvps, r.dots, r.vops) == (ores.counters.mvps - 10, ores.counters.dots - sum(
-            2 * j + 1 for j in range(1, 11)), ores.counters.vops - sum(4 * j + 2 for j in range(1, 11)))
+    # same cycle count as the oracle for this start vector (double eigenvalues
+    # make the count rounding-sensitive for some others: seed 2 takes 3 cycles
+    # in the oracle and 4 on the device), and then the same work: the device
+    # counts exclude the polynomial build (10 products, sum 2j+1 inner
+    # products and sum 4j+2 vector operations over its 10 Gram-Schmidt steps)
+    assert r.cycles == ores.cycles
+    assert (r.mvps, r.dots, r.vops) == (ores.counters.mvps - 10, ores.counters.dots - sum(
+        2 * j + 1 for j in range(1, 11)), ores.counters.vops - sum(4 * j + 2 for j in range(1, 11)))
     # eigenvectors returned on the device: unit norm, A x = mu x
     X = host(r.X).T
     S = csr.to_scipy()
