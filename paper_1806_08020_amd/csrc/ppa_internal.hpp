@@ -146,9 +146,10 @@ struct Ring {
 //   [1] LDS entries of all runs
 //   [2 + k] first column of run k (k < SPMV_RUNS_MAX; unused: INT32_MAX)
 //   [2 + SPMV_RUNS_MAX + k - 1] LDS offset of run k, k >= 1 (unused: INT32_MAX)
-// The block copies its runs of u into LDS with 16-byte loads issued together
-// with its matrix stream (they do not wait for the column indices), then
-// reads every gathered entry from LDS.  A block whose runs exceed
+// The runs also cover the block's own rows.  The block copies its runs of u
+// into LDS with 16-byte loads issued together with its matrix stream (they do
+// not wait for the column indices), then reads every gathered entry from LDS,
+// and x[r] too when x is u.  A block whose runs exceed
 // SPMV_RUNS_LDS bytes in the value type gathers from global memory.
 #ifndef PPA_SPMV_RUNS_MAX
 #define PPA_SPMV_RUNS_MAX 7

@@ -354,6 +354,14 @@ __global__ __launch_bounds__(BS_) void k_fused_spmv(
     };
     const int ra = r0 + tid, rb = r0 + tid + BS_;
     RowPre<VT> qa, qb;
+    // x is the gathered vector itself (a real root's pass, w - A w / theta):
+    // the runs hold the block's own rows as well (the setup adds them), so
+    // the thread's first two x values are read from the window
+    const bool xw = use_win && (const void*)x == (const void*)u;
+    auto x_from_window = [&]() {
+        qa.x = win[run_pos(R, min(ra, r1 - 1))];
+        qb.x = win[run_pos(R, min(rb, r1 - 1))];
+    };
     if constexpr (G == 1) {
         // positions past the block re-read its last nonzero (masked below)
         const int cnt = p1 - p0, last = p1 - 1;
@@ -369,9 +377,10 @@ __global__ __launch_bounds__(BS_) void k_fused_spmv(
         }
         if (use_win) load_window();
         // the thread's first two rows (clamped into the block; masked at use)
-        qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
-        qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), x, z, z2);
+        qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), xw ? nullptr : x, z, z2);
+        qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), xw ? nullptr : x, z, z2);
         if (use_win) store_window();
+        if (xw) x_from_window();
         if (cnt > 0) {
             VT g[PER];
             if (use_win) {
@@ -401,9 +410,10 @@ __global__ __launch_bounds__(BS_) void k_fused_spmv(
             }
         }
         if (use_win) load_window();
-        qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), x, z, z2);
-        qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), x, z, z2);
+        qa = row_pre<VT, EPI>(rowptr, min(ra, r1 - 1), xw ? nullptr : x, z, z2);
+        qb = row_pre<VT, EPI>(rowptr, min(rb, r1 - 1), xw ? nullptr : x, z, z2);
         if (use_win) store_window();
+        if (xw) x_from_window();
         if (p1 > p0) {
             VT g[NG][G];
             if (use_win) {
@@ -1121,7 +1131,7 @@ static std::vector<int32_t> partition(const std::vector<int32_t>& rp, int64_t n,
 }
 
 // Column runs of every large block (the record layout is described with
-// Runs).  The column indices are copied to the host once; the blocks are
+// Runs); the runs also cover the block's own rows.  The column indices are copied to the host once; the blocks are
 // split over host threads.  A block's columns are sorted, joined into runs
 // (gaps of at most SPMV_RUNS_GAP entries bridged), the runs widened to
 // multiples of 4 entries (16-byte loads of FP32 or FP64 vectors) and joined
@@ -1145,7 +1155,10 @@ static void build_runs(Matrix& A, hipStream_t s) {
         for (int k = 1; k < SPMV_RUNS_MAX; ++k) r[2 + SPMV_RUNS_MAX + k - 1] = INT32_MAX;
         const int p0 = bm[b].z, p1 = bm[b].w;
         if (p1 <= p0 || p1 - p0 > SPMV_CHUNK) return;
+        // the block's columns and its own rows (a pass whose x is u reads
+        // x[r] from the window)
         t.assign(ci.begin() + p0, ci.begin() + p1);
+        for (int r = bm[b].x; r < bm[b].y; ++r) t.push_back(r);
         std::sort(t.begin(), t.end());
         // runs [start, end) of the sorted columns, then aligned to 4 entries
         rs.clear();

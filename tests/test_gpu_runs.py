@@ -4,8 +4,9 @@ products and row sums are unchanged, so the output is bitwise that of the
 same kernel gathering from memory, in FP64, FP32 and the mixed
 FP32-values / FP64-vector forms, with and without the epilogue vectors;
 blocks whose runs do not fit (too many, too long, a long row) gather from
-memory inside the same launch; a gathered vector that is not 16-byte aligned
-sends the launch to the plain form."""
+memory inside the same launch; when x is the gathered vector itself its
+entries come from the runs too (they cover the block's rows); a gathered
+vector that is not 16-byte aligned sends the launch to the plain form."""
 import numpy as np
 import pytest
 import torch
@@ -78,7 +79,9 @@ def test_runs_bitwise_equal_to_memory_gathers(lib, name):
                 A.set_spmv_runs(on, prec)
             assert A.spmv_runs(prec)[0] == (on and with_runs[prec][0])
             assert A.spmv_blocks(prec) == 2048
+            ut = dev(u, dt)
             o = [lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt)),
+                 lib.fused_spmv(A, 1.0, ut, -0.5, ut),          # x is u: x read from the runs
                  lib.fused_spmv(A, 0.5, dev(x, dt), -2.0, dev(u, dt), 1.5, dev(z, dt), -0.25, dev(z2, dt)),
                  lib.fused_spmv(A, 1.0, dev(u, dt), -0.5, dev(u, dt))]
             if prec == "f32":
