@@ -35,18 +35,17 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this benchmark, scaled by
 # the factors the same counters give for a plain 2 GiB device copy (FETCH_SIZE
 # reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config, pass
-# precision and
-# by the hash of the plain kernel's source (spmv.hip up to the windowed
-# variant) the counters were taken on, by the cache policy, by the block
-# shape (nonzeros per block) and by the use of column runs: any change of that
+# precision, the hash of the plain kernel's source (spmv.hip up to the
+# windowed variant) the counters were taken on, the cache policy, the block
+# shape (nonzeros per block) and the use of column runs: any change of that
 # kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
     # 3-D 160^3, FP64, non-temporal loads, 2048 nonzeros per block, column runs:
-    # the solve's mix of the plain pass (22206 launches: 196394.47 KiB fetched,
-    # 32005.16 KiB written per dispatch) and the tau-epilogue pass (2460
-    # launches: 219220.71 / 32018.55 KiB), weighted by launch count
-    ("c3", "f64", "b454f77359cab70d", "stream", 2048, True): {
-        "fetch_kib": 198670.99, "write_kib": 32006.50, "fetch_factor": 2.0, "write_factor": 1.0},
+    # the solve's mix of the plain pass (22206 launches: 195996.46 KiB fetched,
+    # 32001.16 KiB written per dispatch) and the tau-epilogue pass (2460
+    # launches: 218394.33 / 32002.47 KiB), weighted by launch count
+    ("c3", "f64", "e9b3f092c93e1260", "stream", 2048, True): {
+        "fetch_kib": 198230.25, "write_kib": 32001.29, "fetch_factor": 2.0, "write_factor": 1.0},
 }
 
 CONFIGS = {
