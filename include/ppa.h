@@ -51,7 +51,9 @@ typedef enum ppa_precision {
     PPA_F64 = 0,    /* everything in FP64                                           */
     PPA_F32 = 1,    /* pi(A)v with FP32 matrix values and FP32 vectors              */
     PPA_MIXED = 2   /* eigs: pi(A)v in FP32, orthogonalisation / Ritz / residual in
-                       FP64, closing FP64 cycles to reach rtol                        */
+                       FP64; when the FP32 cycles stall, a closing FP64
+                       Rayleigh-Ritz with A on their basis, then FP64 cycles
+                       from its Ritz vectors unless it already meets rtol     */
 } ppa_precision;
 
 typedef struct ppa_matrix ppa_matrix;
@@ -403,7 +405,9 @@ typedef struct ppa_eigs_result {
     double* lam_re;
     double* lam_im;
     double* resid;       /* ||A y - mu y|| with unit y                       */
-    double* ritz_re;     /* Ritz values nu of pi(A) for the same pairs (may be NULL) */
+    double* ritz_re;     /* Ritz values nu of pi(A) for the same pairs (may be NULL);
+                            a mixed solve that ends with its closing
+                            Rayleigh-Ritz returns the Ritz values of A there */
     double* ritz_im;
     /* device array (may be NULL): n x nev complex128 (interleaved re, im),
      * column j the unit eigenvector estimate of lam j */
