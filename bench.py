@@ -228,6 +228,68 @@ def copy_probe(torch, reps):
                       "GBps": round(2 * 8 * n / ms / 1e6, 1)}), flush=True)
 
 
+def bw_probe(torch, reps=20):
+    """Bandwidth reference on this device from hand-written kernels of plain
+    access patterns (libppa_bwprobe.so; no part of the solver): streaming
+    reads with 16-byte non-temporal, 16-byte plain and 4-byte loads, a copy,
+    and a read with a write stream one eighth its size (a fused SpMV pass's
+    byte mix), at 1 GiB (beyond the 256 MB last-level cache) and 80 MB
+    (within it).  GB/s = bytes moved per launch / HIP-event-timed launch on
+    torch's current stream, best over three grid sizes."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1806_08020_amd", "libppa_bwprobe.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libppa_bwprobe.so is not built (python -m paper_1806_08020_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.ppa_probe_read.argtypes = [vp, i64, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, vp]
+    lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, vp]
+    grids = (1024, 4096, 16384)
+    big = 1 << 30
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = torch.randint(-2 ** 31, 2 ** 31 - 1, (big // 4,), dtype=torch.int32, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    sink = torch.empty(max(grids) * 256, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    xp, yp, sp = x.data_ptr(), y.data_ptr(), sink.data_ptr()
+    never = 0x9E3779B9
+    kinds = {
+        "read16_nontemporal": (lambda nb, gr: lib.ppa_probe_read(xp, nb, 16, 1, never, sp, gr, stream), 1.0),
+        "read16": (lambda nb, gr: lib.ppa_probe_read(xp, nb, 16, 0, never, sp, gr, stream), 1.0),
+        "read4": (lambda nb, gr: lib.ppa_probe_read(xp, nb, 4, 0, never, sp, gr, stream), 1.0),
+        "copy": (lambda nb, gr: lib.ppa_probe_copy(xp, yp, nb, gr, stream), 2.0),
+        "read_plus_write_eighth": (lambda nb, gr: lib.ppa_probe_read_write8(xp, yp, nb, gr, stream), 1.125),
+    }
+    out = {}
+    for label, nbytes in (("1GiB", big), ("80MB", 80_000_000)):
+        row = {}
+        for name, (launch, mult) in kinds.items():
+            best, best_g = 0.0, None
+            for gr in grids:
+                for _ in range(2):
+                    if launch(nbytes, gr) != 0:
+                        raise RuntimeError(f"probe {name} refused {nbytes} bytes")
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    launch(nbytes, gr)
+                e1.record()
+                torch.cuda.synchronize()
+                gbs = mult * nbytes * reps / e0.elapsed_time(e1) / 1e6
+                if gbs > best:
+                    best, best_g = gbs, gr
+            row[name] = {"GBps": round(best, 1), "frac_of_peak": round(best / HBM_PEAK_GBS, 4),
+                         "workgroups": best_g}
+        out[label] = row
+    out["note"] = ("grid-stride kernels of 256 threads, best of 1024/4096/16384 workgroups; "
+                   "read_plus_write_eighth moves bytes * 1.125 per launch")
+    del x, y, sink
+    torch.cuda.empty_cache()
+    return out
+
+
 def stability_report(P, dbl):
     """Section 7 stability control: the headline polynomial's largest
     log10 pof and the extra roots the procedure would add, and Example 7
@@ -530,6 +592,9 @@ def parse_args(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy instead (HBM counter calibration)")
+    ap.add_argument("--bw-probe", action="store_true",
+                    help="only the bandwidth reference kernels (streaming read, copy, read plus an "
+                         "eighth written) at 1 GiB and 80 MB; prints its own JSON line")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the solve in the other precision (mixed vs FP64)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served mix")
@@ -571,6 +636,9 @@ def main():
         return
     if args.copy_probe:
         copy_probe(torch, args.steps)
+        return
+    if args.bw_probe:
+        print(json.dumps({"hbm_reference": bw_probe(torch)}), flush=True)
         return
     from paper_1806_08020_amd import ppa
     from paper_1806_08020_amd import workloads as W
@@ -727,6 +795,7 @@ def main():
         }
     acc = None
     if not args.headline_only:
+        line["hbm_reference"] = bw_probe(torch)
         acc = mixed_accuracy_report()
         if args.config != "c2":
             line["c2_cache_resident"] = cache_resident_report("c2", 3, args.max_cycles)

@@ -34,6 +34,18 @@ def test_exports_every_declared_symbol(cdll):
     assert not missing, missing
 
 
+def test_bandwidth_probe_library_exports():
+    """The benchmark's bandwidth reference kernels are built beside the
+    solver library, as a library of their own."""
+    path = os.path.join(ROOT, "paper_1806_08020_amd", "libppa_bwprobe.so")
+    if not os.path.exists(path):
+        pytest.fail("libppa_bwprobe.so is not built (run python -m paper_1806_08020_amd.build)")
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    for name in ("ppa_probe_read", "ppa_probe_copy", "ppa_probe_read_write8"):
+        assert hasattr(lib, name), name
+
+
 def test_abi_version(cdll):
     from paper_1806_08020_amd import ppa
     assert ppa.abi_version() == 1
