@@ -235,17 +235,18 @@ def bw_probe(torch, reps=20):
     and a read with a write stream one eighth its size (a fused SpMV pass's
     byte mix), at 1 GiB (beyond the 256 MB last-level cache) and 80 MB
     (within it).  GB/s = bytes moved per launch / HIP-event-timed launch on
-    torch's current stream, best over three grid sizes."""
+    torch's current stream, best over two layouts (grid-stride, one
+    contiguous range per workgroup) and five grid sizes."""
     import ctypes
     path = os.path.join(ROOT, "paper_1806_08020_amd", "libppa_bwprobe.so")
     if not os.path.exists(path):
         raise RuntimeError("libppa_bwprobe.so is not built (python -m paper_1806_08020_amd.build)")
     lib = ctypes.CDLL(path)
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
-    lib.ppa_probe_read.argtypes = [vp, i64, ci, ci, ctypes.c_uint32, vp, ci, vp]
-    lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, vp]
-    lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, vp]
-    grids = (1024, 4096, 16384)
+    lib.ppa_probe_read.argtypes = [vp, i64, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, ci, vp]
+    lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, ci, vp]
+    grids = (256, 512, 1024, 4096, 16384)
     big = 1 << 30
     g = torch.Generator(device="cuda")
     g.manual_seed(5)
@@ -256,35 +257,41 @@ def bw_probe(torch, reps=20):
     xp, yp, sp = x.data_ptr(), y.data_ptr(), sink.data_ptr()
     never = 0x9E3779B9
     kinds = {
-        "read16_nontemporal": (lambda nb, gr: lib.ppa_probe_read(xp, nb, 16, 1, never, sp, gr, stream), 1.0),
-        "read16": (lambda nb, gr: lib.ppa_probe_read(xp, nb, 16, 0, never, sp, gr, stream), 1.0),
-        "read4": (lambda nb, gr: lib.ppa_probe_read(xp, nb, 4, 0, never, sp, gr, stream), 1.0),
-        "copy": (lambda nb, gr: lib.ppa_probe_copy(xp, yp, nb, gr, stream), 2.0),
-        "read_plus_write_eighth": (lambda nb, gr: lib.ppa_probe_read_write8(xp, yp, nb, gr, stream), 1.125),
+        "read16_nontemporal": (lambda nb, c, gr: lib.ppa_probe_read(xp, nb, 16, 1, c, never, sp, gr, stream), 1.0),
+        "read16": (lambda nb, c, gr: lib.ppa_probe_read(xp, nb, 16, 0, c, never, sp, gr, stream), 1.0),
+        "read4": (lambda nb, c, gr: lib.ppa_probe_read(xp, nb, 4, 0, c, never, sp, gr, stream), 1.0),
+        "copy": (lambda nb, c, gr: lib.ppa_probe_copy(xp, yp, nb, c, gr, stream), 2.0),
+        "read_plus_write_eighth": (lambda nb, c, gr: lib.ppa_probe_read_write8(xp, yp, nb, c, gr, stream), 1.125),
     }
     out = {}
     for label, nbytes in (("1GiB", big), ("80MB", 80_000_000)):
         row = {}
         for name, (launch, mult) in kinds.items():
-            best, best_g = 0.0, None
-            for gr in grids:
-                for _ in range(2):
-                    if launch(nbytes, gr) != 0:
-                        raise RuntimeError(f"probe {name} refused {nbytes} bytes")
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                for _ in range(reps):
-                    launch(nbytes, gr)
-                e1.record()
-                torch.cuda.synchronize()
-                gbs = mult * nbytes * reps / e0.elapsed_time(e1) / 1e6
-                if gbs > best:
-                    best, best_g = gbs, gr
+            best, where, one_per_cu = 0.0, None, None
+            for contiguous in (0, 1):
+                for gr in grids:
+                    for _ in range(2):
+                        if launch(nbytes, contiguous, gr) != 0:
+                            raise RuntimeError(f"probe {name} refused {nbytes} bytes")
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        launch(nbytes, contiguous, gr)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    gbs = mult * nbytes * reps / e0.elapsed_time(e1) / 1e6
+                    if gbs > best:
+                        best, where = gbs, ("contiguous" if contiguous else "grid-stride", gr)
+                    if contiguous and gr == 256:
+                        one_per_cu = gbs
             row[name] = {"GBps": round(best, 1), "frac_of_peak": round(best / HBM_PEAK_GBS, 4),
-                         "workgroups": best_g}
+                         "layout": where[0], "workgroups": where[1],
+                         "one_range_per_cu_GBps": round(one_per_cu, 1)}
         out[label] = row
-    out["note"] = ("grid-stride kernels of 256 threads, best of 1024/4096/16384 workgroups; "
-                   "read_plus_write_eighth moves bytes * 1.125 per launch")
+    out["note"] = ("256-thread workgroups, eight loads in flight per thread, best of grid-stride and "
+                   "contiguous-range layouts at 256-16384 workgroups; one_range_per_cu_GBps: the "
+                   "contiguous layout with 256 workgroups, one stream per CU as in the sliding-window "
+                   "SpMV; read_plus_write_eighth moves bytes * 1.125 per launch")
     del x, y, sink
     torch.cuda.empty_cache()
     return out

@@ -46,6 +46,12 @@
 #ifndef PPA_SPMV_G32
 #define PPA_SPMV_G32 4
 #endif
+// The sliding-window kernel gathers from LDS, so wider FP64 groups do not
+// spread its gathers over more cache lines: 8-byte index and 16-byte value
+// loads per lane there.
+#ifndef PPA_SPMV_RING_G64
+#define PPA_SPMV_RING_G64 2
+#endif
 
 namespace ppa {
 
@@ -627,6 +633,11 @@ __global__ __launch_bounds__(BS) void k_fused_spmv_ring(
         S.hi = m1.y;
         const int base = S.p0 & ~(G - 1);
         const int gmax = max((S.p1 - base - 1) / G, 0);
+        // the new ring entries first: they are written one step after this
+        // load, the matrix operands two steps after it, and a wait for a
+        // load also waits for every load issued before it
+#pragma unroll
+        for (int j = 0; j < RN; ++j) S.w[j] = u[min(S.lo + tid + j * BS, n - 1)];
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
             const int idx = base + G * min(tid + k * BS, gmax);
@@ -634,8 +645,6 @@ __global__ __launch_bounds__(BS) void k_fused_spmv_ring(
             S.c[k] = load_grp<G, CP_STREAM>(colind, idx, full, nnz - 1);
             S.v[k] = load_grp<G, CP_STREAM>(val, idx, full, nnz - 1);
         }
-#pragma unroll
-        for (int j = 0; j < RN; ++j) S.w[j] = u[min(S.lo + tid + j * BS, n - 1)];
         const int r = min(S.r0 + tid, S.r1 - 1);
         S.a = rowptr[r];
         S.e = rowptr[r + 1];
@@ -837,6 +846,10 @@ template <typename VT>
 constexpr int grp_width() {
     return sizeof(VT) == 8 ? PPA_SPMV_G64 : PPA_SPMV_G32;
 }
+template <typename VT>
+constexpr int ring_grp_width() {
+    return sizeof(VT) == 8 ? PPA_SPMV_RING_G64 : PPA_SPMV_G32;
+}
 
 template <typename VT, typename IT, typename OT>
 static void run_fused(const Matrix& A, const VT* val, const Window& W, const Ring& R, double alpha,
@@ -848,7 +861,9 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, const Rin
     const bool valg = reinterpret_cast<uintptr_t>(val) % (G * sizeof(VT)) == 0;
     if (R.on) {
         constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>(), BS = ring_threads<VT>();
-        const bool grp = G > 1 && R.align % G == 0 && valg;
+        constexpr int GR = ring_grp_width<VT>();
+        const bool grp = GR > 1 && R.align % GR == 0 &&
+                         reinterpret_cast<uintptr_t>(val) % (GR * sizeof(VT)) == 0;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3((unsigned)R.nseg), dim3(BS), R.lds_bytes, s,
                                A.rowptr, A.colind, val, R.rm, R.seg, (int)R.nseg, (int)A.nnz,
@@ -856,8 +871,8 @@ static void run_fused(const Matrix& A, const VT* val, const Window& W, const Rin
                                (VT)alpha, (VT)beta, (VT)gamma, (VT)delta);
         };
         if (grp)
-            epi ? go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, true>)
-                : go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, false>);
+            epi ? go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, GR, true>)
+                : go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, GR, false>);
         else
             epi ? go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, 1, true>)
                 : go(k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, 1, false>);
@@ -1311,7 +1326,7 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
 // dynamic LDS.
 template <typename VT, typename IT, typename OT>
 static bool allow_ring_one(int b) {
-    constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>(), G = grp_width<VT>();
+    constexpr int CH = ring_chunk<VT>(), RW = ring_size<VT>(), G = ring_grp_width<VT>();
     constexpr int BS = ring_threads<VT>();
     bool ok = true;
     for (const void* f : {(const void*)k_fused_spmv_ring<VT, IT, OT, BS, CH, RW, G, true>,
