@@ -543,8 +543,8 @@ def table81_report(max_cycles_d0):
 def served_mix_report(count, closed_only=False):
     """Served mix (2-D convection-diffusion solves of random size, degree and
     nev, seeded): capacity from a closed-loop run (all requests at t = 0),
-    then Poisson arrivals at 0.7 x capacity, FP64 and mixed precision (mixed
-    applies to the single-solve path; the batched small solves run FP64), and
+    then Poisson arrivals at 0.7 x capacity, FP64 and mixed precision (FP32
+    pi(A)v in the batched engine and on the single-solve path alike), and
     FP64 with graph-replayed restart cycles on the single-solve path."""
     from paper_1806_08020_amd import serve as S
     reqs = S.served_mix(count=count, seed=5, rate=1e9, max_cycles=30)
@@ -582,9 +582,8 @@ def served_mix_report(count, closed_only=False):
         rep[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in o.items()}
     rep["note"] = ("the same arrivals with the single-solve path replaying each restart cycle from "
                    "a HIP graph (f64_graph, PPA_FLAG_GRAPH) or using the delayed-reorthogonalisation "
-                   "Gram-Schmidt (f64_lowsync, PPA_FLAG_LOWSYNC); the batched small solves are the same "
-                   "and run in FP64 in every form (by_path.batch), so mixed precision differs from FP64 "
-                   "only on the stream path (by_path.stream)")
+                   "Gram-Schmidt (f64_lowsync, PPA_FLAG_LOWSYNC); mixed runs FP32 pi(A)v on both "
+                   "paths (by_path.*.fp32_cycles), the graph and low-sync forms change the stream path only")
     return rep
 
 

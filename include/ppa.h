@@ -454,7 +454,10 @@ int ppa_eigs(const ppa_matrix* A, const ppa_poly* p, const ppa_eigs_opts* o,
  * reduction inside that workgroup, so a solve's result does not depend on the
  * other solves in the batch.  The host handles the small projected problems
  * between launches.  Requests join free slots and leave between launches
- * (continuous batching).  FP64 throughout; no eigenvectors are returned.
+ * (continuous batching).  FP64 throughout, or per request PPA_MIXED
+ * (ppa_batch_submit_ex): pi(A)v in FP32 as in ppa_eigs, with the same rule
+ * for leaving the FP32 phase and the same closing FP64 Rayleigh-Ritz pass.
+ * No eigenvectors are returned.
  * ------------------------------------------------------------------------ */
 typedef struct ppa_batch ppa_batch;
 
@@ -475,11 +478,24 @@ typedef struct ppa_batch_request {
 } ppa_batch_request;
 
 int ppa_batch_workspace_bytes(int64_t n, int d, int m, int nev, size_t* bytes);
+/* Workspace of a request in precision PPA_F64 (as above) or PPA_MIXED, which
+ * also holds an FP32 copy of the nnz values and four FP32 n-vectors.
+ * PPA_ERR_INVALID for another precision or nnz < 0. */
+int ppa_batch_workspace_bytes_ex(int64_t n, int64_t nnz, int d, int m, int nev, int precision,
+                                 size_t* bytes);
 /* Engine with up to max_slots concurrent solves; all its work goes to `stream`. */
 int ppa_batch_create(int max_slots, void* stream, ppa_batch** out);
 int ppa_batch_destroy(ppa_batch* b);
 /* Admit a request into a free slot (*slot); PPA_ERR_BUSY when none is free. */
 int ppa_batch_submit(ppa_batch* b, const ppa_batch_request* rq, int* slot);
+/* As ppa_batch_submit, with precision PPA_F64 or PPA_MIXED (mixed precision,
+ * section 4's Arnoldi on an FP32 pi(A) until the wanted residuals reach the
+ * FP32 floor or stall near it, then the closing FP64 Rayleigh-Ritz pass and,
+ * if needed, FP64 cycles).  rq->ws_bytes must cover
+ * ppa_batch_workspace_bytes_ex for this precision and A's nonzero count; the
+ * FP32 values are copied from val_d at submit.  Results report fp32_cycles
+ * and spmv_passes_f32. */
+int ppa_batch_submit_ex(ppa_batch* b, const ppa_batch_request* rq, int precision, int* slot);
 /* One launch for all admitted solves, then the host work of the phase ends.
  * finished[0 .. min(*nfinished, cap)) receive slots whose solve ended (their
  * results are ready); *nactive the number of solves that took part.

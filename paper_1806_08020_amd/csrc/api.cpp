@@ -546,6 +546,16 @@ int ppa_batch_workspace_bytes(int64_t n, int d, int m, int nev, size_t* bytes) {
     });
 }
 
+int ppa_batch_workspace_bytes_ex(int64_t n, int64_t nnz, int d, int m, int nev, int precision,
+                                 size_t* bytes) {
+    return guarded([&] {
+        PPA_REQUIRE(bytes && n >= 1 && d >= 1 && m >= 2 && nev >= 1 && nnz >= 0, "bad arguments");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_MIXED, "precision must be F64 or MIXED");
+        *bytes = batch_ws_bytes(n, d, m, nev, nnz, precision);
+        return PPA_OK;
+    });
+}
+
 int ppa_batch_create(int max_slots, void* stream, ppa_batch** out) {
     return guarded([&] {
         PPA_REQUIRE(out != nullptr, "out is NULL");
@@ -565,6 +575,13 @@ int ppa_batch_submit(ppa_batch* b, const ppa_batch_request* rq, int* slot) {
     return guarded([&] {
         PPA_REQUIRE(b && rq && slot, "batch, request and slot are required");
         return batch_submit(*reinterpret_cast<Batch*>(b), *rq, slot);
+    });
+}
+
+int ppa_batch_submit_ex(ppa_batch* b, const ppa_batch_request* rq, int precision, int* slot) {
+    return guarded([&] {
+        PPA_REQUIRE(b && rq && slot, "batch, request and slot are required");
+        return batch_submit(*reinterpret_cast<Batch*>(b), *rq, slot, precision);
     });
 }
 

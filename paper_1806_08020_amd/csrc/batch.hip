@@ -9,13 +9,17 @@
 //          pass budget, optionally after the thick-restart product V Q,
 //   TEST   Ritz vectors Y = V_m G, A Y, Rayleigh quotients and residual norms
 //          (section 4),
+//   RR     the closing FP64 Rayleigh-Ritz projection of a mixed-precision
+//          solve, K = V^T A V over the basis its FP32 cycles built,
 // and the host handles the small projected problems between launches (roots,
 // Ritz pairs, restart), sharing that logic with the single-solve driver.
 // Solves join free slots and leave finished ones between launches
 // (continuous batching).  Every reduction runs inside one workgroup in a fixed
 // order, so a solve's result does not depend on what else is in the batch.
 // The per-row sums of a pass follow the same order and expression as the
-// main SpMV kernel.
+// main SpMV kernel.  A mixed-precision solve applies pi(A) in FP32 (values,
+// vectors and sums; the last factor's result stored to the FP64 basis), as
+// the single-solve path does, and everything else in FP64.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,7 +37,7 @@ constexpr int BMAXJ = 128;        // largest basis (GMRES degree or m) + 1
 constexpr int BMAXW = 32;         // largest nev
 constexpr double kBTol = 1e-14;   // breakdown threshold, as in the main path
 
-enum : int { PH_IDLE = 0, PH_BUILD = 1, PH_CYCLE = 2, PH_TEST = 3 };
+enum : int { PH_IDLE = 0, PH_BUILD = 1, PH_CYCLE = 2, PH_TEST = 3, PH_RR = 4 };
 
 }  // namespace
 
@@ -55,8 +59,15 @@ struct BSlot {
     const double* start;
     const double* rre;   // polynomial roots, application order
     const double* rim;
+    const float* val32;  // FP32 copy of the values (mixed precision), else null
+    float* f1;           // FP32 chain vectors (mixed precision)
+    float* f2;
+    float* f3;
+    float* f4;
     int n, ld, ldh;
     int phase, init, restart, use_poly;
+    int f32;             // CYCLE: pi(A) in FP32
+    int ystart;          // CYCLE: start from Y Q (qin columns of Y, one output), normalised
     int j, jend, budget, deg;
     int qin, qout;
     int nw, ycols;
@@ -111,6 +122,61 @@ __device__ void wg_pass(const BSlot& S, double alpha, const double* x, double be
         out[r] = beta * s + alpha * xv + gamma * zv + 0.0 * 0.0;
     }
     __syncthreads();
+}
+
+// FP32 form of wg_pass for the mixed-precision chain (no z term: the chain
+// never uses it); the result goes to out32, or, when out64 is given, is
+// stored there widened to FP64.
+__device__ void wg_pass32(const BSlot& S, float alpha, const float* x, float beta, const float* u,
+                          float* out32, double* out64) {
+    for (int r = threadIdx.x; r < S.n; r += BWG) {
+        const int a = S.rowptr[r], e = S.rowptr[r + 1];
+        float s = 0.0f;
+        for (int k = a; k < e; ++k) s += S.val32[k] * u[S.colind[k]];
+        const float xv = x ? x[r] : 0.0f;
+        const float o = beta * s + alpha * xv + 0.0f * 0.0f;
+        if (out64)
+            out64[r] = (double)o;
+        else
+            out32[r] = o;
+    }
+    __syncthreads();
+}
+
+__device__ float* pick3f(const BSlot& S, const float* a, const float* b) {
+    float* c[3] = {S.f1, S.f2, S.f3};
+    for (int i = 0; i < 3; ++i)
+        if (c[i] != a && c[i] != b) return c[i];
+    return S.f3;
+}
+
+// y = pi(A) v with the chain in FP32: v rounded to FP32 once, every factor
+// in FP32 (coefficients formed in FP64, then rounded), the last factor's
+// result widened into y
+__device__ void wg_apply32(const BSlot& S, const double* v, double* y) {
+    for (int r = threadIdx.x; r < S.n; r += BWG) S.f4[r] = (float)v[r];
+    __syncthreads();
+    const float* cur = S.f4;
+    int i = 0;
+    while (i < S.deg) {
+        const double re = S.rre[i], im = S.rim[i];
+        const bool pair = im != 0.0;
+        const bool last = i + (pair ? 2 : 1) >= S.deg;
+        if (!pair) {
+            float* nx = last ? nullptr : pick3f(S, cur, nullptr);
+            wg_pass32(S, 1.0f, cur, (float)(-1.0 / re), cur, nx, last ? y : nullptr);
+            cur = nx;
+            i += 1;
+        } else {
+            const double q = re * re + im * im;
+            float* sb = pick3f(S, cur, nullptr);
+            wg_pass32(S, (float)(2.0 * re), cur, -1.0f, cur, sb, nullptr);
+            float* nx = last ? nullptr : pick3f(S, cur, sb);
+            wg_pass32(S, 1.0f, cur, (float)(-1.0 / q), sb, nx, last ? y : nullptr);
+            cur = nx;
+            i += 2;
+        }
+    }
 }
 
 __device__ double* pick3(const BSlot& S, const double* a, const double* b) {
@@ -253,21 +319,39 @@ __global__ __launch_bounds__(BWG) void k_batch(BSlot* __restrict__ slots) {
     __shared__ double Qs[65 * 64];
     BSlot& S = slots[blockIdx.x];
     if (S.phase == PH_IDLE) return;
+    if (S.phase == PH_RR) {
+        // K = V^T (A V) over the first qin basis columns: A V into V2, then
+        // column c of K (qin entries) into Q + c qin
+        for (int c = 0; c < S.qin; ++c)
+            wg_pass(S, 0.0, nullptr, 1.0, S.V + (size_t)c * S.ld, 0.0, nullptr, S.V2 + (size_t)c * S.ld);
+        for (int c = 0; c < S.qin; ++c)
+            wg_proj(S, S.V, S.qin, S.V2 + (size_t)c * S.ld, S.Q + (size_t)c * S.qin, red);
+        if (threadIdx.x == 0) S.j_done = S.j;
+        return;
+    }
     if (S.phase == PH_BUILD || S.phase == PH_CYCLE) {
         double* V = S.V;
-        if (S.restart) {
-            // thick restart: V2 = V Q (Q staged in LDS), then continue on V2
+        if (S.restart || S.ystart) {
+            // thick restart: V2 = V Q (Q staged in LDS), then continue on V2;
+            // FP64 restart of a mixed solve: the start vector Y Q into t2
             for (int i = threadIdx.x; i < S.qin * S.qout; i += BWG) Qs[i] = S.Q[i];
             __syncthreads();
-            wg_gemm(S, S.V, Qs, S.qin, S.qout, S.V2);
-            V = S.V2;
+            if (S.restart) {
+                wg_gemm(S, S.V, Qs, S.qin, S.qout, S.V2);
+                V = S.V2;
+            } else {
+                wg_gemm(S, S.Y, Qs, S.qin, 1, S.t2);
+                wg_normalise(S, S.t2, V, red, tmp);
+            }
         }
         if (S.init) wg_normalise(S, S.start, V, red, tmp);
         int j = S.j, used = 0;
         const int cost = S.use_poly ? S.deg : 1;
         while (j < S.jend && (used == 0 || used + cost <= S.budget)) {
             const double* vj = V + (size_t)j * S.ld;
-            if (S.use_poly)
+            if (S.use_poly && S.f32)
+                wg_apply32(S, vj, S.w);
+            else if (S.use_poly)
                 wg_apply(S, vj, S.w);
             else
                 wg_pass(S, 0.0, nullptr, 1.0, vj, 0.0, nullptr, S.w);
@@ -342,7 +426,7 @@ __global__ __launch_bounds__(BWG) void k_batch(BSlot* __restrict__ slots) {
 // ---------------------------------------------------------------- host driver
 namespace {
 
-enum : int { ST_FREE = 0, ST_BUILD = 1, ST_CYCLE = 2, ST_TEST = 3, ST_DONE = 4 };
+enum : int { ST_FREE = 0, ST_BUILD = 1, ST_CYCLE = 2, ST_TEST = 3, ST_DONE = 4, ST_RR = 5 };
 
 struct BReqState {
     int state = ST_FREE;
@@ -354,7 +438,15 @@ struct BReqState {
     double *V = nullptr, *V2 = nullptr, *w = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
     double *H = nullptr, *Y = nullptr, *AY = nullptr, *Q = nullptr, *out = nullptr;
     double *rre = nullptr, *rim = nullptr;
+    float* val32 = nullptr;   // mixed precision: FP32 values and chain vectors
+    float *f1 = nullptr, *f2 = nullptr, *f3 = nullptr, *f4 = nullptr;
     int ld = 0, ldh = 0;
+    // mixed precision: FP32 phase on, the pending test is the closing
+    // Rayleigh-Ritz pass's, the next cycle starts from Y Q
+    bool f32 = false, rr_test = false, ystart = false;
+    std::vector<double> hist;   // largest wanted residual per cycle
+    int fp32_cycles = 0;
+    int64_t passes32 = 0;
     // progress
     int j = 0, jend = 0, cycle = 0, deg = 0;
     int jstart = 0;   // first Krylov step of the current cycle (0, or kept vectors)
@@ -377,7 +469,7 @@ struct BReqState {
     std::string err;
 };
 
-size_t carve_batch(Carver& c, int64_t n, int d, int m, int nev, BReqState* s) {
+size_t carve_batch(Carver& c, int64_t n, int d, int m, int nev, int64_t nnz, bool mixed, BReqState* s) {
     const int cols = std::max(m, d) + 1;
     const int64_t ld = col_ld(n);
     double* V = c.take<double>((size_t)ld * cols);
@@ -393,9 +485,16 @@ size_t carve_batch(Carver& c, int64_t n, int d, int m, int nev, BReqState* s) {
     double* out = c.take<double>(4 * BMAXW);
     double* rre = c.take<double>(std::max(d, 1));
     double* rim = c.take<double>(std::max(d, 1));
+    float *v32 = nullptr, *f[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (mixed) {
+        v32 = c.take<float>((size_t)std::max<int64_t>(nnz, 1));
+        for (int i = 0; i < 4; ++i) f[i] = c.take<float>((size_t)n);
+    }
     if (s) {
         s->V = V; s->V2 = V2; s->w = w; s->t1 = t1; s->t2 = t2; s->t3 = t3;
         s->H = H; s->Y = Y; s->AY = AY; s->Q = Q; s->out = out; s->rre = rre; s->rim = rim;
+        s->val32 = v32;
+        s->f1 = f[0]; s->f2 = f[1]; s->f3 = f[2]; s->f4 = f[3];
         s->ld = (int)ld;
         s->ldh = cols;
     }
@@ -431,6 +530,11 @@ static void batch_fill(BReqState& q, BSlot& d) {
     d.out = q.out;
     d.rre = q.rre;
     d.rim = q.rim;
+    d.val32 = q.val32;
+    d.f1 = q.f1;
+    d.f2 = q.f2;
+    d.f3 = q.f3;
+    d.f4 = q.f4;
     d.n = (int)q.rq.n;
     d.ld = q.ld;
     d.ldh = q.ldh;
@@ -508,6 +612,27 @@ static void batch_finish_cycle(BReqState& q, hipStream_t s) {
     q.qin = mc;
     q.qout = q.plan.ycols;
     q.hm_last = H[m + (size_t)(m - 1) * ldh];
+    if (q.f32) ++q.fp32_cycles;
+    q.state = ST_TEST;
+}
+
+// Closing FP64 Rayleigh-Ritz pass of a mixed-precision solve: K = V^T A V
+// (downloaded from Q) and its Ritz pairs nearest the origin, tested next on
+// A as every cycle's pairs are.
+static void batch_finish_rr(BReqState& q, hipStream_t s) {
+    const int J = q.qin;
+    std::vector<double> K((size_t)J * J);
+    PPA_HIP(hipMemcpyAsync(K.data(), q.Q, K.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    for (double x : K)
+        if (!std::isfinite(x)) fail(PPA_ERR_NONFINITE, "batched closing Rayleigh-Ritz: non-finite projection");
+    q.mvps += J;
+    q.dots += (int64_t)J * J;
+    q.plan = plan_ritz(K, J, q.rq.nev, 0.0);
+    PPA_HIP(hipMemcpyAsync(q.Q, q.plan.Gw.data(), q.plan.Gw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    q.qin = J;
+    q.qout = q.plan.ycols;
+    q.rr_test = true;
     q.state = ST_TEST;
 }
 
@@ -533,6 +658,33 @@ static bool batch_finish_test(BReqState& q, hipStream_t s) {
     q.mvps += ritz_mvps(R);
     const double rtol_abs = q.rq.rtol * q.anorm;
     const bool conv = nw == nev && mx <= rtol_abs;
+    if (q.rr_test) {
+        // the closing Rayleigh-Ritz pass: done if all wanted pairs meet rtol,
+        // else FP64 cycles from the sum of these unit Ritz vectors
+        q.rr_test = false;
+        q.hist.back() = std::min(q.hist.back(), mx);
+        if (!conv) {
+            double yn[BMAXW];
+            for (int i = 0; i < nw; ++i) yn[i] = out[3 * BMAXW + i];
+            const std::vector<double> coef = fp64_restart_coef(R, std::vector<double>(yn, yn + nw));
+            PPA_HIP(hipMemcpyAsync(q.Q, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            launch_zero(q.H, (int64_t)q.ldh * (q.ldh - 1), s);
+            PPA_HIP(hipStreamSynchronize(s));
+            q.qin = R.ycols;
+            q.qout = 1;
+            q.ystart = true;
+            q.restart = false;
+            q.init = false;
+            q.j = 0;
+            q.jstart = 0;
+            q.jend = m;
+            q.cycle += 1;
+            q.state = ST_CYCLE;
+            return false;
+        }
+    } else {
+        q.hist.push_back(mx);
+    }
     if (conv || q.broke || q.cycle >= q.rq.max_cycles) {
         q.mu = mu;
         q.res = res;
@@ -542,6 +694,14 @@ static bool batch_finish_test(BReqState& q, hipStream_t s) {
         q.status = conv ? PPA_OK : (q.broke ? PPA_WARN_BREAKDOWN : PPA_WARN_NOT_CONVERGED);
         q.state = ST_DONE;
         return true;
+    }
+    if (q.f32 && leave_fp32(q.hist, q.anorm)) {
+        // leave the FP32 phase: closing Rayleigh-Ritz with A on the m + 1
+        // basis vectors the FP32 cycle built
+        q.f32 = false;
+        q.qin = q.mc + 1;
+        q.state = ST_RR;
+        return false;
     }
     const RestartPlan RP = plan_restart(R, q.Hm, q.hm_last, m, q.rq.k);
     PPA_HIP(hipMemcpyAsync(q.Q, RP.Qp.data(), RP.Qp.size() * sizeof(double), hipMemcpyHostToDevice, s));
@@ -580,9 +740,9 @@ __global__ void k_absrowmax(const int32_t* __restrict__ rowptr, const double* __
     if (threadIdx.x == 0) out[0] = sm[0];
 }
 
-size_t batch_ws_bytes(int64_t n, int d, int m, int nev) {
+size_t batch_ws_bytes(int64_t n, int d, int m, int nev, int64_t nnz, int precision) {
     Carver c(nullptr, 0);
-    return carve_batch(c, n, d, m, nev, nullptr);
+    return carve_batch(c, n, d, m, nev, nnz, precision == PPA_MIXED, nullptr);
 }
 
 Batch* batch_create(int max_slots, hipStream_t s) {
@@ -605,7 +765,8 @@ void batch_destroy(Batch* B) {
     delete B;
 }
 
-int batch_submit(Batch& B, const ppa_batch_request& rq, int* slot) {
+int batch_submit(Batch& B, const ppa_batch_request& rq, int* slot, int precision) {
+    PPA_REQUIRE(precision == PPA_F64 || precision == PPA_MIXED, "batch: precision must be F64 or MIXED");
     PPA_REQUIRE(rq.n >= 1 && rq.n < (int64_t(1) << 31), "batch: n out of range");
     PPA_REQUIRE(rq.rowptr_d && rq.colind_d && rq.val_d && rq.b_d && rq.v0_d && rq.ws_d,
                 "batch: matrix, start vectors and workspace are required");
@@ -626,9 +787,20 @@ int batch_submit(Batch& B, const ppa_batch_request& rq, int* slot) {
     }
     BReqState q;
     q.rq = rq;
+    const bool mixed = precision == PPA_MIXED;
+    int32_t nnz = 0;
+    if (mixed) {
+        PPA_HIP(hipMemcpyAsync(&nnz, rq.rowptr_d + rq.n, sizeof(int32_t), hipMemcpyDeviceToHost, B.s));
+        PPA_HIP(hipStreamSynchronize(B.s));
+        PPA_REQUIRE(nnz >= 0, "batch: negative nonzero count");
+    }
     Carver c(rq.ws_d, rq.ws_bytes);
-    carve_batch(c, rq.n, rq.d, rq.m, rq.nev, &q);
+    carve_batch(c, rq.n, rq.d, rq.m, rq.nev, nnz, mixed, &q);
     c.check();
+    if (mixed) {
+        launch_cast_f64_f32(rq.val_d, q.val32, nnz, B.s);
+        q.f32 = true;
+    }
     // ||A||_inf (one small reduction) unless given
     if (rq.anorm > 0.0) {
         q.anorm = rq.anorm;
@@ -652,7 +824,7 @@ int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive) {
     std::vector<int> act;
     for (int i = 0; i < B.max_slots; ++i) {
         const int st = B.st[i].state;
-        if (st == ST_BUILD || st == ST_CYCLE || st == ST_TEST) act.push_back(i);
+        if (st == ST_BUILD || st == ST_CYCLE || st == ST_TEST || st == ST_RR) act.push_back(i);
     }
     *nfin = 0;
     if (nactive) *nactive = (int)act.size();
@@ -676,9 +848,14 @@ int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive) {
             d.init = q.init;
             d.start = q.rq.v0_d;
             d.restart = q.restart;
+            d.ystart = q.ystart;
+            d.f32 = q.f32;
             d.qin = q.qin;
             d.qout = q.qout;
             d.jend = q.jend;
+        } else if (q.state == ST_RR) {
+            d.phase = PH_RR;
+            d.qin = q.qin;
         } else {
             d.phase = PH_TEST;
             d.qin = q.qin;
@@ -714,14 +891,18 @@ int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive) {
                     q.mvps += op;
                     q.vops += op + 4 * (jj + 1) + 2;
                     q.dots += 2 * (jj + 1) + 1;
+                    if (q.f32) q.passes32 += op;
                 }
                 if (q.restart) {
                     std::swap(q.V, q.V2);
                     q.restart = false;
                 }
+                q.ystart = false;
                 q.init = false;
                 q.j = jd;
                 if (q.j >= q.jend) batch_finish_cycle(q, B.s);
+            } else if (q.state == ST_RR) {
+                batch_finish_rr(q, B.s);
             } else {
                 if (batch_finish_test(q, B.s)) {
                     if (nf < cap && finished) finished[nf] = slot;
@@ -781,9 +962,9 @@ int batch_result(Batch& B, int slot, ppa_eigs_result& r) {
         r.dots = q.dots;
         r.vops = q.vops;
         r.max_resid = mx;
-        r.fp32_cycles = 0;
+        r.fp32_cycles = q.fp32_cycles;
         r.spmv_passes = q.mvps;
-        r.spmv_passes_f32 = 0;
+        r.spmv_passes_f32 = q.passes32;
         r.t_apply_ms = r.t_cgs_ms = 0.0;
     }
     B.st[slot] = BReqState();

@@ -563,11 +563,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
             // progress far above the floor is the method's, not the
             // precision's, and FP64 cycles would not speed it up); restart in
             // FP64 from the sum of the wanted unit Ritz vectors
-            const size_t hc = hist.size();
-            const double floor_abs = 100.0 * 1.1920929e-07 * anorm;
-            const bool floor = mx <= floor_abs;
-            const bool stall = hc >= 3 && hist[hc - 1] > 0.5 * hist[hc - 3] && mx <= 1e3 * floor_abs;
-            if (floor || stall) {
+            if (leave_fp32(hist, anorm)) {
                 fp32 = false;
                 // closing FP64 Rayleigh-Ritz with A itself on the FP32-built
                 // basis V_{m+1} (FP64 storage, orthonormal to FP64 rounding):
@@ -598,12 +594,7 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
                     converged = true;
                     break;
                 }
-                std::vector<double> coef(R2.ycols, 0.0);
-                for (int i = 0; i < R2.nw; ++i) {
-                    if (R2.dup[i]) continue;
-                    coef[R2.cre[i]] += 1.0 / Rr2.ynorm[i];
-                    if (R2.cim[i] >= 0) coef[R2.cim[i]] += 1.0 / Rr2.ynorm[i];
-                }
+                const std::vector<double> coef = fp64_restart_coef(R2, Rr2.ynorm);
                 PPA_HIP(hipMemcpyAsync(e.Qd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
                 launch_gemm_tall(n, R2.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
                 launch_zero(e.Hd, (int64_t)(m + 1) * m, s);

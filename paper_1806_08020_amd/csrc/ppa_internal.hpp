@@ -431,6 +431,17 @@ struct RestartPlan {
 };
 RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, double hm, int m, int k);
 
+// Mixed precision (FP32 pi(A)v, FP64 elsewhere), shared by the single-solve
+// driver and the batched engine.  leave_fp32: after an FP32 cycle whose
+// largest wanted residual is hist.back() (hist: one maximum per cycle so far),
+// whether the FP32 phase ends: the residuals reached the FP32 floor
+// 100 eps_32 ||A||, or stopped improving (less than 2x over two cycles) within
+// three decades of it.  fp64_restart_coef: coefficients over the ycols
+// columns of Y of the sum of the wanted unit Ritz vectors, the FP64 restart
+// vector when the closing Rayleigh-Ritz pass does not meet the tolerance.
+bool leave_fp32(const std::vector<double>& hist, double anorm);
+std::vector<double> fp64_restart_coef(const RitzPlan& R, const std::vector<double>& ynorm);
+
 // polynomial construction and Arnoldi drivers (eigs.cpp)
 size_t poly_build_ws(int64_t n, int d, bool dbl);
 int poly_build(const Matrix& A, int d1, int d2, const double* b, void* ws, size_t ws_bytes,
@@ -444,10 +455,12 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
 
 // ---------------------------------------------------------------- batched engine (batch.hip)
 struct Batch;
-size_t batch_ws_bytes(int64_t n, int d, int m, int nev);
+// nnz and precision (PPA_F64 or PPA_MIXED) matter only for PPA_MIXED: room
+// for the FP32 values and the FP32 chain vectors.
+size_t batch_ws_bytes(int64_t n, int d, int m, int nev, int64_t nnz = 0, int precision = PPA_F64);
 Batch* batch_create(int max_slots, hipStream_t s);
 void batch_destroy(Batch* B);
-int batch_submit(Batch& B, const ppa_batch_request& rq, int* slot);
+int batch_submit(Batch& B, const ppa_batch_request& rq, int* slot, int precision = PPA_F64);
 int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive);
 int batch_result(Batch& B, int slot, ppa_eigs_result& r);
 

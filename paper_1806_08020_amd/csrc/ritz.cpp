@@ -159,6 +159,26 @@ int64_t ritz_mvps(const RitzPlan& R) {
     return m;
 }
 
+bool leave_fp32(const std::vector<double>& hist, double anorm) {
+    const size_t hc = hist.size();
+    if (hc == 0) return false;
+    const double mx = hist[hc - 1];
+    const double floor_abs = 100.0 * 1.1920929e-07 * anorm;
+    const bool floor = mx <= floor_abs;
+    const bool stall = hc >= 3 && mx > 0.5 * hist[hc - 3] && mx <= 1e3 * floor_abs;
+    return floor || stall;
+}
+
+std::vector<double> fp64_restart_coef(const RitzPlan& R, const std::vector<double>& ynorm) {
+    std::vector<double> coef(R.ycols, 0.0);
+    for (int i = 0; i < R.nw; ++i) {
+        if (R.dup[i]) continue;
+        coef[R.cre[i]] += 1.0 / ynorm[i];
+        if (R.cim[i] >= 0) coef[R.cim[i]] += 1.0 / ynorm[i];
+    }
+    return coef;
+}
+
 RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, double hm, int m, int k) {
     const int mc = R.mc;
     RestartPlan P;

@@ -108,9 +108,11 @@ def _load():
         "ppa_eigs_workspace_bytes": (i, [vp, vp, P(EigsOpts), P(sz)]),
         "ppa_eigs": (i, [vp, vp, P(EigsOpts), vp, vp, sz, vp, P(EigsResult)]),
         "ppa_batch_workspace_bytes": (i, [i64, i, i, i, P(sz)]),
+        "ppa_batch_workspace_bytes_ex": (i, [i64, i64, i, i, i, i, P(sz)]),
         "ppa_batch_create": (i, [i, vp, P(vp)]),
         "ppa_batch_destroy": (i, [vp]),
         "ppa_batch_submit": (i, [vp, P(BatchRequest), P(i)]),
+        "ppa_batch_submit_ex": (i, [vp, P(BatchRequest), i, P(i)]),
         "ppa_batch_step": (i, [vp, P(i), i, P(i), P(i)]),
         "ppa_batch_result": (i, [vp, i, P(EigsResult)]),
         "ppa_dense_eig": (i, [i, P(d), P(d), P(d), P(d), P(d)]),
@@ -509,9 +511,14 @@ def eigs(A: Matrix, p: Poly | None, v0: torch.Tensor, m: int, k: int, nev: int, 
 PPA_ERR_BUSY = -7
 
 
-def batch_workspace_bytes(n: int, d: int, m: int, nev: int) -> int:
+def batch_workspace_bytes(n: int, d: int, m: int, nev: int, nnz: int = 0, precision: str = "f64") -> int:
+    """Workspace of one batched request; "mixed" also holds FP32 values (nnz)
+    and the FP32 chain vectors."""
     nb = C.c_size_t()
-    _check(_lib.ppa_batch_workspace_bytes(n, d, m, nev, C.byref(nb)))
+    if precision == "f64":
+        _check(_lib.ppa_batch_workspace_bytes(n, d, m, nev, C.byref(nb)))
+    else:
+        _check(_lib.ppa_batch_workspace_bytes_ex(n, nnz, d, m, nev, _PREC[precision], C.byref(nb)))
     return nb.value
 
 
@@ -530,16 +537,22 @@ class Batch:
         self._fin = (C.c_int * max_slots)()
 
     def submit(self, rowptr, colind, vals, d, m, k, nev, b, v0, rtol=1e-8, max_cycles=50,
-               anorm=0.0, ws=None):
+               anorm=0.0, ws=None, precision="f64"):
         """Admit one solve; device tensors stay referenced until its result is
-        taken.  Returns the slot, or None when the engine is full."""
+        taken.  precision: "f64" or "mixed" (FP32 pi(A)v, closing FP64
+        Rayleigh-Ritz).  Returns the slot, or None when the engine is full."""
         n = rowptr.numel() - 1
+        if precision not in ("f64", "mixed"):
+            raise ValueError("precision must be 'f64' or 'mixed'")
         if ws is None:
-            ws = _workspace(batch_workspace_bytes(n, d, m, nev))
+            ws = _workspace(batch_workspace_bytes(n, d, m, nev, vals.numel(), precision))
         rq = BatchRequest(n, _ptr(rowptr), _ptr(colind), _ptr(vals), anorm, d, m, k, nev, max_cycles,
                           rtol, _ptr(b), _ptr(v0), _ptr(ws), ws.numel())
         slot = C.c_int(-1)
-        st = _lib.ppa_batch_submit(self.h, C.byref(rq), C.byref(slot))
+        if precision == "f64":
+            st = _lib.ppa_batch_submit(self.h, C.byref(rq), C.byref(slot))
+        else:
+            st = _lib.ppa_batch_submit_ex(self.h, C.byref(rq), _PREC[precision], C.byref(slot))
         if st == PPA_ERR_BUSY:
             return None
         _check(st)
@@ -564,7 +577,8 @@ class Batch:
         del self._keep[slot]
         return EigsOut(status=st, mu=lre + 1j * lim, resid=res.copy(), nu=nre + 1j * nim, nconv=r.nconv,
                        cycles=r.cycles, mvps=r.mvps, dots=r.dots, vops=r.vops, max_resid=r.max_resid,
-                       fp32_cycles=0, spmv_passes=r.spmv_passes, converged=(st == PPA_OK))
+                       fp32_cycles=r.fp32_cycles, spmv_passes=r.spmv_passes,
+                       spmv_passes_f32=r.spmv_passes_f32, converged=(st == PPA_OK))
 
     def __del__(self):
         h = getattr(self, "h", None)

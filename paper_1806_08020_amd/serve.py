@@ -42,7 +42,7 @@ class Request:
     rtol: float = 1e-8
     max_cycles: int = 30
     arrival: float = 0.0          # seconds after the start of the run
-    precision: str = "f64"        # "f64" or "mixed" (mixed applies to the stream path)
+    precision: str = "f64"        # "f64" or "mixed" (FP32 pi(A)v on either path)
     graph: bool = False           # stream path: replay restart cycles from HIP graphs
     lowsync: bool = False         # stream path: delayed-reorthogonalisation Gram-Schmidt
 
@@ -82,7 +82,8 @@ def stream_footprint(rq: Request) -> int:
 
 
 def batch_footprint(rq: Request) -> int:
-    return csr_bytes(rq.csr) + 16 * rq.csr.n + ppa.batch_workspace_bytes(rq.csr.n, rq.d, rq.m, rq.nev)
+    return csr_bytes(rq.csr) + 16 * rq.csr.n + ppa.batch_workspace_bytes(
+        rq.csr.n, rq.d, rq.m, rq.nev, int(rq.csr.nnz), rq.precision)
 
 
 def _solve_stream(rq: Request, stream: torch.cuda.Stream, window: str = "auto",
@@ -154,7 +155,8 @@ class Server:
                         b = torch.as_tensor(rq.b).to("cuda")
                         v0 = torch.as_tensor(rq.v0).to("cuda")
                     slot = self.batch.submit(rp, ci, va, rq.d, rq.m, rq.k, rq.nev, b, v0,
-                                             rtol=rq.rtol, max_cycles=rq.max_cycles)
+                                             rtol=rq.rtol, max_cycles=rq.max_cycles,
+                                             precision=rq.precision)
                     if slot is None:
                         continue
                     in_batch[slot] = (rq, clock() - t0, fp)
@@ -249,8 +251,8 @@ def summarize(done: list[Completion], wall: float) -> dict:
 
 
 def _path_summary(done: list[Completion]) -> dict:
-    """Latency and work of the requests one path served (the batched engine
-    runs FP64 only; a mixed-precision run applies to the stream path)."""
+    """Latency and work of the requests one path served (batched engine or
+    whole solves on worker streams)."""
     if not done:
         return {"requests": 0}
     lat = np.array([c.latency for c in done])
@@ -258,4 +260,6 @@ def _path_summary(done: list[Completion]) -> dict:
     return {"requests": len(done), "converged": sum(1 for c in ok if c.result.converged),
             "eigenpairs": int(sum(c.result.nconv for c in ok)),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_n": float(np.mean([c.n for c in done]))}
+            "mean_n": float(np.mean([c.n for c in done])),
+            "fp32_cycles": int(sum(c.result.fp32_cycles for c in ok)),
+            "cycles": int(sum(c.result.cycles for c in ok))}

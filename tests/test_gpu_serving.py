@@ -98,15 +98,15 @@ def make_req(csr, seed, d, m, k, nev):
     return dict(csr=csr, b=b, v0=v0, d=d, m=m, k=k, nev=nev)
 
 
-def submit(lib, B, rq, max_cycles=40):
+def submit(lib, B, rq, max_cycles=40, precision="f64"):
     c = rq["csr"]
     return B.submit(dev(c.rowptr), dev(c.colind), dev(c.vals), rq["d"], rq["m"], rq["k"], rq["nev"],
-                    dev(rq["b"]), dev(rq["v0"]), rtol=1e-8, max_cycles=max_cycles)
+                    dev(rq["b"]), dev(rq["v0"]), rtol=1e-8, max_cycles=max_cycles, precision=precision)
 
 
-def run_alone(lib, rq):
+def run_alone(lib, rq, precision="f64"):
     B = lib.Batch(4)
-    s = submit(lib, B, rq)
+    s = submit(lib, B, rq, precision=precision)
     while True:
         fin, _ = B.step()
         if s in fin:
@@ -179,6 +179,76 @@ def test_batch_alone_equals_mix(lib):
             assert abs(mu - ores.mu[t]) <= tol, (i, mu, ores.mu[t], tol)
 
 
+def test_batch_mixed_precision_eigenvalues(lib):
+    """Mixed precision in the batched engine (FP32 pi(A)v, FP64 elsewhere,
+    the closing FP64 Rayleigh-Ritz pass): every request converges to rtol on
+    A in FP64 after at least one FP32 cycle, every eigenvalue lies within its
+    certified distance of the closed form, and within the sum of both runs'
+    bounds of the FP64 oracle's."""
+    for i, rq in enumerate(REQS):
+        r = run_alone(lib, rq, "mixed")
+        anorm = O.infnorm(rq["csr"])
+        print(f"request {i}: cycles {r.cycles}, fp32 cycles {r.fp32_cycles}, mvps {r.mvps}, "
+              f"fp32 passes {r.spmv_passes_f32}, max resid {r.max_resid / anorm:.2e}", flush=True)
+        assert r.converged and r.nconv == rq["nev"], i
+        assert r.fp32_cycles >= 1 and 0 < r.spmv_passes_f32 < r.spmv_passes, i
+        check_eigenvalues(i, r, anorm)
+        ores, _ = O.pp_eigs(rq["csr"], rq["b"], rq["v0"], m=rq["m"], k=rq["k"], nev=rq["nev"],
+                            d=rq["d"], rtol=1e-8, max_cycles=40)
+        lam, kap, sym = closed_for(i)
+        for mu, res in zip(r.mu, r.resid):
+            t = int(np.argmin(np.abs(ores.mu - mu)))
+            tl = int(np.argmin(np.abs(lam - mu.real)))
+            tol = (2e-10 * abs(mu) if sym else 2.0 * kap[tl] * (res + ores.resid[t])) + 2e-14 * anorm
+            assert abs(mu - ores.mu[t]) <= tol, (i, mu, ores.mu[t], tol)
+
+
+def test_batch_mixed_alone_equals_mix(lib):
+    """Mixed and FP64 solves share one engine: each result is bitwise the one
+    computed alone in its own precision."""
+    prec = ["mixed", "f64", "mixed", "mixed", "f64"]
+    alone = [run_alone(lib, rq, p) for rq, p in zip(REQS, prec)]
+    B = lib.Batch(8)
+    slots = {}
+    for i in (0, 1):
+        slots[submit(lib, B, REQS[i], precision=prec[i])] = i
+    got = {}
+    steps = 0
+    while len(got) < len(REQS):
+        fin, _ = B.step()
+        steps += 1
+        for s in fin:
+            got[slots.pop(s)] = B.result(s)
+        if steps == 3:
+            for i in (2, 3, 4):
+                slots[submit(lib, B, REQS[i], precision=prec[i])] = i
+        assert steps < 2000
+    for i, a in enumerate(alone):
+        g = got[i]
+        assert np.array_equal(a.mu, g.mu) and np.array_equal(a.resid, g.resid), i
+        assert (a.cycles, a.fp32_cycles, a.mvps, a.dots, a.spmv_passes_f32) == \
+            (g.cycles, g.fp32_cycles, g.mvps, g.dots, g.spmv_passes_f32), i
+
+
+def test_batch_mixed_workspace_and_precision_checks(lib):
+    """The mixed workspace adds the FP32 values and four FP32 vectors; an
+    unknown precision is refused."""
+    from paper_1806_08020_amd import ppa
+    c = REQS[1]["csr"]
+    f64 = ppa.batch_workspace_bytes(c.n, 12, 30, 7)
+    mixed = ppa.batch_workspace_bytes(c.n, 12, 30, 7, c.nnz, "mixed")
+    assert mixed >= f64 + 4 * c.nnz + 16 * c.n
+    B = lib.Batch(2)
+    with pytest.raises(ValueError):
+        submit(lib, B, REQS[1], precision="f32")
+    # a workspace sized for FP64 is too small for a mixed request
+    rq = REQS[1]
+    ws = torch.empty(f64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ppa.PPAError):
+        B.submit(dev(c.rowptr), dev(c.colind), dev(c.vals), rq["d"], rq["m"], rq["k"], rq["nev"],
+                 dev(rq["b"]), dev(rq["v0"]), ws=ws, precision="mixed")
+
+
 def test_batch_full_engine_reports_busy(lib):
     B = lib.Batch(1)
     assert submit(lib, B, REQS[0]) is not None
@@ -216,6 +286,36 @@ def test_server_budget_and_identity(lib):
     A = lib.Matrix(big)
     r2 = lib.eigs(A, lib.Poly.build(A, 20, dev(b)), dev(v0), 30, 12, 6, rtol=1e-8, max_cycles=20)
     assert np.array_equal(r2.mu, cbig.result.mu)
+
+
+def test_server_mixed_both_paths(lib):
+    """Mixed-precision requests through the server: the small ones run in the
+    batched engine with FP32 cycles and equal their alone runs bitwise, the
+    large one runs on a worker stream and equals the single-solve path."""
+    from paper_1806_08020_amd import serve as S
+    reqs = [S.Request(i, rq["csr"], rq["d"], rq["m"], rq["k"], rq["nev"], rq["b"], rq["v0"],
+                      1e-8, 40, arrival=0.0, precision="mixed") for i, rq in enumerate(REQS[:3])]
+    big = W.convdiff_2d(200, 0.2)
+    b, v0 = W.start_vectors(big.n, 77)
+    reqs.append(S.Request(3, big, 20, 30, 12, 6, b, v0, 1e-8, 20, arrival=0.0, precision="mixed"))
+    srv = S.Server(hbm_budget=8 << 30, max_slots=4, small_n=16384, stream_workers=1)
+    try:
+        done = srv.run(reqs)
+    finally:
+        srv.close()
+    assert all(c.error is None for c in done)
+    for c in done[:3]:
+        assert c.path == "batch" and c.result.fp32_cycles >= 1
+        a = run_alone(lib, REQS[c.rid], "mixed")
+        assert np.array_equal(a.mu, c.result.mu) and np.array_equal(a.resid, c.result.resid)
+    cbig = done[3]
+    assert cbig.path == "stream" and cbig.result.fp32_cycles >= 1
+    A = lib.Matrix(big, want_f32=True)
+    r2 = lib.eigs(A, lib.Poly.build(A, 20, dev(b)), dev(v0), 30, 12, 6, rtol=1e-8, max_cycles=20,
+                  precision="mixed")
+    assert np.array_equal(r2.mu, cbig.result.mu)
+    summ = S.summarize(done, 1.0)
+    assert summ["by_path"]["batch"]["fp32_cycles"] >= 3
 
 
 def test_server_rejects_request_above_budget(lib):
