@@ -31,7 +31,10 @@ namespace ppa {
 
 namespace {
 
-constexpr int BWG = 512;          // threads per workgroup
+#ifndef PPA_BATCH_WG
+#define PPA_BATCH_WG 1024
+#endif
+constexpr int BWG = PPA_BATCH_WG; // threads per workgroup
 constexpr int BNW = BWG / 64;
 constexpr int BMAXJ = 128;        // largest basis (GMRES degree or m) + 1
 constexpr int BMAXW = 32;         // largest nev
