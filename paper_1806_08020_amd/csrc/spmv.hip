@@ -1526,6 +1526,13 @@ void matrix_setup(Matrix& A, hipStream_t s) {
     const double ws32 = 8.0 * A.nnz + 4.0 * (n + 1) + 12.0 * n;
     A.cp64 = ws64 <= keep ? CP_KEEP : CP_STREAM;
     A.cp32 = ws32 <= keep ? CP_KEEP : CP_STREAM;
+    // untimed default block shape: the small blocks (eight times as many,
+    // shorter-lived workgroups) for a matrix served from the last-level cache
+    // whose large partition already fills the CUs several times over; below
+    // that a pass is bound by launch latency and the shape does not matter
+    const bool many = A.nblocks >= 4 * 256 && !A.long_s && A.nblocks_s > 0;
+    A.blk64 = many && ws64 <= keep ? 1 : 0;
+    A.blk32 = many && ws32 <= keep ? 1 : 0;
 }
 
 // Average time of `reps` passes with the current kernel choice.

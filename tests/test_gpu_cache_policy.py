@@ -117,12 +117,17 @@ def test_tuned_policy_full_size_bitwise(lib):
 
 def test_no_tune_keeps_size_rule(lib):
     """PPA_MATRIX_NO_TUNE: no timing at creation, so the size rule's cache
-    policy, the large block shape and the plain kernel (a forced variant is
-    still built); results equal the timed matrix's bit for bit."""
+    policy and block shape (a pass served from the last-level cache with at
+    least 1024 large blocks: the small blocks) and the plain kernel (a forced
+    variant is still built); results equal the timed matrix's bit for bit.
+    A smaller matrix keeps the large blocks."""
+    small = lib.Matrix(W.convdiff_2d(400, 0.5), want_f32=True, tune=False)
+    for prec in ("f64", "f32"):
+        assert small.spmv_blocks(prec) == 2048
     csr = W.convdiff_2d(1000, 0.5)
     A = lib.Matrix(csr, want_f32=True, tune=False)
     for prec in ("f64", "f32"):
-        assert A.spmv_blocks(prec) == 2048
+        assert A.spmv_blocks(prec) == 256
         assert A.cache_policy(prec) == "keep"
         assert A.spmv_variant(prec) == "plain"
     B = lib.Matrix(csr, want_f32=True)
