@@ -41,11 +41,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
     # 3-D 160^3, FP64, non-temporal loads, 2048 nonzeros per block, column runs:
-    # the solve's mix of the plain pass (22206 launches: 195996.46 KiB fetched,
-    # 32001.16 KiB written per dispatch) and the tau-epilogue pass (2460
-    # launches: 218394.33 / 32002.47 KiB), weighted by launch count
-    ("c3", "f64", "e9b3f092c93e1260", "stream", 2048, True): {
-        "fetch_kib": 198230.25, "write_kib": 32001.29, "fetch_factor": 2.0, "write_factor": 1.0},
+    # the solve's mix of the plain pass (22206 launches: 195999.83 KiB fetched,
+    # 32003.90 KiB written per dispatch) and the tau-epilogue pass (2460
+    # launches: 218408.20 / 32013.92 KiB), weighted by launch count
+    ("c3", "f64", "d16bdd986af391ce", "stream", 2048, True): {
+        "fetch_kib": 198234.67, "write_kib": 32004.9, "fetch_factor": 2.0, "write_factor": 1.0},
 }
 
 CONFIGS = {

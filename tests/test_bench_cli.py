@@ -41,3 +41,21 @@ def test_default_headline_is_the_3d_operator_in_fp64():
     A = bench.make_matrix(bench.CONFIGS[a.config])
     assert A.n == 160 ** 3 and A.nnz == 28_518_400
     assert A.nnz * 12 + 4 * (A.n + 1) + 16 * A.n > 256 * 2 ** 20
+
+
+def test_headline_traffic_entry_matches_the_kernel_source():
+    """The HBM traffic the headline line reports was counted for the kernel
+    source as it stands: its key carries the hash of the SpMV source up to
+    the windowed variant, the part the headline kernel is built from.  Any
+    edit there makes the entry stale (reported as null) until the counters
+    are taken again."""
+    import hashlib
+    import bench
+    src = open(os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")).read()
+    h = hashlib.sha256(src[:src.index("// Windowed variant:")].encode()).hexdigest()[:16]
+    keys = [k for k in bench.MEASURED_TRAFFIC if k[0] == "c3" and k[1] == "f64"]
+    assert keys and all(k[2] == h for k in keys), (h, keys)
+    for k in keys:
+        e = bench.MEASURED_TRAFFIC[k]
+        mb = 1024 * (e["fetch_kib"] * e["fetch_factor"] + e["write_kib"] * e["write_factor"]) / 1e6
+        assert 428.9 <= mb <= 1.05 * 428.9   # at or a little above the algorithmic bytes
