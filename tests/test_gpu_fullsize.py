@@ -226,3 +226,38 @@ def test_c3_grid_closed_form_eigenvalues(lib, bh):
         assert claimed[key] <= mult
     # the smallest eigenvalue is simple and always among those returned
     assert np.min(np.abs(r.mu - lam[0])) <= 2.0 * kap[0] * r.max_resid + 1e-14 * A.norm_inf
+
+
+def test_c2_grid_laplacian_closed_form_eigenvalues(lib):
+    """The 2-D workload's grid (1000 x 1000) and solve (d = 50, Arnoldi(50,25),
+    nev = 20, FP64) on the Laplacian, the case whose closed form pins every
+    value at this size (with convection the eigenvalue condition numbers grow
+    as rho^N and no closed-form bound stays useful): each returned value lies
+    within r^2 / gap of a closed-form eigenvalue (symmetric matrix, r its
+    residual, gap the distance to the next distinct eigenvalue), no value is
+    claimed more often than its multiplicity (2 for i != j), and the smallest
+    eigenvalue (simple) is found."""
+    N = 1000
+    csr = W.laplacian_2d(N)
+    b, v0 = W.start_vectors(csr.n, 2)
+    A = lib.Matrix(csr)
+    P = lib.Poly.build(A, 50, dev(b))
+    r = lib.eigs(A, P, dev(v0), 50, 25, 20, rtol=1e-8, max_cycles=40)
+    print(f"Laplacian {N}^2: cycles {r.cycles}, converged {r.converged}, max resid {r.max_resid:.2e}", flush=True)
+    assert r.converged and r.nconv == 20
+    M = 40
+    th = np.arange(1, M + 1) * np.pi / (N + 1)
+    f = 2 - 2 * np.cos(th)
+    lam = (f[:, None] + f[None, :]).ravel()
+    distinct = np.unique(np.round(lam, 13))
+    claimed = {}
+    for mu, res in zip(r.mu, r.resid):
+        assert abs(mu.imag) <= 1e-14 * A.norm_inf
+        u = int(np.argmin(np.abs(distinct - mu.real)))
+        gap = np.min(np.abs(np.delete(distinct, u) - distinct[u]))
+        bound = res * res / gap + 1e-14 * A.norm_inf
+        assert abs(mu.real - distinct[u]) <= bound, (mu, distinct[u], bound)
+        mult = int(np.sum(np.abs(lam - distinct[u]) <= 1e-12))
+        claimed[u] = claimed.get(u, 0) + 1
+        assert claimed[u] <= mult, (distinct[u], mult)
+    assert 0 in claimed
