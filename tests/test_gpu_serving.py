@@ -230,6 +230,31 @@ def test_batch_mixed_alone_equals_mix(lib):
             (g.cycles, g.fp32_cycles, g.mvps, g.dots, g.spmv_passes_f32), i
 
 
+@pytest.mark.parametrize("cap", [1, 2, 3])
+def test_batch_mixed_cycle_cap(lib, cap):
+    """A mixed-precision request under a tight cycle cap ends cleanly at the
+    cap: cycles <= cap, FP32 cycles <= cycles, every returned residual
+    recomputable (finite), and the status says whether it converged."""
+    rq = REQS[4]
+    B = lib.Batch(2)
+    s = submit(lib, B, rq, max_cycles=cap, precision="mixed")
+    steps = 0
+    while True:
+        fin, _ = B.step()
+        steps += 1
+        assert steps < 500
+        if s in fin:
+            r = B.result(s)
+            break
+    assert 1 <= r.cycles <= cap and 1 <= r.fp32_cycles <= r.cycles
+    anorm = O.infnorm(rq["csr"])
+    fin = np.isfinite(r.resid)
+    assert fin.any() and np.array_equal(fin, np.isfinite(r.mu))
+    assert r.nconv == int(np.sum(r.resid[fin] <= 1e-8 * anorm))
+    if r.converged:
+        assert fin.all() and r.nconv == rq["nev"]
+
+
 def test_batch_mixed_workspace_and_precision_checks(lib):
     """The mixed workspace adds the FP32 values and four FP32 vectors; an
     unknown precision is refused."""
