@@ -492,9 +492,10 @@ int ppa_batch_submit(ppa_batch* b, const ppa_batch_request* rq, int* slot);
  * section 4's Arnoldi on an FP32 pi(A) until the wanted residuals reach the
  * FP32 floor or stall near it, then the closing FP64 Rayleigh-Ritz pass and,
  * if needed, FP64 cycles).  rq->ws_bytes must cover
- * ppa_batch_workspace_bytes_ex for this precision and A's nonzero count; the
- * FP32 values are copied from val_d at submit.  Results report fp32_cycles
- * and spmv_passes_f32. */
+ * ppa_batch_workspace_bytes_ex for this precision and A's nonzero count
+ * (PPA_ERR_WORKSPACE otherwise, before anything is launched); the FP32
+ * values are copied from val_d at submit.  PPA_ERR_INVALID for another
+ * precision.  Results report fp32_cycles and spmv_passes_f32. */
 int ppa_batch_submit_ex(ppa_batch* b, const ppa_batch_request* rq, int precision, int* slot);
 /* One launch for all admitted solves, then the host work of the phase ends.
  * finished[0 .. min(*nfinished, cap)) receive slots whose solve ended (their
