@@ -59,3 +59,13 @@ def test_headline_traffic_entry_matches_the_kernel_source():
         e = bench.MEASURED_TRAFFIC[k]
         mb = 1024 * (e["fetch_kib"] * e["fetch_factor"] + e["write_kib"] * e["write_factor"]) / 1e6
         assert 428.9 <= mb <= 1.05 * 428.9   # at or a little above the algorithmic bytes
+
+
+def test_reference_probe_flags():
+    """--bw-probe runs only the bandwidth reference kernels; the default run
+    carries them as hbm_reference beside the headline."""
+    import bench
+    assert bench.parse_args(["--bw-probe"]).bw_probe
+    assert not bench.parse_args([]).bw_probe
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'line["hbm_reference"] = bw_probe(torch)' in src
