@@ -145,3 +145,34 @@ def test_ring_eigs_identical_to_plain(lib):
     assert np.array_equal(ra, rb)
     assert np.array_equal(ma, mb) and np.array_equal(sa, sb)
     assert ca == cb and va == vb
+
+
+def test_ring_unaligned_values_take_the_narrow_loads(lib):
+    """FP64 values whose array is 8- but not 16-byte aligned cannot be read
+    two nonzeros per 16-byte load: the sliding-window kernel then loads them
+    one per lane, with the same bits as the plain kernel and as the aligned
+    handle."""
+    import ctypes
+    from paper_1806_08020_amd import ppa
+    csr = MATS["band_200k"]
+    Aa = lib.Matrix(csr, window="ring")
+    Ap = lib.Matrix(csr, window="off")
+    buf = torch.empty(csr.nnz + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = Aa.vals
+    vals = buf[1:]
+    assert vals.data_ptr() % 16 == 8
+    Au = object.__new__(ppa.Matrix)
+    Au.n, Au.rowptr, Au.colind, Au.vals, Au.vals32 = csr.n, Aa.rowptr, Aa.colind, vals, None
+    h = ctypes.c_void_p()
+    ppa._check(ppa._lib.ppa_matrix_create(csr.n, ppa._ptr(Aa.rowptr), ppa._ptr(Aa.colind), ppa._ptr(vals),
+                                          None, ppa.PPA_MATRIX_RING_FORCE, ppa._stream(), ctypes.byref(h)))
+    Au.h = h
+    Au.nnz, Au.norm_inf, Au.nblocks = Aa.nnz, Aa.norm_inf, Aa.nblocks
+    Au._keep = buf
+    assert Au.spmv_variant("f64") == "ring"
+    rng = np.random.default_rng(17)
+    u, x, z = (dev(rng.standard_normal(csr.n)) for _ in range(3))
+    for args in ((0.5, x, -2.0, u), (1.0, u, -0.25, u), (0.5, x, -2.0, u, 1.5, z)):
+        yu = lib.fused_spmv(Au, *args)
+        assert torch.equal(yu, lib.fused_spmv(Aa, *args))
+        assert torch.equal(yu, lib.fused_spmv(Ap, *args))
