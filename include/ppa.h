@@ -52,8 +52,8 @@ typedef enum ppa_precision {
     PPA_F32 = 1,    /* pi(A)v with FP32 matrix values and FP32 vectors              */
     PPA_MIXED = 2   /* eigs: pi(A)v in FP32, orthogonalisation / Ritz / residual in
                        FP64; when the FP32 cycles stall, a closing FP64
-                       Rayleigh-Ritz with A on their basis, then FP64 cycles
-                       from its Ritz vectors unless it already meets rtol     */
+                       Rayleigh-Ritz with A on their basis, then, unless it
+                       already meets rtol, FP64 cycles from v0 again         */
 } ppa_precision;
 
 typedef struct ppa_matrix ppa_matrix;
@@ -491,7 +491,7 @@ int ppa_batch_submit(ppa_batch* b, const ppa_batch_request* rq, int* slot);
 /* As ppa_batch_submit, with precision PPA_F64 or PPA_MIXED (mixed precision,
  * section 4's Arnoldi on an FP32 pi(A) until the wanted residuals reach the
  * FP32 floor or stall near it, then the closing FP64 Rayleigh-Ritz pass and,
- * if needed, FP64 cycles).  rq->ws_bytes must cover
+ * if needed, FP64 cycles from v0_d).  rq->ws_bytes must cover
  * ppa_batch_workspace_bytes_ex for this precision and A's nonzero count
  * (PPA_ERR_WORKSPACE otherwise, before anything is launched); the FP32
  * values are copied from val_d at submit.  PPA_ERR_INVALID for another

@@ -70,7 +70,6 @@ struct BSlot {
     int n, ld, ldh;
     int phase, init, restart, use_poly;
     int f32;             // CYCLE: pi(A) in FP32
-    int ystart;          // CYCLE: start from Y Q (qin columns of Y, one output), normalised
     int j, jend, budget, deg;
     int qin, qout;
     int nw, ycols;
@@ -334,18 +333,12 @@ __global__ __launch_bounds__(BWG) void k_batch(BSlot* __restrict__ slots) {
     }
     if (S.phase == PH_BUILD || S.phase == PH_CYCLE) {
         double* V = S.V;
-        if (S.restart || S.ystart) {
-            // thick restart: V2 = V Q (Q staged in LDS), then continue on V2;
-            // FP64 restart of a mixed solve: the start vector Y Q into t2
+        if (S.restart) {
+            // thick restart: V2 = V Q (Q staged in LDS), then continue on V2
             for (int i = threadIdx.x; i < S.qin * S.qout; i += BWG) Qs[i] = S.Q[i];
             __syncthreads();
-            if (S.restart) {
-                wg_gemm(S, S.V, Qs, S.qin, S.qout, S.V2);
-                V = S.V2;
-            } else {
-                wg_gemm(S, S.Y, Qs, S.qin, 1, S.t2);
-                wg_normalise(S, S.t2, V, red, tmp);
-            }
+            wg_gemm(S, S.V, Qs, S.qin, S.qout, S.V2);
+            V = S.V2;
         }
         if (S.init) wg_normalise(S, S.start, V, red, tmp);
         int j = S.j, used = 0;
@@ -445,8 +438,8 @@ struct BReqState {
     float *f1 = nullptr, *f2 = nullptr, *f3 = nullptr, *f4 = nullptr;
     int ld = 0, ldh = 0;
     // mixed precision: FP32 phase on, the pending test is the closing
-    // Rayleigh-Ritz pass's, the next cycle starts from Y Q
-    bool f32 = false, rr_test = false, ystart = false;
+    // Rayleigh-Ritz pass's
+    bool f32 = false, rr_test = false;
     std::vector<double> hist;   // largest wanted residual per cycle
     int fp32_cycles = 0;
     int64_t passes32 = 0;
@@ -663,21 +656,15 @@ static bool batch_finish_test(BReqState& q, hipStream_t s) {
     const bool conv = nw == nev && mx <= rtol_abs;
     if (q.rr_test) {
         // the closing Rayleigh-Ritz pass: done if all wanted pairs meet rtol,
-        // else FP64 cycles from the sum of these unit Ritz vectors
+        // else FP64 cycles from the start vector again (as in the
+        // single-solve driver)
         q.rr_test = false;
         q.hist.back() = std::min(q.hist.back(), mx);
         if (!conv) {
-            double yn[BMAXW];
-            for (int i = 0; i < nw; ++i) yn[i] = out[3 * BMAXW + i];
-            const std::vector<double> coef = fp64_restart_coef(R, std::vector<double>(yn, yn + nw));
-            PPA_HIP(hipMemcpyAsync(q.Q, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
             launch_zero(q.H, (int64_t)q.ldh * (q.ldh - 1), s);
             PPA_HIP(hipStreamSynchronize(s));
-            q.qin = R.ycols;
-            q.qout = 1;
-            q.ystart = true;
             q.restart = false;
-            q.init = false;
+            q.init = true;
             q.j = 0;
             q.jstart = 0;
             q.jend = m;
@@ -851,7 +838,6 @@ int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive) {
             d.init = q.init;
             d.start = q.rq.v0_d;
             d.restart = q.restart;
-            d.ystart = q.ystart;
             d.f32 = q.f32;
             d.qin = q.qin;
             d.qout = q.qout;
@@ -900,7 +886,6 @@ int batch_step(Batch& B, int* finished, int cap, int* nfin, int* nactive) {
                     std::swap(q.V, q.V2);
                     q.restart = false;
                 }
-                q.ystart = false;
                 q.init = false;
                 q.j = jd;
                 if (q.j >= q.jend) batch_finish_cycle(q, B.s);

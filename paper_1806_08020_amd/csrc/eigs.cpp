@@ -594,11 +594,13 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
                     converged = true;
                     break;
                 }
-                const std::vector<double> coef = fp64_restart_coef(R2, Rr2.ynorm);
-                PPA_HIP(hipMemcpyAsync(e.Qd, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
-                launch_gemm_tall(n, R2.ycols, 1, e.Y, e.ld, e.Qd, e.V2, e.ld, s);
+                // otherwise the FP64 cycles start again from v0: a restart
+                // from these Ritz vectors carries the copies of multiple
+                // eigenvalues that the FP32 rounding brought in, and when the
+                // wanted set ends inside such a cluster the FP64 cycles keep
+                // trading its members in and out instead of converging
                 launch_zero(e.Hd, (int64_t)(m + 1) * m, s);
-                set_unit(n, e.V2, e.V, e.dpart, nb, e.dout, s);
+                set_unit(n, v0, e.V, e.dpart, nb, e.dout, s);
                 j0 = 0;
                 continue;
             }

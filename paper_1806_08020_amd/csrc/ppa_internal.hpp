@@ -436,11 +436,8 @@ RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, doubl
 // largest wanted residual is hist.back() (hist: one maximum per cycle so far),
 // whether the FP32 phase ends: the residuals reached the FP32 floor
 // 100 eps_32 ||A||, or stopped improving (less than 2x over two cycles) within
-// three decades of it.  fp64_restart_coef: coefficients over the ycols
-// columns of Y of the sum of the wanted unit Ritz vectors, the FP64 restart
-// vector when the closing Rayleigh-Ritz pass does not meet the tolerance.
+// three decades of it.
 bool leave_fp32(const std::vector<double>& hist, double anorm);
-std::vector<double> fp64_restart_coef(const RitzPlan& R, const std::vector<double>& ynorm);
 
 // polynomial construction and Arnoldi drivers (eigs.cpp)
 size_t poly_build_ws(int64_t n, int d, bool dbl);

@@ -169,16 +169,6 @@ bool leave_fp32(const std::vector<double>& hist, double anorm) {
     return floor || stall;
 }
 
-std::vector<double> fp64_restart_coef(const RitzPlan& R, const std::vector<double>& ynorm) {
-    std::vector<double> coef(R.ycols, 0.0);
-    for (int i = 0; i < R.nw; ++i) {
-        if (R.dup[i]) continue;
-        coef[R.cre[i]] += 1.0 / ynorm[i];
-        if (R.cim[i] >= 0) coef[R.cim[i]] += 1.0 / ynorm[i];
-    }
-    return coef;
-}
-
 RestartPlan plan_restart(const RitzPlan& R, const std::vector<double>& Hm, double hm, int m, int k) {
     const int mc = R.mc;
     RestartPlan P;

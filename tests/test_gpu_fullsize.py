@@ -228,6 +228,31 @@ def test_c3_grid_closed_form_eigenvalues(lib, bh):
     assert np.min(np.abs(r.mu - lam[0])) <= 2.0 * kap[0] * r.max_resid + 1e-14 * A.norm_inf
 
 
+def test_c3_grid_closed_form_eigenvalues_mixed(lib):
+    """The same pin for the mixed-precision solve (FP32 pi(A)v, the closing
+    FP64 Rayleigh-Ritz pass, FP64 cycles as needed) at beta*h = 0.02 on the
+    headline's grid: every returned eigenvalue within 2 kappa r of a
+    closed-form one, multiplicities respected, at least one FP32 cycle."""
+    bh = 0.02
+    csr = W.convdiff_3d(160, bh)
+    b, v0 = W.start_vectors(csr.n, 3)
+    A = lib.Matrix(csr, want_f32=True)
+    P = lib.Poly.build_double(A, 10, 20, dev(b))
+    r = lib.eigs(A, P, dev(v0), 40, 20, 15, rtol=1e-8, max_cycles=12, precision="mixed")
+    print(f"160^3 beta*h={bh} mixed: cycles {r.cycles}, fp32 cycles {r.fp32_cycles}", flush=True)
+    assert r.converged and r.nconv == 15 and r.fp32_cycles >= 1
+    lam, kap = _closed_3d(160, bh)
+    claimed = {}
+    for mu, res in zip(r.mu, r.resid):
+        assert res <= 1e-8 * A.norm_inf
+        t = int(np.argmin(np.abs(lam - mu.real)))
+        assert abs(mu - lam[t]) <= 2.0 * kap[t] * res + 1e-14 * A.norm_inf, (mu, lam[t])
+        mult = int(np.sum(np.abs(lam - lam[t]) <= 1e-13))
+        key = round(float(lam[t]), 12)
+        claimed[key] = claimed.get(key, 0) + 1
+        assert claimed[key] <= mult
+
+
 def test_c2_grid_laplacian_closed_form_eigenvalues(lib):
     """The 2-D workload's grid (1000 x 1000) and solve (d = 50, Arnoldi(50,25),
     nev = 20, FP64) on the Laplacian, the case whose closed form pins every

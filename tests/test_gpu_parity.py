@@ -468,6 +468,27 @@ def test_eigs_mixed_precision_per_pair(lib):
     assert np.all(rel(r.mu.real, rd.mu.real) <= 1e-10)
 
 
+@pytest.mark.parametrize("side,bh,d", [(300, 0.2, 20), (120, 0.5, 12)])
+def test_eigs_mixed_falls_back_to_the_fp64_solve(lib, side, bh, d):
+    """When the closing Rayleigh-Ritz pass misses rtol, the FP64 cycles start
+    from v0 again: the mixed solve then runs its FP32 cycles plus exactly the
+    FP64 solve's cycles, and returns that solve's pairs bit for bit."""
+    csr = W.convdiff_2d(side, bh)
+    b, v0 = W.start_vectors(csr.n, 12)
+    A = lib.Matrix(csr, want_f32=True)
+    P = lib.Poly.build(A, d, dev(b))
+    rd = lib.eigs(A, P, dev(v0), 30, 15, 10, rtol=1e-8, max_cycles=60)
+    r = lib.eigs(A, P, dev(v0), 30, 15, 10, rtol=1e-8, max_cycles=60, precision="mixed")
+    print(f"{side}^2 beta*h={bh}: FP64 {rd.cycles} cycles, mixed {r.fp32_cycles} + "
+          f"{r.cycles - r.fp32_cycles}", flush=True)
+    assert rd.converged and r.converged and r.fp32_cycles >= 1
+    if r.cycles == r.fp32_cycles:
+        return          # the closing pass met rtol: nothing to compare
+    assert r.cycles == r.fp32_cycles + rd.cycles
+    assert np.array_equal(r.mu, rd.mu) and np.array_equal(r.resid, rd.resid)
+    assert r.spmv_passes_f32 > 0 and r.spmv_passes > rd.spmv_passes
+
+
 # ---------------------------------------------------------------- windowed SpMV
 @pytest.mark.parametrize("name", ["band_9000", "lap_50", "cd3_13", "diag_5000"])
 def test_windowed_spmv_bitwise_equal(lib, name):

@@ -193,6 +193,12 @@ def test_batch_mixed_precision_eigenvalues(lib):
         assert r.converged and r.nconv == rq["nev"], i
         assert r.fp32_cycles >= 1 and 0 < r.spmv_passes_f32 < r.spmv_passes, i
         check_eigenvalues(i, r, anorm)
+        # a closing Rayleigh-Ritz pass that misses rtol hands over to FP64
+        # cycles from v0: the FP64 request's cycles and bits follow
+        rf = run_alone(lib, rq)
+        if r.cycles > r.fp32_cycles:
+            assert r.cycles == r.fp32_cycles + rf.cycles, i
+            assert np.array_equal(r.mu, rf.mu) and np.array_equal(r.resid, rf.resid), i
         ores, _ = O.pp_eigs(rq["csr"], rq["b"], rq["v0"], m=rq["m"], k=rq["k"], nev=rq["nev"],
                             d=rq["d"], rtol=1e-8, max_cycles=40)
         lam, kap, sym = closed_for(i)
@@ -253,6 +259,30 @@ def test_batch_mixed_cycle_cap(lib, cap):
     assert r.nconv == int(np.sum(r.resid[fin] <= 1e-8 * anorm))
     if r.converged:
         assert fin.all() and r.nconv == rq["nev"]
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_batch_largest_small_request(lib, precision):
+    """A request at the engine's size limit (n = 16384, the 128 x 128
+    Laplacian): converged, every eigenvalue within r^2 / gap of the closed
+    form, multiplicities (2 for i != j) respected."""
+    N = 128
+    rq = make_req(W.laplacian_2d(N), 9, 20, 40, 15, 10)
+    r = run_alone(lib, rq, precision)
+    assert r.converged and r.nconv == 10
+    if precision == "mixed":
+        assert r.fp32_cycles >= 1
+    lam = lap_closed(N, N)
+    distinct = np.unique(np.round(lam, 13))
+    claimed = {}
+    anorm = O.infnorm(rq["csr"])
+    for mu, res in zip(r.mu, r.resid):
+        assert res <= 1e-8 * anorm and abs(mu.imag) <= 1e-14 * anorm
+        u = int(np.argmin(np.abs(distinct - mu.real)))
+        gap = np.min(np.abs(np.delete(distinct, u) - distinct[u]))
+        assert abs(mu.real - distinct[u]) <= res * res / gap + 1e-14 * anorm
+        claimed[u] = claimed.get(u, 0) + 1
+        assert claimed[u] <= int(np.sum(np.abs(lam - distinct[u]) <= 1e-12))
 
 
 def test_batch_mixed_workspace_and_precision_checks(lib):
