@@ -379,6 +379,37 @@ def safeguards_report():
     return out
 
 
+def looser_rtol_report(A, P, vt, cfg, max_cycles, rtol=1e-6):
+    """The headline solve (same matrix, polynomial and start vector) in FP64
+    and in mixed precision at a looser tolerance, where the closing FP64
+    Rayleigh-Ritz pass of the mixed solve can meet it: solve time (best of
+    two, polynomial built once), cycles and the largest residual."""
+    import torch
+    from paper_1806_08020_amd import ppa
+
+    if not A.has_f32:
+        return {"skipped": "matrix has no FP32 values"}
+    out = {"rtol": rtol}
+    for prec in ("f64", "mixed"):
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ppa.eigs(A, P, vt, cfg["m"], cfg["k"], cfg["nev"], rtol=rtol, max_cycles=max_cycles,
+                         precision=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, r)
+        dt, r = best
+        out[prec] = {"ms_per_solve": round(dt * 1e3, 2), "converged": bool(r.converged),
+                     "cycles": int(r.cycles), "fp32_cycles": int(r.fp32_cycles),
+                     "eigenpairs_per_s": round(r.nconv / dt, 3),
+                     "max_resid_rel": float(f"{r.max_resid / A.norm_inf:.3e}")}
+    out["mixed_speedup"] = round(out["f64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"], 3)
+    return out
+
+
 def lowsync_report(A, P, bt, vt, cfg, prec, max_cycles):
     """The headline solve (same matrix, polynomial and start vector) with the
     default Gram-Schmidt (three passes over V per step) and with the delayed
@@ -806,6 +837,7 @@ def main():
         if args.config != "c2":
             line["c2_cache_resident"] = cache_resident_report("c2", 3, args.max_cycles)
         line["lowsync"] = lowsync_report(A, P, bt, vt, cfg, prec, args.max_cycles)
+        line["precision_compare_rtol_1e-6"] = looser_rtol_report(A, P, vt, cfg, args.max_cycles)
         line["stability"] = stability_report(P, dbl)
         line["safeguards"] = safeguards_report()
         line["harmonic"] = harmonic_report()
