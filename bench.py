@@ -825,10 +825,12 @@ def main():
                 np.min(np.abs(r0.mu - z)) <= 1e-6 * abs(z) for z in ra.mu)),
             "per_pair_rel_diff_" + alt + "_vs_" + prec: [
                 float(f"{np.min(np.abs(r0.mu - z)) / abs(z):.3e}") for z in ra.mu],
-            "note": "every returned pair of both runs meets rtol on A in FP64; the operator's "
-                    "eigenvalue condition number is about 1e7 per axis, so a residual of 1e-8 ||A|| "
-                    "fixes an eigenvalue only loosely and the two runs may certify different "
-                    "pseudo-eigenvalues; mixed_accuracy gives the per-pair error on a pinned workload",
+            "note": "every returned pair of both runs meets rtol on A in FP64; when the mixed "
+                    "solve's closing Rayleigh-Ritz pass misses rtol its FP64 cycles start from v0 "
+                    "again and its pairs equal the FP64 run's bit for bit; a pair that the closing "
+                    "pass certifies can differ, since the operator's eigenvalue condition number is "
+                    "about 1e7 per axis and a residual of 1e-8 ||A|| fixes an eigenvalue only "
+                    "loosely; mixed_accuracy gives the per-pair error on a pinned workload",
         }
     acc = None
     if not args.headline_only:
