@@ -69,3 +69,23 @@ def test_reference_probe_flags():
     assert not bench.parse_args([]).bw_probe
     src = open(os.path.join(ROOT, "bench.py")).read()
     assert 'line["hbm_reference"] = bw_probe(torch)' in src
+
+
+def test_cpu_baseline_fields_on_the_small_configuration():
+    """The CPU baseline leg (the oracle, bounded) returns the reported rate
+    with its unit, cores and kind, the per-step timings and the per-solve
+    estimate, and the host description, on the 2-D Laplacian 50 x 50."""
+    import bench
+    import oracle as O
+    cfg = bench.CONFIGS["c1"]
+    csr = bench.make_matrix(cfg)
+    from paper_1806_08020_amd import workloads as W
+    b, _ = W.start_vectors(csr.n, cfg["seed"])
+    roots, _ = O.gmres_poly(O.csr_matvec(csr), b, cfg["d"])
+    bpa = cfg["d"] * (csr.nnz * 12 + 4 * (csr.n + 1) + 16 * csr.n)
+    cb = bench.cpu_baseline(csr, roots, bpa, 0.2, cfg, 2, b)
+    assert cb["unit"] == "GB/s" and cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0
+    for k in ("s_per_pi_apply", "s_polynomial_build", "s_per_cycle_estimate", "s_per_solve_estimate",
+              "eigenpairs_per_s_estimate", "host", "sample"):
+        assert k in cb, k
+    assert cb["s_per_solve_estimate"] >= cb["s_polynomial_build"]
