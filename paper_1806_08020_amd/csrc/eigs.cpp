@@ -561,17 +561,16 @@ int eigs(const Matrix& A, const Poly* p, const ppa_eigs_opts& o, const double* v
             // leave the FP32 phase when the wanted residuals reach the FP32
             // floor, or stop improving within three decades of it (slow
             // progress far above the floor is the method's, not the
-            // precision's, and FP64 cycles would not speed it up); restart in
-            // FP64 from the sum of the wanted unit Ritz vectors
+            // precision's, and FP64 cycles would not speed it up)
             if (leave_fp32(hist, anorm)) {
                 fp32 = false;
                 // closing FP64 Rayleigh-Ritz with A itself on the FP32-built
                 // basis V_{m+1} (FP64 storage, orthonormal to FP64 rounding):
                 // K = V^T A V, its Ritz pairs nearest the target, tested on A
                 // as every cycle's pairs are.  When they all meet rtol the
-                // solve ends here; otherwise the FP64 cycles restart from the
-                // sum of these unit Ritz vectors.  Costs m + 1 products with A
-                // and (m + 1)^2 inner products, against m factors of pi per cycle.
+                // solve ends here; otherwise the FP64 cycles start from v0.
+                // Costs m + 1 products with A and (m + 1)^2 inner products,
+                // against m factors of pi per cycle.
                 const int J = mc + 1;
                 launch_spmm_cols(A, e.V, e.ld, J, e.V2, s);
                 launch_gram(n, J, e.V, e.ld, e.V2, J, e.Qd, e.cw, s);
