@@ -35,18 +35,45 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this benchmark, scaled by
 # the factors the same counters give for a plain 2 GiB device copy (FETCH_SIZE
 # reads half of the bytes: x2.0; WRITE_SIZE exact: x1.0).  Keyed by config, pass
-# precision, the hash of the plain kernel's source (spmv.hip up to the
-# windowed variant) the counters were taken on, the cache policy, the block
-# shape (nonzeros per block) and the use of column runs: any change of that
-# kernel makes the entry stale and the field null.
+# precision, kernel variant, the hash of the variant's source the counters
+# were taken on (kernel_source_hash) and, for the plain kernel, its cache
+# policy, block shape (nonzeros per block) and use of column runs: any change
+# of that kernel makes the entry stale and the field null.
 MEASURED_TRAFFIC = {
     # 3-D 160^3, FP64, non-temporal loads, 2048 nonzeros per block, column runs:
     # the solve's mix of the plain pass (22206 launches: 195999.83 KiB fetched,
     # 32003.90 KiB written per dispatch) and the tau-epilogue pass (2460
     # launches: 218408.20 / 32013.92 KiB), weighted by launch count
-    ("c3", "f64", "d16bdd986af391ce", "stream", 2048, True): {
+    ("c3", "f64", "plain", "d16bdd986af391ce", "stream", 2048, True): {
         "fetch_kib": 198234.67, "write_kib": 32004.9, "fetch_factor": 2.0, "write_factor": 1.0},
+    # random band n = 2e6, FP64, sliding window: 400 dispatches of the
+    # degree-100 polynomial's passes (two applications)
+    ("c4", "f64", "ring", "8730b550a0be96aa", None, None, None): {
+        "fetch_kib": 353195.02, "write_kib": 15635.51, "fetch_factor": 2.0, "write_factor": 1.0},
 }
+
+
+def kernel_source_hash(variant):
+    """Hash of the SpMV source a kernel variant is built from: the plain
+    kernel and the helpers every variant shares (spmv.hip up to the windowed
+    variant), plus the variant's own kernel for the windowed and
+    sliding-window forms.  A traffic entry keyed on it goes stale (reported
+    as null) with any edit to that source."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")).read()
+    part = src[:src.index("// Windowed variant:")]
+    if variant == "window":
+        part += src[src.index("// Windowed variant:"):src.index("// Sliding-window variant")]
+    elif variant == "ring":
+        part += src[src.index("// Sliding-window variant"):src.index("// A Y for K columns")]
+    return hashlib.sha256(part.encode()).hexdigest()[:16]
+
+
+def traffic_key(config, prec, variant, policy, blocks, runs_on):
+    """MEASURED_TRAFFIC key; the plain kernel's settings only count for it."""
+    if variant == "plain":
+        return (config, prec, variant, kernel_source_hash(variant), policy, blocks, runs_on)
+    return (config, prec, variant, kernel_source_hash(variant), None, None, None)
 
 CONFIGS = {
     # name: (builder, seed, d or (d1, d2), m, k, nev, precision, description)
@@ -243,7 +270,7 @@ def bw_probe(torch, reps=20):
         raise RuntimeError("libppa_bwprobe.so is not built (python -m paper_1806_08020_amd.build)")
     lib = ctypes.CDLL(path)
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
-    lib.ppa_probe_read.argtypes = [vp, i64, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_read_wg.argtypes = [vp, i64, ci, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
     lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, ci, vp]
     lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, ci, vp]
     grids = (256, 512, 1024, 4096, 16384)
@@ -252,17 +279,32 @@ def bw_probe(torch, reps=20):
     g.manual_seed(5)
     x = torch.randint(-2 ** 31, 2 ** 31 - 1, (big // 4,), dtype=torch.int32, device="cuda", generator=g)
     y = torch.empty_like(x)
-    sink = torch.empty(max(grids) * 256, dtype=torch.int32, device="cuda")
+    sink = torch.empty(max(grids) * 256, dtype=torch.int32, device="cuda")   # >= 256 x 1024 too
     stream = torch.cuda.current_stream().cuda_stream
     xp, yp, sp = x.data_ptr(), y.data_ptr(), sink.data_ptr()
     never = 0x9E3779B9
+    def read(width, nt):
+        return lambda nb, c, gr, wg=256: lib.ppa_probe_read_wg(xp, nb, width, nt, c, wg, never, sp, gr, stream)
     kinds = {
-        "read16_nontemporal": (lambda nb, c, gr: lib.ppa_probe_read(xp, nb, 16, 1, c, never, sp, gr, stream), 1.0),
-        "read16": (lambda nb, c, gr: lib.ppa_probe_read(xp, nb, 16, 0, c, never, sp, gr, stream), 1.0),
-        "read4": (lambda nb, c, gr: lib.ppa_probe_read(xp, nb, 4, 0, c, never, sp, gr, stream), 1.0),
+        "read16_nontemporal": (read(16, 1), 1.0),
+        "read16": (read(16, 0), 1.0),
+        "read4": (read(4, 0), 1.0),
         "copy": (lambda nb, c, gr: lib.ppa_probe_copy(xp, yp, nb, c, gr, stream), 2.0),
         "read_plus_write_eighth": (lambda nb, c, gr: lib.ppa_probe_read_write8(xp, yp, nb, c, gr, stream), 1.125),
     }
+
+    def rate(launch, name, nbytes, mult, *a):
+        for _ in range(2):
+            if launch(nbytes, *a) != 0:
+                raise RuntimeError(f"probe {name} refused {nbytes} bytes")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            launch(nbytes, *a)
+        e1.record()
+        torch.cuda.synchronize()
+        return mult * nbytes * reps / e0.elapsed_time(e1) / 1e6
+
     out = {}
     for label, nbytes in (("1GiB", big), ("80MB", 80_000_000)):
         row = {}
@@ -270,16 +312,7 @@ def bw_probe(torch, reps=20):
             best, where, one_per_cu = 0.0, None, None
             for contiguous in (0, 1):
                 for gr in grids:
-                    for _ in range(2):
-                        if launch(nbytes, contiguous, gr) != 0:
-                            raise RuntimeError(f"probe {name} refused {nbytes} bytes")
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    for _ in range(reps):
-                        launch(nbytes, contiguous, gr)
-                    e1.record()
-                    torch.cuda.synchronize()
-                    gbs = mult * nbytes * reps / e0.elapsed_time(e1) / 1e6
+                    gbs = rate(launch, name, nbytes, mult, contiguous, gr)
                     if gbs > best:
                         best, where = gbs, ("contiguous" if contiguous else "grid-stride", gr)
                     if contiguous and gr == 256:
@@ -287,11 +320,16 @@ def bw_probe(torch, reps=20):
             row[name] = {"GBps": round(best, 1), "frac_of_peak": round(best / HBM_PEAK_GBS, 4),
                          "layout": where[0], "workgroups": where[1],
                          "one_range_per_cu_GBps": round(one_per_cu, 1)}
+            if name.startswith("read") and "write" not in name:
+                row[name]["one_range_per_cu_1024_threads_GBps"] = round(
+                    rate(launch, name, nbytes, mult, 1, 256, 1024), 1)
         out[label] = row
     out["note"] = ("256-thread workgroups, eight loads in flight per thread, best of grid-stride and "
                    "contiguous-range layouts at 256-16384 workgroups; one_range_per_cu_GBps: the "
-                   "contiguous layout with 256 workgroups, one stream per CU as in the sliding-window "
-                   "SpMV; read_plus_write_eighth moves bytes * 1.125 per launch")
+                   "contiguous layout with 256 workgroups, one stream per CU; "
+                   "one_range_per_cu_1024_threads_GBps: the same with 1024-thread workgroups, the "
+                   "shape of the sliding-window SpMV; read_plus_write_eighth moves bytes * 1.125 per "
+                   "launch")
     del x, y, sink
     torch.cuda.empty_cache()
     return out
@@ -746,14 +784,12 @@ def main():
     kern_gbs = (pi_bytes / t_apply / 1e9) if t_apply > 0 else None
     avg_pass_us = t_apply / passes * 1e6 if passes else None
     nconv = sum(r.nconv for r in results)
-    import hashlib
-    # the plain kernel and its helpers: spmv.hip up to the windowed variant
-    ksrc = open(os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")).read()
-    khash = hashlib.sha256(ksrc[:ksrc.index("// Windowed variant:")].encode()).hexdigest()[:16]
     policy = A.cache_policy("f32" if prec == "mixed" else "f64")
     blocks = A.spmv_blocks("f32" if prec == "mixed" else "f64")
     runs_on, runs_blocks = A.spmv_runs("f32" if prec == "mixed" else "f64")
-    tr = MEASURED_TRAFFIC.get((args.config, "f64" if prec == "f64" else "f32", khash, policy, blocks, runs_on))
+    variant = A.spmv_variant("f32" if prec == "mixed" else "f64")
+    tr = MEASURED_TRAFFIC.get(traffic_key(args.config, "f64" if prec == "f64" else "f32", variant,
+                                          policy, blocks, runs_on))
     traffic = (round(1024 * (tr["fetch_kib"] * tr["fetch_factor"] + tr["write_kib"] * tr["write_factor"]))
                if tr else None)
     line = {

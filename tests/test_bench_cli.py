@@ -7,6 +7,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -43,22 +44,31 @@ def test_default_headline_is_the_3d_operator_in_fp64():
     assert A.nnz * 12 + 4 * (A.n + 1) + 16 * A.n > 256 * 2 ** 20
 
 
-def test_headline_traffic_entry_matches_the_kernel_source():
-    """The HBM traffic the headline line reports was counted for the kernel
-    source as it stands: its key carries the hash of the SpMV source up to
-    the windowed variant, the part the headline kernel is built from.  Any
-    edit there makes the entry stale (reported as null) until the counters
-    are taken again."""
+@pytest.mark.parametrize("config,variant,alg_mb,slack", [("c3", "plain", 428.9, 1.05),
+                                                          ("c4", "ring", 695.7, 1.10)])
+def test_traffic_entries_match_the_kernel_source(config, variant, alg_mb, slack):
+    """The HBM traffic a line reports was counted for the kernel source as
+    it stands: its key carries the hash of the source the variant is built
+    from (the shared part of spmv.hip up to the windowed variant, plus the
+    sliding-window kernel for that variant), so any edit there makes the
+    entry stale (reported as null) until the counters are taken again.  The
+    counted bytes sit at or a little above the algorithmic bytes per launch
+    (for the sliding window, each segment's first column range on top)."""
     import hashlib
     import bench
     src = open(os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")).read()
-    h = hashlib.sha256(src[:src.index("// Windowed variant:")].encode()).hexdigest()[:16]
-    keys = [k for k in bench.MEASURED_TRAFFIC if k[0] == "c3" and k[1] == "f64"]
-    assert keys and all(k[2] == h for k in keys), (h, keys)
+    part = src[:src.index("// Windowed variant:")]
+    if variant == "ring":
+        part += src[src.index("// Sliding-window variant"):src.index("// A Y for K columns")]
+    h = hashlib.sha256(part.encode()).hexdigest()[:16]
+    assert bench.kernel_source_hash(variant) == h
+    keys = [k for k in bench.MEASURED_TRAFFIC if k[0] == config and k[1] == "f64" and k[2] == variant]
+    assert keys and all(k[3] == h for k in keys), (h, keys)
     for k in keys:
+        assert bench.traffic_key(config, "f64", variant, *k[4:]) == k
         e = bench.MEASURED_TRAFFIC[k]
         mb = 1024 * (e["fetch_kib"] * e["fetch_factor"] + e["write_kib"] * e["write_factor"]) / 1e6
-        assert 428.9 <= mb <= 1.05 * 428.9   # at or a little above the algorithmic bytes
+        assert alg_mb <= mb <= slack * alg_mb
 
 
 def test_reference_probe_flags():

@@ -1,7 +1,8 @@
 """The benchmark's bandwidth reference kernels (libppa_bwprobe.so) move the
 bytes they claim: the copy reproduces its input, the read-plus-eighth-write
-kernel writes every eighth 16-byte unit of its input, and sizes that are not
-whole units are refused."""
+kernel writes every eighth 16-byte unit of its input, the read visits every
+unit exactly once with either workgroup size, and sizes that are not whole
+units are refused."""
 import ctypes
 import os
 
@@ -21,6 +22,7 @@ def probe():
     lib = ctypes.CDLL(PROBE)
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.ppa_probe_read.argtypes = [vp, i64, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_read_wg.argtypes = [vp, i64, ci, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
     lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, ci, vp]
     lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, ci, vp]
     return lib
@@ -71,3 +73,38 @@ def test_read_runs_and_refusals(probe):
     assert probe.ppa_probe_read(xp, 64, 4, 1, 0, 0, sp, 0, s) == -1        # non-temporal only at 16 bytes
     assert probe.ppa_probe_copy(xp, xp, 24, 0, 0, s) == -1
     assert probe.ppa_probe_read_write8(xp, xp, 64, 0, 0, s) == -1          # not whole 128-byte pieces
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("contiguous", [0, 1])
+@pytest.mark.parametrize("width,nt", [(16, 1), (16, 0), (4, 0)])
+def test_read_visits_every_unit_once(probe, width, nt, contiguous, threads):
+    """Data zero but for one unit, never = 0: every thread whose XOR is zero
+    writes its sink entry, so exactly one entry (the thread that read the
+    marked unit, once) keeps its initial value.  Marked units at the start,
+    inside and at the end, over ragged sizes and grids."""
+    s = torch.cuda.current_stream().cuda_stream
+    words_per_unit = width // 4
+    for units, blocks in ((1, 0), (1000 + 3, 5), (1 << 16, 0), ((1 << 16) + 17, 256)):
+        x = torch.zeros(units * words_per_unit, dtype=torch.int32, device="cuda")
+        for mark in sorted({0, units // 2, units - 1}):
+            x.zero_()
+            x[mark * words_per_unit] = 0x5A5A5A5
+            grid = blocks if blocks > 0 else 4096
+            sink = torch.full((grid * threads,), -1, dtype=torch.int32, device="cuda")
+            rc = probe.ppa_probe_read_wg(x.data_ptr(), units * width, width, nt, contiguous, threads, 0,
+                                         sink.data_ptr(), blocks, s)
+            assert rc == 0
+            torch.cuda.synchronize()
+            launched = min(grid, -(-units // threads))
+            used = sink[:launched * threads]
+            assert int((used == -1).sum()) == 1, (units, blocks, mark)
+            assert torch.all(sink[launched * threads:] == -1)
+
+
+def test_read_workgroup_size_refusals(probe):
+    s = torch.cuda.current_stream().cuda_stream
+    x = rand_words(1 << 10, 4)
+    sink = torch.zeros(4096 * 1024, dtype=torch.int32, device="cuda")
+    for threads in (0, 64, 512, 2048):
+        assert probe.ppa_probe_read_wg(x.data_ptr(), 4 << 10, 16, 0, 1, threads, 0, sink.data_ptr(), 0, s) == -1
