@@ -53,6 +53,10 @@ MEASURED_TRAFFIC = {
 }
 
 
+# the fused SpMV kernel each variant launches
+KERNEL_OF_VARIANT = {"plain": "k_fused_spmv", "window": "k_fused_spmv_win", "ring": "k_fused_spmv_ring"}
+
+
 def kernel_source_hash(variant):
     """Hash of the SpMV source a kernel variant is built from: the plain
     kernel and the helpers every variant shares (spmv.hip up to the windowed
@@ -821,10 +825,9 @@ def main():
                   "mvps": results[-1].mvps, "dots": results[-1].dots,
                   "mu_head": [[round(z.real, 10), round(z.imag, 10)] for z in results[-1].mu[:4]],
                   "fp32_cycles": results[-1].fp32_cycles},
-        "roofline": {"kernel": "k_fused_spmv", "bound": "hbm",
-                     "spmv_variant": A.spmv_variant("f32" if prec == "mixed" else "f64"),
-                     "cache_policy": policy, "nnz_per_block": blocks,
-                     "column_runs": runs_on, "blocks_with_runs": runs_blocks, "blocks": A.nblocks,
+        "roofline": {"kernel": KERNEL_OF_VARIANT[variant], "bound": "hbm", "spmv_variant": variant,
+                     **({"cache_policy": policy, "nnz_per_block": blocks, "column_runs": runs_on,
+                         "blocks_with_runs": runs_blocks, "blocks": A.nblocks} if variant == "plain" else {}),
                      "achieved": round(kern_gbs, 1) if kern_gbs else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4) if kern_gbs else None,
                      "traffic": traffic, "bytes_per_launch": round(pi_bytes / max(passes, 1)),

@@ -99,3 +99,16 @@ def test_cpu_baseline_fields_on_the_small_configuration():
               "eigenpairs_per_s_estimate", "host", "sample"):
         assert k in cb, k
     assert cb["s_per_solve_estimate"] >= cb["s_polynomial_build"]
+
+
+def test_every_spmv_variant_names_its_kernel():
+    """The roofline block names the kernel of whichever SpMV variant the
+    matrix runs, and each variant's traffic key hashes a different source."""
+    import bench
+    from paper_1806_08020_amd import ppa
+    assert set(bench.KERNEL_OF_VARIANT) == set(ppa.Matrix.SPMV_VARIANTS)
+    src = open(os.path.join(ROOT, "paper_1806_08020_amd", "csrc", "spmv.hip")).read()
+    for v, k in bench.KERNEL_OF_VARIANT.items():
+        assert f"void {k}(" in src, k
+    hashes = {bench.kernel_source_hash(v) for v in bench.KERNEL_OF_VARIANT}
+    assert len(hashes) == len(bench.KERNEL_OF_VARIANT)
