@@ -5,6 +5,10 @@ which times the windowed variant against the plain one for large matrices).
 * pi(A)v: whole output vectors against the FP64 oracle element by element
   (a CSR mat-vec at these sizes costs the oracle tens of milliseconds), with
   the same first-order rounding bound as the small-size tests;
+* single fused passes in the launch configurations the solves run (column
+  runs for the 3-D operator, the sliding window for the band matrix):
+  bitwise equal to the plain kernel and within the bound of the host's
+  CSR product;
 * polynomial roots: the GPU's harmonic Ritz values against the oracle's own
   GMRES(d) run on the same seed vector;
 * eigensolves: properties that hold at any size -- every returned pair's
@@ -110,6 +114,60 @@ def test_band_full_apply_fp32_and_fp64(lib, band):
     assert np.max(np.abs(y - ref)) <= tol
     y32 = host(lib.apply(A, P, dev(v0, torch.float32), precision="f32")).astype(float)
     assert np.max(np.abs(y32 - ref)) <= tol * (EPS32 / EPS64) * 2
+
+
+def _check_pass(csr, run, run_ref, seed):
+    """One fused pass, out = alpha x + beta A u, through `run` and through
+    `run_ref` (each called as f(alpha, x, beta, u) on device vectors): the
+    two are bitwise equal (same products, same summation order) and within
+    the first-order bound of the host's FP64 CSR product.  Cases: a real
+    root's pass (x is the gathered vector itself) and a conjugate pair's
+    second pass (x and u distinct)."""
+    rng = np.random.default_rng(seed)
+    u, x = rng.standard_normal(csr.n), rng.standard_normal(csr.n)
+    S = csr.to_scipy()
+    Su, aSu = S @ u, abs(S) @ np.abs(u)
+    nnzr = int(np.diff(csr.rowptr).max())
+    ut = dev(u)
+    for alpha, xv, beta in ((1.0, None, -0.3), (0.7, x, -1.3)):
+        xt = ut if xv is None else dev(xv)
+        y = run(alpha, xt, beta, ut)
+        y0 = run_ref(alpha, xt, beta, ut)
+        assert torch.equal(y, y0)
+        xh = u if xv is None else xv
+        ref = alpha * xh + beta * Su
+        scale = abs(alpha) * np.abs(xh) + abs(beta) * aSu
+        assert np.all(np.abs(host(y) - ref) <= (nnzr + 4) * EPS64 * scale)
+
+
+def test_c3_headline_pass_in_the_benchmark_configuration(lib, cd3):
+    """The headline pass as the benchmark times it: n = 4.1e6, FP64, column
+    runs staged in LDS, non-temporal matrix loads, 2048 nonzeros per block;
+    against the same kernel gathering from memory and the host's product."""
+    A = lib.Matrix(cd3, window="runs")
+    A.set_cache_policy("stream")
+    A.set_spmv_blocks(2048)
+    on, nb = A.spmv_runs("f64")
+    assert on and nb >= 0.99 * A.nblocks
+    assert A.cache_policy("f64") == "stream" and A.spmv_blocks("f64") == 2048
+
+    def with_runs(flag):
+        def run(alpha, x, beta, u):
+            A.set_spmv_runs(flag)
+            return lib.fused_spmv(A, alpha, x, beta, u)
+        return run
+    _check_pass(cd3, with_runs(True), with_runs(False), 31)
+
+
+def test_band_full_sliding_window_pass(lib, band):
+    """The banded matrix's FP64 pass as its solve runs it (n = 2e6, the
+    sliding-window kernel, one 1024-thread block per CU), against the plain
+    kernel and the host's product."""
+    Ar = lib.Matrix(band, window="ring")
+    Ap = lib.Matrix(band, window="off")
+    assert Ar.spmv_variant("f64") == "ring" and Ap.spmv_variant("f64") == "plain"
+    _check_pass(band, lambda a, x, b, u: lib.fused_spmv(Ar, a, x, b, u),
+                lambda a, x, b, u: lib.fused_spmv(Ap, a, x, b, u), 32)
 
 
 def test_cd2_full_eigs_fp64_properties(lib, cd2):
