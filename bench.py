@@ -277,6 +277,8 @@ def bw_probe(torch, reps=20):
     lib.ppa_probe_read_wg.argtypes = [vp, i64, ci, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
     lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, ci, vp]
     lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, ci, vp]
+    lib.ppa_probe_read_streams.argtypes = [vp, i64, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_spmv_mix.argtypes = [vp, vp, vp, vp, i64, i64, ci, ci, ctypes.c_uint32, vp, vp]
     grids = (256, 512, 1024, 4096, 16384)
     big = 1 << 30
     g = torch.Generator(device="cuda")
@@ -328,12 +330,35 @@ def bw_probe(torch, reps=20):
                 row[name]["one_range_per_cu_1024_threads_GBps"] = round(
                     rate(launch, name, nbytes, mult, 1, 256, 1024), 1)
         out[label] = row
+    # one range per CU (256 workgroups of 1024 threads) split into 1, 2 or 4 streams
+    out["1GiB"]["read16_nontemporal_streams_per_range"] = {
+        str(ns): round(rate(lambda nb, ns_: lib.ppa_probe_read_streams(xp, nb, ns_, 1024, never, sp, 256, stream),
+                            "streams", big, 1.0, ns), 1) for ns in (1, 2, 4)}
+    # the sliding-window SpMV's streams in the banded matrix's shape: 256
+    # workgroups of 51 chunks, 4096 nonzeros and 152 rows per chunk
+    nch, per_wg, rows = 256 * 51, 51, 152
+    nnz = nch * 4096
+    idx_p, val_p = xp, xp + (256 << 20)               # 214 MB and 428 MB of x
+    vec_p, out_p = yp, yp + (64 << 20)                # 16 MB each in y
+    loads = nnz * 12 + nch * rows * 8
+    mix = {}
+    for store, key in ((0, "loads_only"), (1, "stores_per_chunk"), (2, "stores_after_segment")):
+        moved = loads + (nch * rows * 8 if store else 0)
+        mix[key + "_GBps"] = round(rate(lambda nb, st: lib.ppa_probe_spmv_mix(
+            idx_p, val_p, vec_p, out_p, nch, per_wg, rows, st, never, sp, stream), "spmv_mix", moved, 1.0,
+            store), 1)
+    mix["shape"] = ("256 workgroups of 1024 threads, 51 chunks each of 4096 nonzeros (two 8-byte index and "
+                    "two 16-byte value loads per thread) and 152 rows (one 8-byte vector load per thread, "
+                    "one 8-byte store per row), three chunks ahead in registers")
+    out["1GiB"]["sliding_window_streams"] = mix
     out["note"] = ("256-thread workgroups, eight loads in flight per thread, best of grid-stride and "
                    "contiguous-range layouts at 256-16384 workgroups; one_range_per_cu_GBps: the "
                    "contiguous layout with 256 workgroups, one stream per CU; "
                    "one_range_per_cu_1024_threads_GBps: the same with 1024-thread workgroups, the "
-                   "shape of the sliding-window SpMV; read_plus_write_eighth moves bytes * 1.125 per "
-                   "launch")
+                   "shape of the sliding-window SpMV; read16_nontemporal_streams_per_range: that range "
+                   "split into 1, 2 or 4 streams; sliding_window_streams: the sliding-window SpMV's "
+                   "loads and stores without its arithmetic; read_plus_write_eighth moves bytes * 1.125 "
+                   "per launch")
     del x, y, sink
     torch.cuda.empty_cache()
     return out

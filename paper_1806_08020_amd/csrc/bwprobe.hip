@@ -9,12 +9,17 @@
 // units, eight loads in flight per thread, either as one grid-stride walk or
 // as one contiguous range per workgroup; sizes must be multiples of the unit.
 // Workgroups have 256 threads; the read also comes with 1024 (the shape of
-// the sliding-window SpMV: one 1024-thread workgroup per CU).
+// the sliding-window SpMV: one 1024-thread workgroup per CU), and with one
+// to four streams per workgroup.  A last kernel issues the sliding-window
+// SpMV's memory streams without its arithmetic: its index, value and
+// vector loads per chunk, three chunks ahead, with or without its output
+// stores, to see what those streams alone reach.
 //
 // Built into libppa_bwprobe.so, loaded only by the benchmark.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 namespace {
 
@@ -145,6 +150,118 @@ int launch(K kern, int64_t n, int blocks, hipStream_t s, A... args) {
     return (int)hipGetLastError();
 }
 
+// NS equal streams (stream s: units [s L, (s + 1) L)) read by workgroups of
+// BS threads; workgroup b reads units [b per, (b + 1) per) of every stream,
+// each thread UNROLL / NS units of each stream per step, so that eight loads
+// are in flight per thread whatever NS.
+template <int NS, int BS>
+__global__ __launch_bounds__(BS) void k_read_streams(const u32x4* __restrict__ x, int64_t L, int64_t per,
+                                                     uint32_t never, uint32_t* __restrict__ sink) {
+    constexpr int UPS = UNROLL / NS;
+    const int64_t s0 = (int64_t)blockIdx.x * per;
+    const int64_t end = s0 + per < L ? s0 + per : L;
+    uint32_t acc = 0;
+    int64_t i = s0 + threadIdx.x;
+    for (; i + (UPS - 1) * BS < end; i += UPS * BS) {
+        u32x4 v[NS][UPS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int u = 0; u < UPS; ++u) v[s][u] = __builtin_nontemporal_load(x + s * L + i + u * BS);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int u = 0; u < UPS; ++u) acc ^= fold(v[s][u]);
+    }
+    for (; i < end; i += BS)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc ^= fold(__builtin_nontemporal_load(x + s * L + i));
+    if (acc == never) sink[(int64_t)blockIdx.x * BS + threadIdx.x] = acc;
+}
+
+// The sliding-window SpMV's memory streams without its arithmetic, in its
+// shape: workgroups of MIX_BS threads, each walking chunks [b q, (b + 1) q)
+// of MIX_CH nonzeros.  Per chunk a thread loads the column indices and
+// values of its MIX_CH / MIX_BS nonzeros two per lane (8-byte index loads,
+// 16-byte value loads, non-temporal) and one 8-byte vector entry (the new
+// ring entry), MIX_D chunks ahead in registers, and folds what it loaded
+// into a running XOR.  Chunk c owns output rows [c R, (c + 1) R), R <= MIX_BS;
+// thread t < R gives row c R + t its running XOR.  STORE 0: nothing is
+// stored (the XOR goes to the sink only when it equals `never`); 1: one
+// 8-byte store per row at the end of each chunk, as the kernel does; 2: the
+// rows' values kept in LDS and written after the workgroup's last chunk
+// (q R <= MIX_DEFER_MAX).  Modes 1 and 2 store the same values.
+constexpr int MIX_BS = 1024, MIX_CH = 4096, MIX_D = 3, MIX_DEFER_MAX = 8192;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+struct MixSlot {
+    u32x2 c[MIX_CH / MIX_BS / 2];
+    u32x4 v[MIX_CH / MIX_BS / 2];
+    u32x2 w;
+};
+
+template <class F, int... I>
+__device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll_n(F&& f) {
+    unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int STORE>
+__global__ __launch_bounds__(MIX_BS) void k_spmv_mix(const u32x2* __restrict__ idx, const u32x4* __restrict__ val,
+                                                     const u32x2* __restrict__ vec, u32x2* __restrict__ out,
+                                                     int64_t q, int rows, uint32_t never,
+                                                     uint32_t* __restrict__ sink) {
+    constexpr int NG = MIX_CH / MIX_BS / 2;
+    __shared__ u32x2 keep[STORE == 2 ? MIX_DEFER_MAX : 1];
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * q, c1 = c0 + q;
+    uint32_t acc = 0;
+    auto load = [&](MixSlot& S, int64_t c) {
+        c = c < c1 ? c : c1 - 1;
+        S.w = vec[c * rows + (tid < rows ? tid : rows - 1)];
+        const int64_t b = c * (MIX_CH / 2);       // in pairs of nonzeros
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            S.c[k] = __builtin_nontemporal_load(idx + b + tid + k * MIX_BS);
+            S.v[k] = __builtin_nontemporal_load(val + b + tid + k * MIX_BS);
+        }
+    };
+    auto use = [&](const MixSlot& S, int64_t c) {
+#pragma unroll
+        for (int k = 0; k < NG; ++k) acc ^= S.c[k].x ^ S.c[k].y ^ fold(S.v[k]);
+        acc ^= S.w.x ^ S.w.y;
+        if constexpr (STORE != 0) {
+            if (tid < rows) {
+                const u32x2 o = {acc, ~acc};
+                if constexpr (STORE == 1)
+                    out[c * rows + tid] = o;
+                else
+                    keep[(c - c0) * rows + tid] = o;
+            }
+        }
+    };
+    MixSlot S[MIX_D];
+    unroll_n<MIX_D>([&](auto i) { load(S[decltype(i)::value], c0 + decltype(i)::value); });
+    for (int64_t c = c0; c < c1; c += MIX_D) {
+        unroll_n<MIX_D>([&](auto i) {
+            constexpr int j = decltype(i)::value;
+            if (c + j < c1) {
+                use(S[j], c + j);
+                load(S[j], c + j + MIX_D);
+            }
+        });
+    }
+    if constexpr (STORE == 2) {
+        // each thread wrote only its own entries of keep: no barrier needed
+        for (int64_t c = c0; c < c1; ++c)
+            if (tid < rows) out[c * rows + tid] = keep[(c - c0) * rows + tid];
+    }
+    if (acc == never) sink[(int64_t)blockIdx.x * MIX_BS + tid] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -201,6 +318,61 @@ int ppa_probe_read_write8(const void* x, void* y, int64_t bytes, int contiguous,
     hipStream_t s = (hipStream_t)stream;
     return contiguous ? launch(k_read_write8<true>, n, blocks, s, (const u32x4*)x, (u32x4*)y)
                       : launch(k_read_write8<false>, n, blocks, s, (const u32x4*)x, (u32x4*)y);
+}
+
+// Reads `bytes` bytes at x as `streams` equal streams (1, 2 or 4; bytes a
+// multiple of 16 * streams) with workgroups of `threads` threads (256 or
+// 1024), each workgroup one contiguous range of every stream, non-temporal
+// 16-byte loads.  blocks, sink and never as for ppa_probe_read_wg.  Returns
+// 0, -1 for arguments that do not fit, or the HIP error of the launch.
+int ppa_probe_read_streams(const void* x, int64_t bytes, int streams, int threads, uint32_t never,
+                           uint32_t* sink, int blocks, void* stream) {
+    if (bytes < 0 || (streams != 1 && streams != 2 && streams != 4) || bytes % (16 * streams) != 0)
+        return -1;
+    if (threads != 256 && threads != 1024) return -1;
+    const int64_t L = bytes / 16 / streams;
+    if (L == 0) return 0;
+    const int g = grid_for(L, blocks, threads);
+    const int64_t per = (L + g - 1) / g;
+    hipStream_t s = (hipStream_t)stream;
+    const u32x4* p = (const u32x4*)x;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(g), dim3(threads), 0, s, p, L, per, never, sink);
+    };
+    if (threads == 256)
+        streams == 1 ? go(k_read_streams<1, 256>) : streams == 2 ? go(k_read_streams<2, 256>) : go(k_read_streams<4, 256>);
+    else
+        streams == 1 ? go(k_read_streams<1, 1024>) : streams == 2 ? go(k_read_streams<2, 1024>) : go(k_read_streams<4, 1024>);
+    return (int)hipGetLastError();
+}
+
+// The sliding-window SpMV's memory streams (k_spmv_mix above): `chunks`
+// chunks of 4096 nonzeros, `chunks_per_group` per 1024-thread workgroup
+// (chunks a multiple of it), `rows` output rows per chunk (1..1024).  idx:
+// 4 * 4096 * chunks bytes (column indices), val: 8 * 4096 * chunks bytes
+// (values), vec and out: 8 * rows * chunks bytes each; all device pointers,
+// 16-byte aligned.  store: 0 none, 1 per chunk, 2 after each workgroup's
+// last chunk (chunks_per_group * rows <= 8192).  sink: 1024 uint32 per
+// workgroup, written where a thread's XOR equals `never`.  Returns 0, -1 for
+// arguments that do not fit, or the HIP error of the launch.
+int ppa_probe_spmv_mix(const void* idx, const void* val, const void* vec, void* out, int64_t chunks,
+                       int64_t chunks_per_group, int rows, int store, uint32_t never, uint32_t* sink,
+                       void* stream) {
+    if (chunks <= 0 || chunks_per_group <= 0 || chunks % chunks_per_group != 0) return -1;
+    if (rows < 1 || rows > MIX_BS || store < 0 || store > 2) return -1;
+    if (store == 2 && chunks_per_group * rows > MIX_DEFER_MAX) return -1;
+    for (const void* ptr : {idx, val, vec, (const void*)out})
+        if (reinterpret_cast<uintptr_t>(ptr) % 16 != 0) return -1;
+    const int64_t groups = chunks / chunks_per_group;
+    if (groups > 65535) return -1;
+    hipStream_t s = (hipStream_t)stream;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(MIX_BS), 0, s, (const u32x2*)idx,
+                           (const u32x4*)val, (const u32x2*)vec, (u32x2*)out, chunks_per_group, rows,
+                           never, sink);
+    };
+    store == 0 ? go(k_spmv_mix<0>) : store == 1 ? go(k_spmv_mix<1>) : go(k_spmv_mix<2>);
+    return (int)hipGetLastError();
 }
 
 }  // extern "C"

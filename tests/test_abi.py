@@ -42,7 +42,8 @@ def test_bandwidth_probe_library_exports():
         pytest.fail("libppa_bwprobe.so is not built (run python -m paper_1806_08020_amd.build)")
     import torch  # noqa: F401
     lib = ctypes.CDLL(path)
-    for name in ("ppa_probe_read", "ppa_probe_read_wg", "ppa_probe_copy", "ppa_probe_read_write8"):
+    for name in ("ppa_probe_read", "ppa_probe_read_wg", "ppa_probe_read_streams", "ppa_probe_copy",
+                 "ppa_probe_read_write8", "ppa_probe_spmv_mix"):
         assert hasattr(lib, name), name
 
 

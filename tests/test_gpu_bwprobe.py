@@ -23,6 +23,8 @@ def probe():
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.ppa_probe_read.argtypes = [vp, i64, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
     lib.ppa_probe_read_wg.argtypes = [vp, i64, ci, ci, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_read_streams.argtypes = [vp, i64, ci, ci, ctypes.c_uint32, vp, ci, vp]
+    lib.ppa_probe_spmv_mix.argtypes = [vp, vp, vp, vp, i64, i64, ci, ci, ctypes.c_uint32, vp, vp]
     lib.ppa_probe_copy.argtypes = [vp, vp, i64, ci, ci, vp]
     lib.ppa_probe_read_write8.argtypes = [vp, vp, i64, ci, ci, vp]
     return lib
@@ -108,3 +110,60 @@ def test_read_workgroup_size_refusals(probe):
     sink = torch.zeros(4096 * 1024, dtype=torch.int32, device="cuda")
     for threads in (0, 64, 512, 2048):
         assert probe.ppa_probe_read_wg(x.data_ptr(), 4 << 10, 16, 0, 1, threads, 0, sink.data_ptr(), 0, s) == -1
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("streams", [1, 2, 4])
+def test_read_streams_visits_every_unit_once(probe, streams, threads):
+    """As for the single-stream read: one marked 16-byte unit, in the first,
+    a middle or the last stream, is read by exactly one thread, once."""
+    s = torch.cuda.current_stream().cuda_stream
+    for per_stream, blocks in ((1, 0), (1000 + 3, 7), (1 << 15, 256)):
+        units = per_stream * streams
+        x = torch.zeros(units * 4, dtype=torch.int32, device="cuda")
+        for mark in sorted({0, units // 2, units - 1}):
+            x.zero_()
+            x[4 * mark + 1] = 0x2468ACE
+            grid = blocks if blocks > 0 else 4096
+            sink = torch.full((grid * threads,), -1, dtype=torch.int32, device="cuda")
+            assert probe.ppa_probe_read_streams(x.data_ptr(), 16 * units, streams, threads, 0,
+                                                sink.data_ptr(), blocks, s) == 0
+            torch.cuda.synchronize()
+            launched = min(grid, -(-per_stream // threads))
+            assert int((sink[:launched * threads] == -1).sum()) == 1, (per_stream, blocks, mark)
+    sink = torch.zeros(4096 * 1024, dtype=torch.int32, device="cuda")
+    assert probe.ppa_probe_read_streams(x.data_ptr(), 16 * streams + 16, streams, threads, 0, sink.data_ptr(),
+                                        0, s) == (-1 if streams > 1 else 0)
+    assert probe.ppa_probe_read_streams(x.data_ptr(), 64, 3, threads, 0, sink.data_ptr(), 0, s) == -1
+    assert probe.ppa_probe_read_streams(x.data_ptr(), 64, streams, 512, 0, sink.data_ptr(), 0, s) == -1
+    torch.cuda.synchronize()
+
+
+def test_spmv_mix_stores_every_row_once_per_mode(probe):
+    """The sliding-window stream probe: storing per chunk and storing after
+    each workgroup's last chunk write the same value to every row, and the
+    load-only mode writes none; arguments that do not fit are refused."""
+    s = torch.cuda.current_stream().cuda_stream
+    chunks, per, rows = 12, 3, 150
+    nnz = chunks * 4096
+    idx = rand_words(nnz, 11)
+    val = rand_words(2 * nnz, 12)
+    vec = rand_words(2 * chunks * rows, 13)
+    sink = torch.zeros((chunks // per) * 1024, dtype=torch.int32, device="cuda")
+    outs = {}
+    for store in (0, 1, 2):
+        out = torch.full((2 * chunks * rows,), -5, dtype=torch.int32, device="cuda")
+        assert probe.ppa_probe_spmv_mix(idx.data_ptr(), val.data_ptr(), vec.data_ptr(), out.data_ptr(), chunks,
+                                        per, rows, store, 0x9E3779B9, sink.data_ptr(), s) == 0
+        torch.cuda.synchronize()
+        outs[store] = out
+    assert torch.all(outs[0] == -5)
+    assert torch.equal(outs[1], outs[2])
+    pairs = outs[1].view(-1, 2)
+    assert torch.all(pairs[:, 1] == ~pairs[:, 0])          # every row written: (acc, ~acc)
+    op = outs[0].data_ptr()
+    args = lambda **k: dict(dict(chunks=chunks, per=per, rows=rows, store=1, out=op), **k)
+    for bad in (args(rows=0), args(rows=1025), args(chunks=13), args(store=3), args(per=60, rows=150, chunks=60, store=2),
+                args(out=op + 8)):
+        assert probe.ppa_probe_spmv_mix(idx.data_ptr(), val.data_ptr(), vec.data_ptr(), bad["out"], bad["chunks"],
+                                        bad["per"], bad["rows"], bad["store"], 0, sink.data_ptr(), s) == -1
