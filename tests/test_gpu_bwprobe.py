@@ -150,11 +150,14 @@ def test_spmv_mix_stores_every_row_once_per_mode(probe):
     val = rand_words(2 * nnz, 12)
     vec = rand_words(2 * chunks * rows, 13)
     sink = torch.zeros((chunks // per) * 1024, dtype=torch.int32, device="cuda")
+    def mix(out_ptr, chunks, per, rows, store):
+        return probe.ppa_probe_spmv_mix(idx.data_ptr(), val.data_ptr(), vec.data_ptr(), out_ptr, chunks, per,
+                                        rows, store, 0x9E3779B9, sink.data_ptr(), s)
+
     outs = {}
     for store in (0, 1, 2):
         out = torch.full((2 * chunks * rows,), -5, dtype=torch.int32, device="cuda")
-        assert probe.ppa_probe_spmv_mix(idx.data_ptr(), val.data_ptr(), vec.data_ptr(), out.data_ptr(), chunks,
-                                        per, rows, store, 0x9E3779B9, sink.data_ptr(), s) == 0
+        assert mix(out.data_ptr(), chunks, per, rows, store) == 0
         torch.cuda.synchronize()
         outs[store] = out
     assert torch.all(outs[0] == -5)
@@ -162,8 +165,7 @@ def test_spmv_mix_stores_every_row_once_per_mode(probe):
     pairs = outs[1].view(-1, 2)
     assert torch.all(pairs[:, 1] == ~pairs[:, 0])          # every row written: (acc, ~acc)
     op = outs[0].data_ptr()
-    args = lambda **k: dict(dict(chunks=chunks, per=per, rows=rows, store=1, out=op), **k)
-    for bad in (args(rows=0), args(rows=1025), args(chunks=13), args(store=3), args(per=60, rows=150, chunks=60, store=2),
-                args(out=op + 8)):
-        assert probe.ppa_probe_spmv_mix(idx.data_ptr(), val.data_ptr(), vec.data_ptr(), bad["out"], bad["chunks"],
-                                        bad["per"], bad["rows"], bad["store"], 0, sink.data_ptr(), s) == -1
+    for bad in ((op, chunks, per, 0, 1), (op, chunks, per, 1025, 1), (op, 13, per, rows, 1),
+                (op, chunks, per, rows, 3), (op, 60, 60, 150, 2),      # 60 x 150 rows kept: too many
+                (op + 8, chunks, per, rows, 1)):                      # output not 16-byte aligned
+        assert mix(*bad) == -1
