@@ -102,6 +102,9 @@ const char* ppa_last_error(void);
 #define PPA_MATRIX_RUNS_FORCE 32    /* build the column runs of the plain kernel's
                                        large blocks and use them (both value
                                        types), see ppa_matrix_spmv_runs          */
+#define PPA_MATRIX_TWO_STEP 64      /* build the records for two factors of pi per
+                                       pass where the bandwidth allows it, and
+                                       use them, see ppa_matrix_two_step         */
 int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_d,
                       const double* val64_d, const float* val32_d, int flags,
                       void* stream, ppa_matrix** out);
@@ -166,6 +169,28 @@ int ppa_matrix_set_spmv_blocks(ppa_matrix* A, int precision, int nnz_per_block);
  * have runs that fit the LDS budget of that value type. */
 int ppa_matrix_spmv_runs(const ppa_matrix* A, int precision, int* on, int64_t* blocks_with_runs);
 int ppa_matrix_set_spmv_runs(ppa_matrix* A, int precision, int on);
+
+/* Two factors of pi per pass (a matrix-powers form of eq. (2.1), section 9
+ * names communication-avoiding variants): for a matrix whose entries all
+ * lie within h of the diagonal, one block per CU owns a range of output
+ * rows, stages the gathered vector on that range widened by 2h in LDS,
+ * computes the first of two consecutive factors on the range widened by h
+ * into LDS and the second on its own rows from there.  The polynomial
+ * application (ppa_poly_apply, and the Arnoldi cycles of ppa_eigs) then
+ * takes two real roots in a row, or a conjugate pair, in one launch, except
+ * for the last factor; every result is bitwise that of the single passes.
+ * The matrix is read once per two factors plus the 2h halo rows per block
+ * (and again from the L2 for the block's own rows), and the intermediate
+ * vector never reaches memory.  The records are built at creation by
+ * PPA_MATRIX_TWO_STEP when no row has more than 2048 nonzeros and a
+ * block's ranges fit its LDS (FP64: (2R + 6h + 4096) * 8 bytes <= 160 KB,
+ * R = n / CUs; FP32 half that).  *on receives 1 when the form is in use for
+ * `precision`, *bandwidth the h found (-1 when no records were built; both
+ * may be NULL).  The setter turns it on (1) or off (0); PPA_ERR_INVALID when
+ * it does not fit that value type.  It must not race with launches that
+ * use A. */
+int ppa_matrix_two_step(const ppa_matrix* A, int precision, int* on, int* bandwidth);
+int ppa_matrix_set_two_step(ppa_matrix* A, int precision, int on);
 
 /* ------------------------------------------------------------------------
  * Polynomial pi in factored form, eq. (2.1): pi(z) = prod_i (1 - z/theta_i),

@@ -89,6 +89,7 @@ int ppa_matrix_create(int64_t n, const int32_t* rowptr_d, const int32_t* colind_
                               : (flags & PPA_MATRIX_RUNS_FORCE)   ? 3
                                                                   : 0;
             matrix_tune(*A, wmode, (flags & PPA_MATRIX_NO_TUNE) == 0, s);
+            if (flags & PPA_MATRIX_TWO_STEP) build_two_step(*A, s);
             A->rp_host.clear();
             A->rp_host.shrink_to_fit();
         } catch (...) {
@@ -191,6 +192,31 @@ int ppa_matrix_spmv_runs(const ppa_matrix* h, int precision, int* on, int64_t* b
         const bool f64 = precision == PPA_F64;
         *on = (A->runs.rec && (f64 ? A->runs.on64 : A->runs.on32)) ? 1 : 0;
         if (blocks_with_runs) *blocks_with_runs = A->runs.rec ? (f64 ? A->runs.nwin64 : A->runs.nwin32) : 0;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_two_step(const ppa_matrix* h, int precision, int* on, int* bandwidth) {
+    return guarded([&] {
+        PPA_REQUIRE(h, "matrix is required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        const Matrix* A = reinterpret_cast<const Matrix*>(h);
+        if (on) *on = two_step_on(*A, precision == PPA_F64 ? VecT::F64 : VecT::F32) ? 1 : 0;
+        if (bandwidth) *bandwidth = A->two.blk ? A->two.h : -1;
+        return PPA_OK;
+    });
+}
+
+int ppa_matrix_set_two_step(ppa_matrix* h, int precision, int on) {
+    return guarded([&] {
+        PPA_REQUIRE(h, "matrix is required");
+        PPA_REQUIRE(precision == PPA_F64 || precision == PPA_F32, "precision must be PPA_F64 or PPA_F32");
+        PPA_REQUIRE(on == 0 || on == 1, "on must be 0 or 1");
+        Matrix* A = reinterpret_cast<Matrix*>(h);
+        const bool f64 = precision == PPA_F64;
+        PPA_REQUIRE(on == 0 || (A->two.blk && (f64 ? A->two.ok64 : A->two.ok32)),
+                    "two factors per pass do not fit this matrix and value type");
+        (f64 ? A->two.on64 : A->two.on32) = on == 1;
         return PPA_OK;
     });
 }

@@ -124,6 +124,19 @@ struct Chain {
         else
             bytes += launch_fused_spmv(A, ct, out_t, alpha, x, beta, u, gamma, z, delta, z2, out, s);
     }
+    // two consecutive factor passes as one launch (launch_two_step):
+    // s = a1 u + b1 A u, out = a2 x2 + b2 A s (+ g2 s with zs), x2 = s or u
+    void pass_two(double a1, double b1, double a2, double b2, double g2, bool zs, bool x2s,
+                  const void* u, void* out) {
+        if (dry) {
+            static char tag_s;
+            const void* sp = &tag_s;
+            bytes += fused_spmv_bytes(A, ct, ct, u, u, nullptr, nullptr) +
+                     fused_spmv_bytes(A, ct, ct, x2s ? sp : u, sp, zs ? sp : nullptr, nullptr);
+        } else {
+            bytes += launch_two_step(A, ct, a1, b1, a2, b2, g2, zs, x2s, u, out, s);
+        }
+    }
     void axpy3(double a, const void* x, double b, const void* y, double c, const void* z, void* out,
                VecT out_t) {
         const size_t sin = ct == VecT::F64 ? 8 : 4, sout = out_t == VecT::F64 ? 8 : 4;
@@ -153,11 +166,32 @@ void pi_chain(Chain& ch, const std::vector<cplx>& roots, const void* u0, double 
     //   real:  w - (A - sigma) w / theta = (1 + sigma/theta) w - A w / theta
     //   pair:  s = (2a + sigma) w - A w,  w - (A - sigma) s / q = w - A s / q + (sigma/q) s
     const double sg = ch.sigma;
+    // two factors per launch where the matrix has the records for it: two
+    // real roots in a row or a conjugate pair, neither the chain's last
+    // factor (that one carries the scaling and the epilogue terms)
+    const bool two = two_step_on(ch.A, ch.ct);
     size_t i = 0;
     while (i < nr) {
         const cplx t = roots[i];
         const bool pair = t.imag() != 0.0;
         const bool last = (i + (pair ? 2 : 1)) >= nr;
+        if (two && !pair && i + 2 < nr && roots[i + 1].imag() == 0.0) {
+            const double ib = -1.0 / t.real(), ib2 = -1.0 / roots[i + 1].real();
+            void* nx = pick(cur, nullptr);
+            ch.pass_two(1.0 - sg * ib, ib, 1.0 - sg * ib2, ib2, 0.0, false, true, cur, nx);
+            cur = nx;
+            i += 2;
+            continue;
+        }
+        if (two && pair && !last) {
+            const double q = t.real() * t.real() + t.imag() * t.imag();
+            const double ss = sg / q;
+            void* nx = pick(cur, nullptr);
+            ch.pass_two(2.0 * t.real() + sg, -1.0, 1.0, -1.0 / q, ss, ss != 0.0, false, cur, nx);
+            cur = nx;
+            i += 2;
+            continue;
+        }
         if (!pair) {
             const double ib = -1.0 / t.real();
             const double sx = 1.0 - sg * ib;

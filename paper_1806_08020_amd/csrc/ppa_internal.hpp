@@ -127,6 +127,31 @@ constexpr int SPMV_RPERCU_F32 = PPA_SPMV_RPERCU_F32;  // blocks (segments) per C
 constexpr int SPMV_RING_NEW = PPA_SPMV_RING_NEW;      // new ring columns per thread and chunk
 constexpr int SPMV_RING_D = PPA_SPMV_RING_D;          // chunks held in registers
 
+// Two factors of the polynomial per pass, for matrices of small bandwidth
+// h (every entry has |column - row| <= h).  Block b (SPMV_TWO_BS threads,
+// one per CU) owns output rows [r0, r1); it stages u on [w0, w1) =
+// [r0 - 2h, r1 + 2h) in LDS, computes the first factor on rows [e0, e1) =
+// [r0 - h, r1 + h) into LDS and the second factor on its own rows from
+// there (all ranges clipped to [0, n)).  Per block three records
+// {r0, r1, e0, e1}, {w0, w1, c0, c1}, {c2, 0, 0, 0}: sub-chunks [c0, c1)
+// cover rows [e0, e1) and [c1, c2) rows [r0, r1), each sub-chunk
+// {row begin, row end, nonzero begin, nonzero end} of whole rows with at
+// most SPMV_TWO_CH nonzeros.
+#ifndef PPA_SPMV_TWO_CH
+#define PPA_SPMV_TWO_CH 4096
+#endif
+constexpr int SPMV_TWO_BS = 1024;
+constexpr int SPMV_TWO_CH = PPA_SPMV_TWO_CH;
+
+struct TwoStep {
+    bool on64 = false, on32 = false;   // in use for this value type
+    bool ok64 = false, ok32 = false;   // fits the LDS for this value type
+    int4* blk = nullptr;               // device, three records per block
+    int4* sub = nullptr;               // device, sub-chunk records
+    int64_t nblk = 0, nsub = 0;
+    int h = 0, wmax = 0, emax = 0;
+};
+
 struct Ring {
     bool on = false;
     int4* rm = nullptr;              // device, per chunk {r0, r1, p0, p1}, {lo, hi, 0, 0}
@@ -201,6 +226,7 @@ struct Matrix {
     Window win64, win32;
     Ring ring64, ring32;
     Runs runs;
+    TwoStep two;
     std::vector<int32_t> rp_host;    // host copy of rowptr (setup only)
 };
 
@@ -259,6 +285,20 @@ void launch_spmm_cols(const Matrix& A, const double* Y, int64_t ld, int ncols, d
 size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const void* x,
                        double beta, const void* u, double gamma, const void* z, double delta,
                        const void* z2, void* o, hipStream_t s);
+// Two consecutive factor passes of a chain in one launch (TwoStep): with s
+// the first pass's output,
+//   s   = a1 u + b1 A u
+//   out = a2 x2 + b2 A s + g2 s,   x2 = s (x2s) or u
+// where the g2 term is present only with zs.  Each value is bitwise the one
+// the two single passes give (same products, same row sums).  Needs
+// two_step_on(A, t); u and out in the value type t.  Returns the two
+// passes' algorithmic bytes.
+bool two_step_on(const Matrix& A, VecT t);
+size_t launch_two_step(const Matrix& A, VecT t, double a1, double b1, double a2, double b2, double g2,
+                       bool zs, bool x2s, const void* u, void* out, hipStream_t s);
+// Records for two factors per pass when the bandwidth lets a block's LDS
+// hold its ranges; call during creation (needs rp_host).
+void build_two_step(Matrix& A, hipStream_t s);
 void matrix_setup(Matrix& A, hipStream_t s);   // validate, norm, partition
 // Choose between the plain and the windowed SpMV for each available value
 // type: mode 0 times both on a scratch vector (large matrices only), mode 1

@@ -984,6 +984,193 @@ size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const
     return bytes;
 }
 
+// ---------------------------------------------------------------- two factors per pass
+// Two consecutive factors of eq. (2.1) in one launch for matrices of small
+// bandwidth (the records are described with TwoStep).  The block stages u on
+// [w0, w1) in LDS, computes s = a1 u + b1 A u on rows [e0, e1) sub-chunk by
+// sub-chunk into LDS (products into an LDS buffer, then every row summed by
+// row_out, exactly as the single pass sums it), then out = a2 x2 + b2 A s
+// (+ g2 s) on its own rows [r0, r1), gathering s from LDS.  The matrix rows
+// of [r0, r1) are read twice, the second time right after the first from
+// the L2; u is read once with the halo and s never leaves the CU.
+template <typename VT, bool X2S>
+__global__ __launch_bounds__(SPMV_TWO_BS) void k_spmv_two(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const VT* __restrict__ val, const int4* __restrict__ blk, const int4* __restrict__ sub,
+    int wmax, int emax, const VT* __restrict__ u, VT* __restrict__ out, VT a1, VT b1, VT a2, VT b2,
+    VT g2, int zs) {
+    constexpr int BS = SPMV_TWO_BS, CH = SPMV_TWO_CH, PER = CH / BS;
+    static_assert(CH % BS == 0, "a sub-chunk is whole rounds of the block");
+    extern __shared__ __align__(16) unsigned char smem[];
+    VT* uw = reinterpret_cast<VT*>(smem);
+    VT* sw = uw + wmax;
+    VT* prod = sw + emax;
+    const int tid = threadIdx.x;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int4 m0 = blk[3 * b], m1 = blk[3 * b + 1], m2 = blk[3 * b + 2];
+    const int e0 = m0.z, w0 = m1.x, nw = m1.y - m1.x;
+    // u on [w0, w1), eight loads per thread in flight before their LDS writes
+    constexpr int WU = 8;
+    for (int i0 = 0; i0 < nw; i0 += WU * BS) {
+        VT t[WU];
+#pragma unroll
+        for (int j = 0; j < WU; ++j) t[j] = u[w0 + min(i0 + tid + j * BS, nw - 1)];
+#pragma unroll
+        for (int j = 0; j < WU; ++j)
+            if (i0 + tid + j * BS < nw) uw[i0 + tid + j * BS] = t[j];
+    }
+    __syncthreads();
+    // first factor: rows [e0, e1), gathered from uw, results into sw
+    for (int c = m1.z; c < m1.w; ++c) {
+        const int4 q4 = sub[c];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = q4.z + tid + k * BS;
+            if (e < q4.w) prod[tid + k * BS] = val[e] * uw[colind[e] - w0];
+        }
+        __syncthreads();
+        for (int r = q4.x + tid; r < q4.y; r += BS) {
+            RowPre<VT> q;
+            q.a = rowptr[r];
+            q.e = rowptr[r + 1];
+            q.x = uw[r - w0];
+            q.z = (VT)0;
+            q.z2 = (VT)0;
+            row_out<CP_KEEP>(q, prod, q4.z, r - e0, sw, a1, b1, (VT)0, (VT)0);
+        }
+        __syncthreads();
+    }
+    // second factor: rows [r0, r1), gathered from sw, results to memory
+    for (int c = m1.w; c < m2.x; ++c) {
+        const int4 q4 = sub[c];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = q4.z + tid + k * BS;
+            if (e < q4.w) prod[tid + k * BS] = val[e] * sw[colind[e] - e0];
+        }
+        __syncthreads();
+        for (int r = q4.x + tid; r < q4.y; r += BS) {
+            RowPre<VT> q;
+            q.a = rowptr[r];
+            q.e = rowptr[r + 1];
+            q.x = X2S ? sw[r - e0] : uw[r - w0];
+            q.z = zs ? sw[r - e0] : (VT)0;
+            q.z2 = (VT)0;
+            row_out<CP_KEEP>(q, prod, q4.z, r, out, a2, b2, g2, (VT)0);
+        }
+        __syncthreads();
+    }
+}
+
+static size_t two_step_lds(const TwoStep& T, size_t vbytes) {
+    return (size_t)(T.wmax + T.emax + SPMV_TWO_CH) * vbytes;
+}
+
+bool two_step_on(const Matrix& A, VecT t) {
+    return A.two.blk != nullptr && (t == VecT::F64 ? A.two.on64 : (A.two.on32 && A.v32 != nullptr));
+}
+
+size_t launch_two_step(const Matrix& A, VecT t, double a1, double b1, double a2, double b2, double g2,
+                       bool zs, bool x2s, const void* u, void* o, hipStream_t s) {
+    PPA_REQUIRE(two_step_on(A, t), "two factors per pass are not set up for this value type");
+    PPA_REQUIRE(u != nullptr && o != nullptr && o != u, "two-step pass: u and a separate out are required");
+    const TwoStep& T = A.two;
+    auto go = [&](auto kern, const auto* val, auto* uu, auto* oo, auto tag) {
+        using V = decltype(tag);
+        hipLaunchKernelGGL(kern, dim3((unsigned)T.nblk), dim3(SPMV_TWO_BS), two_step_lds(T, sizeof(V)), s,
+                           A.rowptr, A.colind, val, T.blk, T.sub, T.wmax, T.emax, uu, oo, (V)a1, (V)b1,
+                           (V)a2, (V)b2, (V)g2, zs ? 1 : 0);
+    };
+    if (t == VecT::F64) {
+        const double* uu = (const double*)u;
+        double* oo = (double*)o;
+        x2s ? go(k_spmv_two<double, true>, A.v64, uu, oo, 0.0) : go(k_spmv_two<double, false>, A.v64, uu, oo, 0.0);
+    } else {
+        const float* uu = (const float*)u;
+        float* oo = (float*)o;
+        x2s ? go(k_spmv_two<float, true>, A.v32, uu, oo, 0.0f) : go(k_spmv_two<float, false>, A.v32, uu, oo, 0.0f);
+    }
+    PPA_HIP(hipGetLastError());
+    // the two single passes' bytes: s = a1 u + b1 A u, then out from x2, s (and s again)
+    static char tag_s;
+    const void* sp = &tag_s;
+    return fused_spmv_bytes(A, t, t, u, u, nullptr, nullptr) +
+           fused_spmv_bytes(A, t, t, x2s ? sp : u, sp, zs ? sp : nullptr, nullptr);
+}
+
+void build_two_step(Matrix& A, hipStream_t s) {
+    TwoStep& T = A.two;
+    if (T.blk || A.nnz == 0 || A.rp_host.empty()) return;
+    const std::vector<int32_t>& rp = A.rp_host;
+    std::vector<int32_t> ci(A.nnz);
+    PPA_HIP(hipMemcpyAsync(ci.data(), A.colind, A.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    // bandwidth, and rows short enough that the single pass sums them in
+    // the same order (no row needs a block of its own there)
+    int64_t h = 0;
+    for (int64_t r = 0; r < A.n; ++r) {
+        if (rp[r + 1] - rp[r] > SPMV_CHUNK) return;
+        for (int32_t k = rp[r]; k < rp[r + 1]; ++k) h = std::max<int64_t>(h, std::abs((int64_t)ci[k] - r));
+    }
+    int ncu = 0, maxlds = 0;
+    PPA_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, A.device));
+    PPA_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, A.device));
+    const int64_t nb = std::min<int64_t>(std::max(ncu, 1), A.n);
+    const int64_t R = (A.n + nb - 1) / nb;
+    std::vector<int4> blk, sub;
+    int64_t wmax = 0, emax = 0;
+    auto cut = [&](int64_t ra, int64_t rb) {
+        int64_t r = ra;
+        while (r < rb) {
+            int64_t q = r + 1;
+            while (q < rb && (int64_t)rp[q + 1] - rp[r] <= SPMV_TWO_CH) ++q;
+            sub.push_back(make_int4((int)r, (int)q, rp[r], rp[q]));
+            r = q;
+        }
+    };
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t r0 = b * R, r1 = std::min<int64_t>(A.n, r0 + R);
+        if (r0 >= r1) break;
+        const int64_t e0 = std::max<int64_t>(0, r0 - h), e1 = std::min<int64_t>(A.n, r1 + h);
+        const int64_t w0 = std::max<int64_t>(0, e0 - h), w1 = std::min<int64_t>(A.n, e1 + h);
+        const int c0 = (int)sub.size();
+        cut(e0, e1);
+        const int c1 = (int)sub.size();
+        cut(r0, r1);
+        const int c2 = (int)sub.size();
+        blk.push_back(make_int4((int)r0, (int)r1, (int)e0, (int)e1));
+        blk.push_back(make_int4((int)w0, (int)w1, c0, c1));
+        blk.push_back(make_int4(c2, 0, 0, 0));
+        wmax = std::max(wmax, w1 - w0);
+        emax = std::max(emax, e1 - e0);
+    }
+    T.h = (int)h;
+    T.wmax = (int)wmax;
+    T.emax = (int)emax;
+    auto fits = [&](size_t vb, const void* k1, const void* k2) {
+        const size_t b = two_step_lds(T, vb);
+        if (b > (size_t)maxlds) return false;
+        bool ok = true;
+        for (const void* f : {k1, k2})
+            ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) == hipSuccess;
+        return ok;
+    };
+    T.ok64 = fits(sizeof(double), (const void*)k_spmv_two<double, true>, (const void*)k_spmv_two<double, false>);
+    T.ok32 = A.v32 != nullptr &&
+             fits(sizeof(float), (const void*)k_spmv_two<float, true>, (const void*)k_spmv_two<float, false>);
+    if (!T.ok64 && !T.ok32) return;
+    T.nblk = (int64_t)blk.size() / 3;
+    T.nsub = (int64_t)sub.size();
+    PPA_HIP(hipMalloc(&T.blk, blk.size() * sizeof(int4)));
+    PPA_HIP(hipMalloc(&T.sub, std::max<size_t>(sub.size(), 1) * sizeof(int4)));
+    PPA_HIP(hipMemcpyAsync(T.blk, blk.data(), blk.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    if (!sub.empty())
+        PPA_HIP(hipMemcpyAsync(T.sub, sub.data(), sub.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    PPA_HIP(hipStreamSynchronize(s));
+    T.on64 = T.ok64;
+    T.on32 = T.ok32;
+}
+
 // ---------------------------------------------------------------- setup
 // Per-row structural check (indices in range, strictly increasing) and the
 // absolute row sum; one result per block: bad-row count and max row sum.
@@ -1712,6 +1899,10 @@ void matrix_release(Matrix& A) {
         R->rm = nullptr;
         R->seg = nullptr;
     }
+    if (A.two.blk) (void)hipFree(A.two.blk);
+    if (A.two.sub) (void)hipFree(A.two.sub);
+    A.two.blk = nullptr;
+    A.two.sub = nullptr;
     A.bm = nullptr;
     A.v32_owned = nullptr;
 }

@@ -26,6 +26,7 @@ PPA_F64, PPA_F32, PPA_MIXED = 0, 1, 2
 PPA_MATRIX_F32, PPA_MATRIX_WINDOW_FORCE, PPA_MATRIX_WINDOW_OFF, PPA_MATRIX_RING_FORCE = 1, 2, 4, 8
 PPA_MATRIX_NO_TUNE = 16
 PPA_MATRIX_RUNS_FORCE = 32
+PPA_MATRIX_TWO_STEP = 64
 _PREC = {"f64": PPA_F64, "f32": PPA_F32, "mixed": PPA_MIXED}
 
 vp = C.c_void_p
@@ -83,6 +84,8 @@ def _load():
         "ppa_matrix_set_spmv_blocks": (i, [vp, i, i]),
         "ppa_matrix_spmv_runs": (i, [vp, i, P(i), P(i64)]),
         "ppa_matrix_set_spmv_runs": (i, [vp, i, i]),
+        "ppa_matrix_two_step": (i, [vp, i, P(i), P(i)]),
+        "ppa_matrix_set_two_step": (i, [vp, i, i]),
         "ppa_poly_from_roots": (i, [i, P(d), P(d), i, P(d), P(d), P(vp)]),
         "ppa_poly_destroy": (i, [vp]),
         "ppa_poly_degree": (i, [vp, P(i), P(i)]),
@@ -166,12 +169,15 @@ class Matrix:
     """Device CSR matrix handle.  ``csr`` is a workloads.CSR (host arrays);
     the device copies are owned by this object and borrowed by the handle."""
 
-    def __init__(self, csr, want_f32: bool = False, window: str = "auto", tune: bool = True):
+    def __init__(self, csr, want_f32: bool = False, window: str = "auto", tune: bool = True,
+                 two_step: bool = False):
         """window: "auto" (time the SpMV variants on large matrices),
         "force" (LDS-windowed whenever it fits), "ring" (sliding window
         whenever it fits), "runs" (plain kernel with column runs staged in
         LDS) or "off" (plain kernel only, global gathers).  tune=False skips the
-        timing at creation (size-rule cache policy, large blocks)."""
+        timing at creation (size-rule cache policy, large blocks).  two_step:
+        build (and use) two factors of pi per pass where the bandwidth
+        allows it (ppa_matrix_two_step)."""
         dev = torch.device("cuda")
         self.n = int(csr.n)
         self.rowptr = torch.as_tensor(np.asarray(csr.rowptr, dtype=np.int32)).to(dev)
@@ -186,6 +192,8 @@ class Matrix:
                  "off": PPA_MATRIX_WINDOW_OFF, "runs": PPA_MATRIX_RUNS_FORCE}[window]
         if not tune:
             flags |= PPA_MATRIX_NO_TUNE
+        if two_step:
+            flags |= PPA_MATRIX_TWO_STEP
         _check(_lib.ppa_matrix_create(self.n, _ptr(self.rowptr), _ptr(self.colind), _ptr(self.vals),
                                       _ptr(self.vals32), flags, _stream(), C.byref(h)))
         self.h = h
@@ -240,6 +248,16 @@ class Matrix:
 
     def set_spmv_runs(self, on: bool, precision: str = "f64") -> None:
         _check(_lib.ppa_matrix_set_spmv_runs(self.h, _PREC[precision], int(bool(on))))
+
+    def two_step(self, precision: str = "f64"):
+        """(on, bandwidth): whether pi is applied two factors per pass, and
+        the bandwidth found at creation (-1 when no records were built)."""
+        on, bw = C.c_int(), C.c_int()
+        _check(_lib.ppa_matrix_two_step(self.h, _PREC[precision], C.byref(on), C.byref(bw)))
+        return bool(on.value), bw.value
+
+    def set_two_step(self, on: bool, precision: str = "f64") -> None:
+        _check(_lib.ppa_matrix_set_two_step(self.h, _PREC[precision], int(bool(on))))
 
     def __del__(self):
         h = getattr(self, "h", None)
