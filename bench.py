@@ -547,7 +547,7 @@ def cache_resident_report(name, steps, max_cycles):
     pib = sum(r.spmv_bytes for r in rs)
     ta = sum(r.t_apply_ms for r in rs) / 1e3
     npass = sum(r.spmv_passes for r in rs)
-    return {"workload": cfg["desc"], "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
+    out = {"workload": cfg["desc"], "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
             "pi_bytes_GBps": round(pib / wall / 1e9, 1),
             "kernel_GBps": round(pib / ta / 1e9, 1), "kernel_frac_of_hbm_peak": round(pib / ta / 1e9 / HBM_PEAK_GBS, 4),
             "avg_launch_us": round(ta / npass * 1e6, 3), "bytes_per_launch": round(pib / npass),
@@ -557,6 +557,55 @@ def cache_resident_report(name, steps, max_cycles):
             "cycles": [r.cycles for r in rs],
             "note": "last-level-cache resident: one pass (80-88 MB) fits the 256 MB last-level cache, "
                     "which serves it from one factor to the next; not a measure of HBM bandwidth"}
+    out["two_step"] = two_step_report(csr, cfg, bt, vt, max_cycles)
+    return out
+
+
+def two_step_report(csr, cfg, bt, vt, max_cycles, reps=20):
+    """Two factors of pi per pass (ppa_matrix_two_step) on this workload:
+    pi(A)v and the whole step (build plus solve) with the form on and off,
+    the results compared bit for bit."""
+    import torch
+    from paper_1806_08020_amd import ppa
+    A = ppa.Matrix(csr, two_step=True)
+    on, h = A.two_step("f64")
+    if not on:
+        return {"available": False, "bandwidth": h}
+    P = ppa.Poly.build(A, cfg["d"], bt)
+    ws = ppa.apply_workspace(A, P)
+    res, ms = {}, {}
+    for flag in (True, False):
+        A.set_two_step(flag)
+        y = ppa.apply(A, P, vt, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ppa.apply(A, P, vt, out=y, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[flag] = e0.elapsed_time(e1) / reps
+        res[flag] = y.clone()
+    steps = {}
+    for flag in (True, False):
+        A.set_two_step(flag)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            Pq = ppa.Poly.build(A, cfg["d"], bt)
+            r = ppa.eigs(A, Pq, vt, cfg["m"], cfg["k"], cfg["nev"], rtol=1e-8, max_cycles=max_cycles)
+        torch.cuda.synchronize()
+        steps[flag] = ((time.perf_counter() - t0) / 3 * 1e3, r)
+    return {"available": True, "bandwidth": h,
+            "ms_per_pi_apply": {"two_step": round(ms[True], 4), "single_passes": round(ms[False], 4)},
+            "speedup_pi_apply": round(ms[False] / ms[True], 3),
+            "ms_per_step": {"two_step": round(steps[True][0], 2), "single_passes": round(steps[False][0], 2)},
+            "bitwise_equal": bool(torch.equal(res[True], res[False])) and
+            bool(np.array_equal(steps[True][1].mu, steps[False][1].mu)),
+            "note": "two consecutive factors per launch (real-root pairs and conjugate pairs, all but "
+                    "the last factor); the matrix is read once per two factors plus the 2h halo rows "
+                    "of each block, the intermediate vector stays in LDS; HIP events around 20 "
+                    "applications of the degree-d polynomial on the launch stream"}
 
 
 def harmonic_report():
@@ -699,6 +748,9 @@ def parse_args(argv=None):
     ap.add_argument("--bw-probe", action="store_true",
                     help="only the bandwidth reference kernels (streaming read, copy, read plus an "
                          "eighth written) at 1 GiB and 80 MB; prints its own JSON line")
+    ap.add_argument("--two-step-report", action="store_true",
+                    help="only the two-factors-per-pass comparison on --config (pi(A)v and the step, "
+                         "on and off); prints its own JSON line")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the solve in the other precision (mixed vs FP64)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served mix")
@@ -750,6 +802,12 @@ def main():
     cfg = CONFIGS[args.config]
     csr = make_matrix(cfg)
     b, v0 = W.start_vectors(csr.n, cfg["seed"])
+    if args.two_step_report:
+        bt, vt = torch.as_tensor(b, device="cuda"), torch.as_tensor(v0, device="cuda")
+        d = cfg["d"] if not isinstance(cfg["d"], tuple) else cfg["d"][0]
+        print(json.dumps({"two_step": two_step_report(csr, dict(cfg, d=d), bt, vt, args.max_cycles),
+                          "workload": cfg["desc"]}), flush=True)
+        return
     prec = cfg["precision"] if args.precision == "auto" else args.precision
     A = ppa.Matrix(csr, want_f32=(prec != "f64"),
                    window={"auto": "auto", "plain": "off", "runs": "runs", "window": "force",

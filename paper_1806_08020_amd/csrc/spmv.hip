@@ -1009,6 +1009,32 @@ __global__ __launch_bounds__(SPMV_TWO_BS) void k_spmv_two(
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int4 m0 = blk[3 * b], m1 = blk[3 * b + 1], m2 = blk[3 * b + 2];
     const int e0 = m0.z, w0 = m1.x, nw = m1.y - m1.x;
+    // sub-chunks [c0, c1): first factor on rows [e0, e1), gathered from uw,
+    // results into sw; [c1, c2): second factor on rows [r0, r1), gathered
+    // from sw, results to memory.  A sub-chunk's indices, values and first
+    // row pointers are loaded one sub-chunk ahead (the first with the
+    // staging of u), so that only LDS work waits between two barriers.
+    const int cA = m1.z, cB = m1.w, cC = m2.x;
+    struct Ahead {
+        int col[PER];
+        VT v[PER];
+        int a, e;
+    };
+    auto fetch = [&](int c, Ahead& h) {
+        const int4 f = sub[c];
+        const int last = max(f.w - 1, 0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = min(f.z + tid + k * BS, last);
+            h.col[k] = colind[e];
+            h.v[k] = val[e];
+        }
+        const int r = min(f.x + tid, f.y - 1);
+        h.a = rowptr[r];
+        h.e = rowptr[r + 1];
+    };
+    Ahead cur;
+    if (cA < cC) fetch(cA, cur);
     // u on [w0, w1), eight loads per thread in flight before their LDS writes
     constexpr int WU = 8;
     for (int i0 = 0; i0 < nw; i0 += WU * BS) {
@@ -1020,45 +1046,40 @@ __global__ __launch_bounds__(SPMV_TWO_BS) void k_spmv_two(
             if (i0 + tid + j * BS < nw) uw[i0 + tid + j * BS] = t[j];
     }
     __syncthreads();
-    // first factor: rows [e0, e1), gathered from uw, results into sw
-    for (int c = m1.z; c < m1.w; ++c) {
+    for (int c = cA; c < cC; ++c) {
         const int4 q4 = sub[c];
+        const bool second = c >= cB;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int e = q4.z + tid + k * BS;
-            if (e < q4.w) prod[tid + k * BS] = val[e] * uw[colind[e] - w0];
+            if (e < q4.w)
+                prod[tid + k * BS] = cur.v[k] * (second ? sw[cur.col[k] - e0] : uw[cur.col[k] - w0]);
         }
+        Ahead nxt;
+        if (c + 1 < cC) fetch(c + 1, nxt);
         __syncthreads();
         for (int r = q4.x + tid; r < q4.y; r += BS) {
             RowPre<VT> q;
-            q.a = rowptr[r];
-            q.e = rowptr[r + 1];
-            q.x = uw[r - w0];
-            q.z = (VT)0;
+            if (r == q4.x + tid) {
+                q.a = cur.a;
+                q.e = cur.e;
+            } else {
+                q.a = rowptr[r];
+                q.e = rowptr[r + 1];
+            }
             q.z2 = (VT)0;
-            row_out<CP_KEEP>(q, prod, q4.z, r - e0, sw, a1, b1, (VT)0, (VT)0);
+            if (!second) {
+                q.x = uw[r - w0];
+                q.z = (VT)0;
+                row_out<CP_KEEP>(q, prod, q4.z, r - e0, sw, a1, b1, (VT)0, (VT)0);
+            } else {
+                q.x = X2S ? sw[r - e0] : uw[r - w0];
+                q.z = zs ? sw[r - e0] : (VT)0;
+                row_out<CP_KEEP>(q, prod, q4.z, r, out, a2, b2, g2, (VT)0);
+            }
         }
         __syncthreads();
-    }
-    // second factor: rows [r0, r1), gathered from sw, results to memory
-    for (int c = m1.w; c < m2.x; ++c) {
-        const int4 q4 = sub[c];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = q4.z + tid + k * BS;
-            if (e < q4.w) prod[tid + k * BS] = val[e] * sw[colind[e] - e0];
-        }
-        __syncthreads();
-        for (int r = q4.x + tid; r < q4.y; r += BS) {
-            RowPre<VT> q;
-            q.a = rowptr[r];
-            q.e = rowptr[r + 1];
-            q.x = X2S ? sw[r - e0] : uw[r - w0];
-            q.z = zs ? sw[r - e0] : (VT)0;
-            q.z2 = (VT)0;
-            row_out<CP_KEEP>(q, prod, q4.z, r, out, a2, b2, g2, (VT)0);
-        }
-        __syncthreads();
+        cur = nxt;
     }
 }
 
