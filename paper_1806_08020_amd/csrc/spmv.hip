@@ -1168,12 +1168,14 @@ void build_two_step(Matrix& A, hipStream_t s) {
     T.h = (int)h;
     T.wmax = (int)wmax;
     T.emax = (int)emax;
+    // the kernels' LDS limit is a property of the function, shared by every
+    // matrix: it is raised to the device maximum, and each launch asks for
+    // what its matrix needs
     auto fits = [&](size_t vb, const void* k1, const void* k2) {
-        const size_t b = two_step_lds(T, vb);
-        if (b > (size_t)maxlds) return false;
+        if (two_step_lds(T, vb) > (size_t)maxlds) return false;
         bool ok = true;
         for (const void* f : {k1, k2})
-            ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) == hipSuccess;
+            ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds) == hipSuccess;
         return ok;
     };
     T.ok64 = fits(sizeof(double), (const void*)k_spmv_two<double, true>, (const void*)k_spmv_two<double, false>);

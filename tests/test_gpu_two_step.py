@@ -88,6 +88,24 @@ def test_solve_bitwise_equal(lib, precision):
     assert np.array_equal(r1.mu, r0.mu) and np.array_equal(r1.resid, r0.resid)
 
 
+def test_matrices_of_different_lds_needs_side_by_side(lib):
+    """Two matrices whose ranges need different amounts of LDS, created in
+    either order, both applied afterwards (the kernels' LDS limit is shared
+    by all matrices)."""
+    big = W.random_banded(60_000, 27, 900, seed=8)        # 80 KB of LDS, the small one 49 KB
+    small = W.convdiff_2d(250, 0.5)
+    for order in ((big, small), (small, big)):
+        mats = [lib.Matrix(c, two_step=True) for c in order]
+        for csr, A in zip(order, mats):
+            assert A.two_step()[0]
+            b, v = W.start_vectors(csr.n, 9)
+            P = lib.Poly.build(A, 8, dev(b))
+            y1 = lib.apply(A, P, dev(v))
+            A.set_two_step(False)
+            assert torch.equal(y1, lib.apply(A, P, dev(v)))
+            A.set_two_step(True)
+
+
 def test_refused_where_it_does_not_fit(lib):
     """Bandwidth 5000 at n = 60,000 (235 rows per block): the FP64 ranges do
     not fit 160 KB of LDS, the FP32 ones do; a row longer than 2048 nonzeros
