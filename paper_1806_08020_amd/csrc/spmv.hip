@@ -1505,7 +1505,9 @@ static void build_window(Matrix& A, Window& W, int chunk, size_t vbytes, hipStre
     // products, then the window with room for the 16-byte aligned copy
     const size_t lds = (size_t)chunk * vbytes + (size_t)(smax + 8) * vbytes;
     bool ok = lds <= (size_t)maxlds && lds <= (size_t)SPMV_WIN_LDS_MAX;
-    if (ok) ok = allow_lds(vbytes, lds);
+    // the kernels' LDS limit is a property of the function, shared by every
+    // matrix: raised to the budget, while each launch asks for its own need
+    if (ok) ok = allow_lds(vbytes, std::min((size_t)maxlds, (size_t)SPMV_WIN_LDS_MAX));
     PPA_HIP(hipFree(dblk));
     PPA_HIP(hipFree(dmeta));
     if (!ok) return;

@@ -514,6 +514,24 @@ def test_windowed_spmv_bitwise_equal(lib, name):
     assert np.all(np.abs(yw - ref) <= (nnzr + 4) * EPS64 * scale)
 
 
+def test_windowed_matrices_of_different_spans_side_by_side(lib):
+    """The windowed kernel's LDS need follows the matrix (its widest block's
+    column span); two matrices of different spans, created in either order,
+    both run windowed afterwards and match the CSR product."""
+    wide = W.random_banded(20_000, 27, 2000, seed=3)
+    narrow = W.random_banded(20_000, 27, 100, seed=4)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(20_000)
+    for order in ((wide, narrow), (narrow, wide)):
+        mats = [lib.Matrix(c, window="force") for c in order]
+        for csr, A in zip(order, mats):
+            assert A.windowed("f64")
+            S = csr.to_scipy()
+            y = host(lib.fused_spmv(A, 0.0, None, 1.0, dev(u)))
+            nnzr = int(np.diff(csr.rowptr).max())
+            assert np.all(np.abs(y - S @ u) <= (nnzr + 1) * EPS64 * (abs(S) @ np.abs(u)))
+
+
 def test_windowed_with_long_rows(lib):
     """A 6000-nonzero row fits the windowed blocks (8192 nonzeros, FP64 and
     FP32); the plain kernel reduces rows longer than 2048 nonzeros with a
