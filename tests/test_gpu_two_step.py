@@ -88,6 +88,24 @@ def test_solve_bitwise_equal(lib, precision):
     assert np.array_equal(r1.mu, r0.mu) and np.array_equal(r1.resid, r0.resid)
 
 
+@pytest.mark.parametrize("variant", ["graph", "harmonic", "lowsync"])
+def test_solve_variants_with_the_form(lib, variant):
+    """The solve's variants with two factors per pass: cycles replayed from
+    HIP graphs, the harmonic restart and the delayed Gram-Schmidt each give
+    the pairs of the same solve with the form off, bit for bit."""
+    csr = W.convdiff_2d(180, 0.6)
+    b, v0 = W.start_vectors(csr.n, 10)
+    out = {}
+    for on in (True, False):
+        A = lib.Matrix(csr, two_step=True)
+        A.set_two_step(on)
+        P = lib.Poly.build(A, 12, dev(b))
+        out[on] = lib.eigs(A, P, dev(v0), 30, 15, 8, rtol=1e-8, max_cycles=40, **{variant: True})
+    r1, r0 = out[True], out[False]
+    assert r1.converged and r0.converged and r1.cycles == r0.cycles
+    assert np.array_equal(r1.mu, r0.mu) and np.array_equal(r1.resid, r0.resid)
+
+
 def test_matrices_of_different_lds_needs_side_by_side(lib):
     """Two matrices whose ranges need different amounts of LDS, created in
     either order, both applied afterwards (the kernels' LDS limit is shared
