@@ -179,9 +179,11 @@ int ppa_matrix_set_spmv_runs(ppa_matrix* A, int precision, int on);
  * application (ppa_poly_apply, and the Arnoldi cycles of ppa_eigs) then
  * takes two real roots in a row, or a conjugate pair, in one launch, except
  * for the last factor; every result is bitwise that of the single passes.
- * The matrix is read once per two factors plus the 2h halo rows per block
- * (and again from the L2 for the block's own rows), and the intermediate
- * vector never reaches memory.  The records are built at creation by
+ * The matrix is read on each block's rows widened by h and again on its own
+ * rows, and the intermediate vector never reaches memory; where the form
+ * fits, a CU's row range is so short against 2h that this saves only that
+ * vector's store and reload, and the form can be slower than the single
+ * passes, so it is used only on request.  The records are built at creation by
  * PPA_MATRIX_TWO_STEP when no row has more than 2048 nonzeros and a
  * block's ranges fit its LDS (FP64: (2R + 6h + 4096) * 8 bytes <= 160 KB,
  * R = n / CUs; FP32 half that).  *on receives 1 when the form is in use for

@@ -990,9 +990,9 @@ size_t launch_fused_spmv(const Matrix& A, VecT in, VecT out, double alpha, const
 // [w0, w1) in LDS, computes s = a1 u + b1 A u on rows [e0, e1) sub-chunk by
 // sub-chunk into LDS (products into an LDS buffer, then every row summed by
 // row_out, exactly as the single pass sums it), then out = a2 x2 + b2 A s
-// (+ g2 s) on its own rows [r0, r1), gathering s from LDS.  The matrix rows
-// of [r0, r1) are read twice, the second time right after the first from
-// the L2; u is read once with the halo and s never leaves the CU.
+// (+ g2 s) on its own rows [r0, r1), gathering s from LDS.  The matrix is
+// read on [e0, e1) for the first factor and on [r0, r1) again for the
+// second; u is read once with the halo and s never leaves the CU.
 template <typename VT, bool X2S>
 __global__ __launch_bounds__(SPMV_TWO_BS) void k_spmv_two(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
