@@ -567,25 +567,33 @@ def two_step_report(csr, cfg, bt, vt, max_cycles, reps=20):
     the results compared bit for bit."""
     import torch
     from paper_1806_08020_amd import ppa
-    A = ppa.Matrix(csr, two_step=True)
+    A = ppa.Matrix(csr, want_f32=True, two_step=True)
     on, h = A.two_step("f64")
     if not on:
         return {"available": False, "bandwidth": h}
     P = ppa.Poly.build(A, cfg["d"], bt)
-    ws = ppa.apply_workspace(A, P)
-    res, ms = {}, {}
-    for flag in (True, False):
-        A.set_two_step(flag)
-        y = ppa.apply(A, P, vt, ws=ws)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            ppa.apply(A, P, vt, out=y, ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
-        ms[flag] = e0.elapsed_time(e1) / reps
-        res[flag] = y.clone()
+
+    def timed_apply(prec):
+        v = vt if prec == "f64" else vt.float()
+        ws = ppa.apply_workspace(A, P, prec)
+        res, ms = {}, {}
+        for flag in (True, False):
+            A.set_two_step(flag, prec)
+            y = ppa.apply(A, P, v, precision=prec, ws=ws)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ppa.apply(A, P, v, precision=prec, out=y, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms[flag] = e0.elapsed_time(e1) / reps
+            res[flag] = y.clone()
+        A.set_two_step(True, prec)
+        return res, ms
+
+    res, ms = timed_apply("f64")
+    res32, ms32 = timed_apply("f32") if A.two_step("f32")[0] else ({}, {})
     steps = {}
     for flag in (True, False):
         A.set_two_step(flag)
@@ -596,16 +604,20 @@ def two_step_report(csr, cfg, bt, vt, max_cycles, reps=20):
             r = ppa.eigs(A, Pq, vt, cfg["m"], cfg["k"], cfg["nev"], rtol=1e-8, max_cycles=max_cycles)
         torch.cuda.synchronize()
         steps[flag] = ((time.perf_counter() - t0) / 3 * 1e3, r)
+    f32 = ({"ms_per_pi_apply_f32": {"two_step": round(ms32[True], 4), "single_passes": round(ms32[False], 4)},
+            "speedup_pi_apply_f32": round(ms32[False] / ms32[True], 3),
+            "bitwise_equal_f32": bool(torch.equal(res32[True], res32[False]))} if ms32 else {})
     return {"available": True, "bandwidth": h,
             "ms_per_pi_apply": {"two_step": round(ms[True], 4), "single_passes": round(ms[False], 4)},
-            "speedup_pi_apply": round(ms[False] / ms[True], 3),
+            "speedup_pi_apply": round(ms[False] / ms[True], 3), **f32,
             "ms_per_step": {"two_step": round(steps[True][0], 2), "single_passes": round(steps[False][0], 2)},
             "bitwise_equal": bool(torch.equal(res[True], res[False])) and
             bool(np.array_equal(steps[True][1].mu, steps[False][1].mu)),
             "note": "two consecutive factors per launch (real-root pairs and conjugate pairs, all but "
-                    "the last factor); the matrix is read once per two factors plus the 2h halo rows "
-                    "of each block, the intermediate vector stays in LDS; HIP events around 20 "
-                    "applications of the degree-d polynomial on the launch stream"}
+                    "the last factor); each block reads the matrix on its rows widened by the "
+                    "bandwidth, then on its own rows again, and keeps the intermediate vector in LDS; "
+                    "HIP events around 20 applications of the degree-d polynomial on the launch "
+                    "stream, FP64 and FP32"}
 
 
 def harmonic_report():
